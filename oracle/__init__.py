@@ -1,0 +1,226 @@
+"""FP64 reference checker for the GAVIS visibility-field path.
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports, links or runs
+anything in this package; only the tests, the smoke check and the CPU-baseline
+leg of the benchmark do.  It shares no code with the GPU path: the C source
+`gavis_oracle.c` is compiled on its own with gcc (`build_oracle()`), and this
+module only marshals numpy arrays into it.
+
+Every function cites the part of the paper it follows; see gavis_oracle.c for
+the step-by-step arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gavis_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP over pixels)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build_oracle()
+        L = ctypes.CDLL(LIB)
+        d, i64, i32, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        L.ora_bessel_i.argtypes = [ctypes.c_int, d]
+        L.ora_bessel_i.restype = d
+        L.ora_a_l.argtypes = [ctypes.c_int, d]
+        L.ora_a_l.restype = d
+        L.ora_sh_real.argtypes = [ctypes.c_int, vp, vp]
+        L.ora_sh_real.restype = ctypes.c_int
+        L.ora_num_threads.restype = ctypes.c_int
+        L.ora_project_view.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, d, d, d, vp]
+        L.ora_project_view.restype = ctypes.c_int
+        L.ora_vf_build.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, d, d, d, d, d, i32,
+                                   vp, vp, vp, vp]
+        L.ora_vf_build.restype = ctypes.c_int
+        L.ora_single_view.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, d, i32, vp, vp, vp]
+        L.ora_single_view.restype = ctypes.c_int
+        L.ora_query_visibility.argtypes = [vp, i32, i64, vp]
+        L.ora_query_visibility.restype = d
+        L.ora_vf_query.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
+                                   d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
+        L.ora_vf_query.restype = ctypes.c_int
+        L.ora_argmax.argtypes = [vp, i32]
+        L.ora_argmax.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Params:
+    """Hyperparameters.  kappa = 1 and L = 2 are the paper's defaults; eps_T =
+    1e-4, beta = 0.5, o0 = 0.15 and Q0 = I come with Alg. 2 / Alg. 6.  The rest
+    are readings where the paper is silent: sigma_c = 0.1 for the constant
+    colour covariance Q_c = sigma_c^2 I (so Q0 >= Q_c as the entropy bound
+    requires), znear = 0.2, a 0.3 px^2 low-pass dilation of the 2D covariance
+    and the 3-sigma overlap cut m <= 9."""
+    kappa: float = 1.0
+    eps_T: float = 1e-4
+    znear: float = 0.2
+    lowpass: float = 0.3
+    cut: float = 9.0
+    beta: float = 0.5
+    o0: float = 0.15
+    half_logdet_Q0: float = 0.0
+    sigma_c: float = 0.1
+
+    @property
+    def half_logdet_Qc(self) -> float:
+        return 3.0 * float(np.log(self.sigma_c))   # 1/2 log|sigma_c^2 I_3|
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
+
+
+def bessel_i(l: int, x: float) -> float:
+    """Modified spherical Bessel function i_l(x) (eq. bl)."""
+    return float(lib().ora_bessel_i(int(l), float(x)))
+
+
+def a_l(l: int, kappa: float) -> float:
+    """a_l = 4 pi exp(-kappa) i_l(kappa) (Alg. 3, eq. vis_gamma)."""
+    return float(lib().ora_a_l(int(l), float(kappa)))
+
+
+def sh_real(L: int, d) -> np.ndarray:
+    """Real SH Y_lm(d), l <= L, index l^2 + l + m (Appendix, eq. vis_real)."""
+    d = _f64(d)
+    out = np.zeros((L + 1) ** 2)
+    if lib().ora_sh_real(int(L), _p(d), _p(out)):
+        raise ValueError("bad direction or degree")
+    return out
+
+
+def _cams(cams):
+    R = _f64(cams.R.reshape(-1, 9))
+    t = _f64(cams.t.reshape(-1, 3))
+    K = _f64(cams.K.reshape(-1, 4))
+    wh = np.ascontiguousarray(cams.wh.reshape(-1, 2), dtype=np.int32)
+    return R, t, K, wh
+
+
+def project_view(scene, cams, i, prm: Params = Params()):
+    """EWA projection of every Gaussian into view i: dict of arrays."""
+    R, t, K, wh = _cams(cams)
+    m, s, q = _f64(scene.means), _f64(scene.scales), _f64(scene.quats)
+    out = np.zeros((scene.n, 10))
+    lib().ora_project_view(scene.n, _p(m), _p(s), _p(q), _p(R[i]), _p(t[i]), _p(K[i]), _p(wh[i]),
+                           prm.znear, prm.lowpass, prm.cut, _p(out))
+    keys = ("ok", "z", "ux", "uy", "ca", "cb", "cc", "sxx", "syy", "band")
+    return {k: out[:, j] for j, k in enumerate(keys)}
+
+
+def single_view(scene, cams, i, prm: Params = Params(), gather_mode: int = 0):
+    """Alg. 2 for view i: (v [n], count [n], near-tie allowance on v [n])."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    v = np.zeros(scene.n)
+    c = np.zeros(scene.n, dtype=np.int64)
+    pert = np.zeros(scene.n)
+    rc = lib().ora_single_view(scene.n, _p(m), _p(s), _p(q), _p(o), _p(R[i]), _p(t[i]), _p(K[i]), _p(wh[i]),
+                               prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode, _p(v), _p(c), _p(pert))
+    if rc:
+        raise RuntimeError("oracle single_view failed")
+    return v, c, pert
+
+
+def vf_build(scene, cams, L: int, prm: Params = Params(), gather_mode: int = 0, want_views: bool = False):
+    """Alg. 3 over all views in `cams`.  Returns dict: gamma [n][K], allow
+    [n][K] (first-order near-tie allowance on each coefficient), stats
+    (pairs composited, list entries, Gaussians with an allowance, views) and
+    vview [V][n] if asked."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    Kc = (L + 1) ** 2
+    gamma = np.zeros((scene.n, Kc))
+    allow = np.zeros((scene.n, Kc))
+    stats = np.zeros(4, dtype=np.int64)
+    vview = np.zeros((cams.n, scene.n)) if want_views else None
+    rc = lib().ora_vf_build(scene.n, _p(m), _p(s), _p(q), _p(o), cams.n, _p(R), _p(t), _p(K), _p(wh),
+                            int(L), prm.kappa, prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode,
+                            _p(gamma), _p(vview), _p(allow), _p(stats))
+    if rc:
+        raise RuntimeError("oracle vf_build failed")
+    return {"gamma": gamma, "allow": allow, "stats": stats, "vview": vview}
+
+
+def query_visibility(gamma_g, L: int, n_train: int, d) -> float:
+    """Alg. 4 for one Gaussian (eq. vis_bound with V~ clamped to [0, |P|])."""
+    g = _f64(gamma_g)
+    d = _f64(d)
+    return float(lib().ora_query_visibility(_p(g), int(L), int(n_train), _p(d)))
+
+
+def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), gather_mode: int = 0,
+             want_maps: bool = True, want_vq: bool = False):
+    """Alg. 4 + Alg. 6 for every view in `cams`.  gamma is [n][K] (float64 or
+    float32; promoted).  Returns dict: scores [V], maps (list of [h, w]),
+    flags (list of [h, w] bool), stats (pairs, entries, flagged px, px), vq."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    g = _f64(gamma)
+    npx = int(np.sum(wh[:, 0].astype(np.int64) * wh[:, 1]))
+    maps = np.zeros(npx) if want_maps else None
+    pflags = np.zeros(npx, dtype=np.uint8)
+    scores = np.zeros(cams.n)
+    stats = np.zeros(4, dtype=np.int64)
+    vq = np.zeros((cams.n, scene.n)) if want_vq else None
+    rc = lib().ora_vf_query(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
+                            int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
+                            prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass,
+                            prm.cut, gather_mode, _p(maps), _p(scores), _p(vq), _p(pflags), _p(stats))
+    if rc:
+        raise RuntimeError("oracle vf_query failed")
+    out_maps, out_flags, off = [], [], 0
+    for (w, h) in wh:
+        n = int(w) * int(h)
+        if maps is not None:
+            out_maps.append(maps[off:off + n].reshape(h, w))
+        out_flags.append(pflags[off:off + n].reshape(h, w).astype(bool))
+        off += n
+    return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
+            "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+
+
+def argmax(scores) -> int:
+    """Next-best view (eq. i_gain): lowest index on exact ties."""
+    s = _f64(scores)
+    return int(lib().ora_argmax(_p(s), int(s.shape[0])))
+
+
+def near_tie_set(scores, abs_h_sums, rel=2e-4):
+    """Views whose oracle score lies within tau = rel * max_v sum|H| of the
+    best; a GPU argmax inside this set is accepted."""
+    s = np.asarray(scores, dtype=np.float64)
+    tau = rel * float(np.max(abs_h_sums)) if len(abs_h_sums) else 0.0
+    best = float(np.max(s))
+    return set(int(i) for i in np.nonzero(s >= best - tau)[0])

@@ -1,0 +1,110 @@
+"""Invariants of the FP64 oracle on seeded synthetic scenes (no GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+from paper_2605_30342_amd import scenes
+from paper_2605_30342_amd.scenes import Cameras
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return scenes.workload("tiny", scale=0.5)
+
+
+def test_brute_force_gather_equals_bbox_scatter(tiny):
+    """The per-pixel list is a geometric predicate: gathering by brute force
+    over all Gaussians and by scattering over ellipse bounding boxes must give
+    identical lists, hence identical gamma and maps."""
+    w = tiny
+    cams = w.train.subset([0, 1])
+    b0 = oracle.vf_build(w.scene, cams, 2, gather_mode=0)
+    b1 = oracle.vf_build(w.scene, cams, 2, gather_mode=1)
+    assert np.array_equal(b0["stats"][:2], b1["stats"][:2])
+    np.testing.assert_allclose(b0["gamma"], b1["gamma"], rtol=1e-12, atol=1e-14)
+    q0 = oracle.vf_query(w.scene, b0["gamma"], 2, cams.n, w.cand.subset([0]), gather_mode=0)
+    q1 = oracle.vf_query(w.scene, b0["gamma"], 2, cams.n, w.cand.subset([0]), gather_mode=1)
+    assert np.array_equal(q0["maps"][0], q1["maps"][0])
+
+
+def test_gamma_is_additive_over_view_sets(tiny):
+    """eq. vis_gamma is a sum over training views: gamma(A u B) = gamma(A) + gamma(B)."""
+    w = tiny
+    A, B = w.train.subset([0, 1, 2]), w.train.subset([3])
+    gA = oracle.vf_build(w.scene, A, 2)["gamma"]
+    gB = oracle.vf_build(w.scene, B, 2)["gamma"]
+    gAB = oracle.vf_build(w.scene, Cameras.concat([A, B]), 2)["gamma"]
+    np.testing.assert_allclose(gAB, gA + gB, rtol=1e-12, atol=1e-14)
+
+
+def test_duplicated_views_double_gamma_and_do_not_lower_v(tiny):
+    w = tiny
+    A = w.train.subset([0, 1])
+    g1 = oracle.vf_build(w.scene, A, 2)["gamma"]
+    g2 = oracle.vf_build(w.scene, Cameras.concat([A, A]), 2)["gamma"]
+    np.testing.assert_allclose(g2, 2 * g1, rtol=1e-13, atol=1e-15)
+    cand = w.cand.subset([0])
+    v1 = oracle.vf_query(w.scene, g1, 2, 2, cand, want_maps=False, want_vq=True)["vq"]
+    v2 = oracle.vf_query(w.scene, g2, 2, 4, cand, want_maps=False, want_vq=True)["vq"]
+    assert np.all(v2 >= v1 - 1e-12)
+
+
+def test_permutation_invariance(tiny):
+    """Relabelling the Gaussians permutes gamma and leaves maps unchanged
+    (all depths are distinct in these scenes)."""
+    w = tiny
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(w.scene.n)
+    sp = scenes.subset_scene(w.scene, perm)
+    cams = w.train.subset([0, 1])
+    g = oracle.vf_build(w.scene, cams, 2)["gamma"]
+    gp = oracle.vf_build(sp, cams, 2)["gamma"]
+    np.testing.assert_allclose(gp, g[perm], rtol=1e-12, atol=1e-14)
+    cand = w.cand.subset([1])
+    m = oracle.vf_query(w.scene, g, 2, 2, cand)["maps"][0]
+    mp = oracle.vf_query(sp, g[perm], 2, 2, cand)["maps"][0]
+    np.testing.assert_allclose(mp, m, rtol=1e-12, atol=1e-12)
+
+
+def test_visibility_ranges(tiny):
+    """0 <= v_p <= 1 per view (Alg. 2) and 0 <= V <= 1 after the query (Alg. 4)."""
+    w = tiny
+    b = oracle.vf_build(w.scene, w.train, 2, want_views=True)
+    assert b["vview"].min() >= 0.0 and b["vview"].max() <= 1.0
+    q = oracle.vf_query(w.scene, b["gamma"], 2, w.train.n, w.cand, want_vq=True)
+    assert q["vq"].min() >= 0.0 and q["vq"].max() <= 1.0
+    assert np.all(np.isfinite(q["scores"]))
+
+
+def test_more_visibility_means_less_uncertainty(tiny):
+    """Raising every Gaussian's visibility (more training views of the same
+    poses) cannot raise the prior-weight term; with sigma_c < 1 the score
+    drops (eq. huber: Q_c is smaller than Q0)."""
+    w = tiny
+    g = oracle.vf_build(w.scene, w.train, 2)["gamma"]
+    cand = w.cand.subset([0, 1])
+    s_none = oracle.vf_query(w.scene, g, 2, 0, cand, want_maps=False)["scores"]
+    s_some = oracle.vf_query(w.scene, g, 2, w.train.n, cand, want_maps=False)["scores"]
+    assert np.all(s_some < s_none)
+
+
+def test_virtual_particles_are_invisible(tiny):
+    """The last n_virtual Gaussians always query V = 0 (density control)."""
+    w = tiny
+    g = oracle.vf_build(w.scene, w.train, 2)["gamma"]
+    sc = scenes.Scene(w.scene.means, w.scene.scales, w.scene.quats, w.scene.opacity, n_virtual=50)
+    q = oracle.vf_query(sc, g, 2, w.train.n, w.cand.subset([0]), want_maps=False, want_vq=True)
+    assert np.all(q["vq"][:, -50:] == 0.0)
+    assert np.any(q["vq"][:, :-50] > 0.0)
+
+
+def test_near_tie_bookkeeping_is_small(tiny):
+    """The parity allowance touches few Gaussians and few pixels."""
+    w = tiny
+    b = oracle.vf_build(w.scene, w.train, 2)
+    g, a = b["gamma"], b["allow"]
+    big = a.max(1) > 1e-4 * np.abs(g).max(1)
+    assert big.mean() < 0.05
+    q = oracle.vf_query(w.scene, g, 2, w.train.n, w.cand)
+    assert q["stats"][2] / q["stats"][3] < 0.01
