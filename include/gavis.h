@@ -1,0 +1,200 @@
+/*
+ * gavis.h -- C ABI of the MI355X (gfx950) visibility-field path of GAVIS
+ * ("Uncertainty-driven 3D Gaussian Splatting Active Mapping via Anisotropic
+ * Visibility Field").
+ *
+ * Three calls follow the paper's statement of the problem:
+ *   vf_build         builds the per-Gaussian SH coefficients gamma of the
+ *                    anisotropic visibility field from the training views
+ *                    (Alg. 2 per view, accumulated as in Alg. 3, eq. vis_gamma);
+ *   vf_query_views   queries gamma in each candidate view's direction with the
+ *                    AM-GM bound (Alg. 1 / Alg. 4, eq. vis_bound) and
+ *                    rasterises the per-pixel entropy bound (Alg. 6, eq.
+ *                    alpha_comp, eq. huber) into one score per view (eq. id,
+ *                    with the spatial-correlation correction taken as zero);
+ *   select_next_view picks the candidate with the largest score (eq. i_gain).
+ *
+ * Conventions shared by every call
+ *   - All data pointers named "device" point to GPU memory owned by the
+ *     caller.  The library never frees them and keeps no reference to them
+ *     after the call returns (a captured graph, see gv_uq_params.use_graph,
+ *     keeps the pointers it was captured with until they change).
+ *   - Camera: pinhole, x_cam = R x_world + t (R row major), image x right,
+ *     y down, z forward; pixel (i, j) is sampled at (i + 0.5, j + 0.5).
+ *   - Gaussians: SoA, means [n][3], scales [n][3] (linear, not log),
+ *     quats [n][4] as (w, x, y, z) (normalised inside), opacity [n] in [0, 1].
+ *   - gamma is planar: coefficient k of Gaussian g at gamma[k * n + g],
+ *     k = l^2 + l + m for the real SH basis Y_lm (world frame, theta from +z),
+ *     K = (L + 1)^2 coefficients, L = sh_degree <= GV_MAX_SH_DEGREE.
+ *   - vf_build and vf_query_views only enqueue work on `hip_stream`
+ *     (a hipStream_t, NULL for the default stream); outputs are valid once
+ *     the stream reaches that point.  The *_workspace_size calls and
+ *     select_next_view synchronise the stream.
+ *   - Errors: calls return a negative gv_status and never throw;
+ *     gv_last_error() describes the last failure on the calling thread.
+ *   - Threading: one context per host thread, or serialise calls on it.
+ *     Calls on different streams need different workspaces.
+ */
+#ifndef GAVIS_H
+#define GAVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GV_MAX_SH_DEGREE 3
+#define GV_MAX_IMAGE_SIDE 16384
+
+typedef enum {
+    GV_OK = 0,
+    GV_ERR_INVALID_ARG = -1,    /* bad pointer, size or parameter */
+    GV_ERR_OUT_OF_MEMORY = -2,  /* a small context-owned buffer could not be allocated */
+    GV_ERR_HIP = -3,            /* a HIP runtime call failed */
+    GV_ERR_CAPACITY = -4,       /* the workspace is smaller than the work needs */
+    GV_ERR_UNSUPPORTED = -5     /* valid but not supported (e.g. sh_degree > 3) */
+} gv_status;
+
+typedef enum { GV_F32 = 0, GV_F16 = 1, GV_BF16 = 2 } gv_dtype;
+
+typedef struct gv_context gv_context;
+
+/* One pinhole camera (host memory). */
+typedef struct {
+    float R[9];                 /* world -> camera rotation, row major */
+    float t[3];                 /* world -> camera translation */
+    float fx, fy, cx, cy;       /* focal lengths and principal point, pixels */
+    int32_t width, height;      /* 1 .. GV_MAX_IMAGE_SIDE */
+} gv_camera;
+
+/* A resident 3DGS scene (device memory).  For GV_F16 / GV_BF16 storage the
+ * means are half offsets from per-block FP32 anchors: mean of Gaussian g =
+ * anchors[g / anchor_block] + means[g]; scales, quats and opacity are plain
+ * half values.  The last n_virtual Gaussians are virtual particles of the
+ * visibility-field density control: their queried visibility is 0. */
+typedef struct {
+    int64_t n;
+    int64_t n_virtual;
+    gv_dtype dtype;
+    const void *means;
+    const void *scales;
+    const void *quats;
+    const void *opacity;
+    const float *anchors;       /* [ceil(n / anchor_block)][3], NULL for GV_F32 */
+    int32_t anchor_block;
+} gv_gaussians;
+
+/* Parameters of the visibility-field construction (Alg. 2 / Alg. 3). */
+typedef struct {
+    int32_t sh_degree;          /* L, 0..3; the paper uses 2 */
+    float kappa;                /* vMF concentration; the paper uses 1 */
+    float eps_T;                /* transmittance cutoff, 1e-4 */
+    float znear;                /* Gaussians with camera z <= znear are not in view */
+    float lowpass;              /* dilation added to the 2D covariance diagonal, px^2 */
+    float cut;                  /* overlap predicate: Mahalanobis^2 <= cut (9) */
+    int32_t views_per_pass;     /* training views rasterised per pass, 0 = all */
+    int32_t accumulate;         /* 0: gamma = result, 1: gamma += result */
+} gv_vf_params;
+
+/* Parameters of the uncertainty rasterisation (Alg. 6). */
+typedef struct {
+    float beta;                 /* opacity reliability, 0.5 */
+    float o0;                   /* prior opacity of invisible particles, 0.15 */
+    float half_logdet_Q0;       /* 1/2 log|Q0|, 0 for Q0 = I */
+    float half_logdet_Qc;       /* 1/2 log|Q_c| of the constant colour covariance */
+    float eps_T;                /* transmittance cutoff, 1e-4 */
+    float znear;
+    float lowpass;
+    float cut;
+    int32_t write_maps;         /* 1: also write the per-pixel entropy maps */
+    int32_t use_graph;          /* 1: capture the launch sequence in a hipGraph and
+                                   replay it while shapes and pointers repeat */
+} gv_uq_params;
+
+/* Workspace plan, filled by the *_workspace_size calls.  The caller
+ * allocates `bytes` of device memory and passes both to the compute call.
+ * max_records / max_instances may be raised to leave slack for other
+ * camera sets; `bytes` must then be recomputed with gv_workspace_bytes. */
+typedef struct {
+    size_t bytes;
+    int64_t max_records;        /* (Gaussian, view) pairs kept after culling */
+    int64_t max_instances;      /* (tile, record) pairs after binning */
+    int64_t n;                  /* Gaussians the plan was made for */
+    int32_t n_views;            /* views per pass the plan was made for */
+    int32_t total_tiles;        /* largest per-pass tile count */
+    int64_t total_pixels;       /* largest per-pass pixel count */
+    int32_t kind;               /* 0 build, 1 query */
+    int32_t sh_degree;
+} gv_workspace;
+
+/* Context: small host state, a few bytes of device counters, cached graphs.
+ * `device` is the HIP device ordinal the context works on. */
+gv_status gv_create(int device, gv_context **out);
+void gv_destroy(gv_context *ctx);
+
+/* Message for the last failure on this thread ("" if none).  The pointer is
+ * valid until the next call on the same thread. */
+const char *gv_last_error(void);
+
+/* Paper defaults (see the field comments). */
+void gv_default_vf_params(gv_vf_params *p);
+void gv_default_uq_params(gv_uq_params *p);
+
+/* Workspace for vf_build over `n_train` training views (host array).  Runs
+ * the culling and binning counts on the GPU (synchronises hip_stream) and
+ * fills `plan` with exact capacities for these inputs. */
+gv_status vf_build_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *train,
+                                  int32_t n_train, const gv_vf_params *params, gv_workspace *plan,
+                                  void *hip_stream);
+
+/* Alg. 3 over the training views: gamma (device, planar [K][n], dtype
+ * gamma_dtype) = sum over views of v_p[g] a_l Y_k(d_p^g), with v_p from Alg. 2
+ * computed by rasterising each view (no per-view host synchronisation).  With
+ * params->accumulate = 1 the result is added to gamma (gamma is linear in the
+ * view set, so a field can be extended with new views).  Returns
+ * GV_ERR_CAPACITY (after synchronising) when the workspace was too small for
+ * these inputs; gamma is then unspecified. */
+gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                   const gv_vf_params *params, void *gamma, gv_dtype gamma_dtype,
+                   const gv_workspace *plan, void *workspace, void *hip_stream);
+
+/* Workspace for vf_query_views over `n_cand` candidate views. */
+gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *cand,
+                                  int32_t n_cand, const gv_uq_params *params, int32_t sh_degree,
+                                  gv_workspace *plan, void *hip_stream);
+
+/* Alg. 4 + Alg. 6 for every candidate view, all views in one launch
+ * sequence.  gamma: device, planar [K][n] of gamma_dtype, K = (sh_degree+1)^2;
+ * n_train = |P| of the AM-GM bound (0 gives V = 0 everywhere).
+ * scores: device [n_cand] float, sum over the view's pixels of the entropy
+ * bound.  maps: device float, optional (NULL, or params->write_maps = 0):
+ * the per-pixel maps packed view after view, row major, view v starting at
+ * the sum of width*height of views < v.  Enqueue only; a capacity overflow
+ * is reported by gv_workspace_check (the scores of an overflowed call are
+ * NaN). */
+gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                         const gv_uq_params *params, float *scores, float *maps,
+                         const gv_workspace *plan, void *workspace, void *hip_stream);
+
+/* Synchronises hip_stream and reads the workspace's status words:
+ * out[0] records used, out[1] instances needed, out[2] overflow flag (1 if a
+ * capacity was exceeded).  Returns GV_ERR_CAPACITY on overflow. */
+gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace,
+                             int64_t out[3], void *hip_stream);
+
+/* Bytes needed for a plan whose capacities the caller edited. */
+size_t gv_workspace_bytes(const gv_workspace *plan);
+
+/* Next-best view (eq. i_gain): index of the largest of the n device scores,
+ * lowest index on exact ties, NaN never wins (-1 if all are NaN).  Runs a
+ * device argmax, copies one int32 to `*best` (host) and synchronises. */
+gv_status select_next_view(gv_context *ctx, const float *scores, int32_t n, int32_t *best, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAVIS_H */

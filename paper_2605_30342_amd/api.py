@@ -1,0 +1,198 @@
+"""Thin Python layer over the C ABI: device buffers come from PyTorch, all
+work runs in libgavis.so.
+
+    ctx = Context()
+    dsc = DeviceScene(scene)                      # attributes resident on the GPU
+    gamma = ctx.vf_build(dsc, train_cams, sh_degree=2)
+    scores, maps = ctx.vf_query_views(dsc, gamma, 2, train_cams.n, cand_cams)
+    best = ctx.select_next_view(scores)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GV_BF16, GV_F16, GV_F32, check, load
+
+DTYPES = {"f32": GV_F32, "f16": GV_F16, "bf16": GV_BF16}
+TORCH_DTYPES = {GV_F32: torch.float32, GV_F16: torch.float16, GV_BF16: torch.bfloat16}
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def half_storage(means: np.ndarray, dtype: str, anchor_block: int = 256):
+    """Block-anchored storage of the means: FP32 anchors (block means) and
+    half offsets.  Returns (anchors [B,3] f32, offsets [N,3] f16/bf16 tensor,
+    dequantised means [N,3] f32 exactly as the kernels rebuild them)."""
+    n = means.shape[0]
+    nb = (n + anchor_block - 1) // anchor_block
+    pad = nb * anchor_block - n
+    m = np.concatenate([means, np.repeat(means[-1:], pad, 0)]) if pad else means
+    anchors = m.reshape(nb, anchor_block, 3).mean(1).astype(np.float32)
+    off = torch.from_numpy(means - np.repeat(anchors, anchor_block, 0)[:n]).to(
+        torch.float16 if dtype == "f16" else torch.bfloat16)
+    deq = np.repeat(anchors, anchor_block, 0)[:n] + off.float().numpy()
+    return anchors, off, deq.astype(np.float32)
+
+
+class DeviceScene:
+    """A scene's Gaussian attributes resident in device memory."""
+
+    def __init__(self, scene, device: str = "cuda", dtype: str = "f32", anchor_block: int = 256):
+        self.n = scene.n
+        self.n_virtual = int(scene.n_virtual)
+        self.dtype = DTYPES[dtype]
+        td = TORCH_DTYPES[self.dtype]
+        anchors = None
+        if self.dtype == GV_F32:
+            means = torch.from_numpy(np.ascontiguousarray(scene.means, np.float32))
+            self.dequantised_means = scene.means
+        else:
+            a, means, self.dequantised_means = half_storage(scene.means.astype(np.float32), dtype, anchor_block)
+            anchors = torch.from_numpy(a).to(device)
+        self.means = means.to(device).contiguous()
+        self.scales = torch.from_numpy(np.ascontiguousarray(scene.scales, np.float32)).to(td).to(device).contiguous()
+        self.quats = torch.from_numpy(np.ascontiguousarray(scene.quats, np.float32)).to(td).to(device).contiguous()
+        self.opacity = torch.from_numpy(np.ascontiguousarray(scene.opacity, np.float32)).to(td).to(device).contiguous()
+        self.anchors = anchors
+        self.anchor_block = anchor_block
+        self.c = _lib.gv_gaussians()
+        self.c.n = self.n
+        self.c.n_virtual = self.n_virtual
+        self.c.dtype = self.dtype
+        self.c.means = self.means.data_ptr()
+        self.c.scales = self.scales.data_ptr()
+        self.c.quats = self.quats.data_ptr()
+        self.c.opacity = self.opacity.data_ptr()
+        self.c.anchors = anchors.data_ptr() if anchors is not None else None
+        self.c.anchor_block = anchor_block if anchors is not None else 0
+
+    def nbytes(self) -> int:
+        t = [self.means, self.scales, self.quats, self.opacity] + ([self.anchors] if self.anchors is not None else [])
+        return sum(x.numel() * x.element_size() for x in t)
+
+
+@dataclass
+class Workspace:
+    plan: _lib.gv_workspace
+    buf: torch.Tensor
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.plan.bytes)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.L = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        check(self.L.gv_create(device, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- plans
+    def _alloc(self, plan) -> Workspace:
+        buf = torch.empty(max(int(plan.bytes), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return Workspace(plan, buf)
+
+    def build_workspace(self, dsc: DeviceScene, cams, params: _lib.gv_vf_params, stream=None) -> Workspace:
+        plan = _lib.gv_workspace()
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_build_workspace_size(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params),
+                                             ctypes.byref(plan), _stream(stream)))
+        return self._alloc(plan)
+
+    def query_workspace(self, dsc: DeviceScene, cams, params: _lib.gv_uq_params, sh_degree: int,
+                        stream=None, slack: float = 1.0) -> Workspace:
+        plan = _lib.gv_workspace()
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_query_workspace_size(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params),
+                                             sh_degree, ctypes.byref(plan), _stream(stream)))
+        if slack != 1.0:
+            plan.max_records = int(plan.max_records * slack) + 1
+            plan.max_instances = int(plan.max_instances * slack) + 1
+            plan.bytes = self.L.gv_workspace_bytes(ctypes.byref(plan))
+        return self._alloc(plan)
+
+    # ---------------------------------------------------------------- calls
+    def vf_build(self, dsc: DeviceScene, cams, sh_degree: int = 2, params: Optional[_lib.gv_vf_params] = None,
+                 ws: Optional[Workspace] = None, gamma: Optional[torch.Tensor] = None,
+                 gamma_dtype: str = "f32", stream=None) -> torch.Tensor:
+        if params is None:
+            params = _lib.default_vf_params(sh_degree=sh_degree)
+        if ws is None:
+            ws = self.build_workspace(dsc, cams, params, stream)
+        K = (params.sh_degree + 1) ** 2
+        gdt = DTYPES[gamma_dtype]
+        if gamma is None:
+            gamma = torch.empty((K, dsc.n), dtype=TORCH_DTYPES[gdt], device=f"cuda:{self.device}")
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_build(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params), _ptr(gamma), gdt,
+                              ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
+        return gamma
+
+    def vf_query_views(self, dsc: DeviceScene, gamma: torch.Tensor, sh_degree: int, n_train: int, cams,
+                       params: Optional[_lib.gv_uq_params] = None, ws: Optional[Workspace] = None,
+                       want_maps: bool = False, scores: Optional[torch.Tensor] = None,
+                       maps: Optional[torch.Tensor] = None, stream=None):
+        if params is None:
+            params = _lib.default_uq_params()
+        params.write_maps = 1 if want_maps else 0
+        if ws is None:
+            ws = self.query_workspace(dsc, cams, params, sh_degree, stream)
+        dev = f"cuda:{self.device}"
+        if scores is None:
+            scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
+        if want_maps and maps is None:
+            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+        gdt = {torch.float32: GV_F32, torch.float16: GV_F16, torch.bfloat16: GV_BF16}[gamma.dtype]
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_query_views(self.h, ctypes.byref(dsc.c), _ptr(gamma), gdt, sh_degree, int(n_train), cc,
+                                    cams.n, ctypes.byref(params), _ptr(scores), _ptr(maps) if want_maps else None,
+                                    ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
+        return scores, maps
+
+    def check_workspace(self, ws: Workspace, stream=None):
+        out = (ctypes.c_int64 * 3)()
+        st = self.L.gv_workspace_check(self.h, ctypes.byref(ws.plan), _ptr(ws.buf), out, _stream(stream))
+        return st, (int(out[0]), int(out[1]), int(out[2]))
+
+    def select_next_view(self, scores: torch.Tensor, stream=None) -> int:
+        best = ctypes.c_int32(-1)
+        check(self.L.select_next_view(self.h, _ptr(scores), int(scores.numel()), ctypes.byref(best),
+                                      _stream(stream)))
+        return int(best.value)
+
+
+def split_maps(maps: torch.Tensor, cams):
+    """Per-view [h, w] views of the packed maps tensor."""
+    out, off = [], 0
+    for w, h in cams.wh:
+        n = int(w) * int(h)
+        out.append(maps[off:off + n].view(int(h), int(w)))
+        off += n
+    return out

@@ -1,0 +1,727 @@
+// gv_bin.hip -- culling, projection (with the fused visibility-field query),
+// device scans, LSD radix sort and tile binning for gfx950.
+//
+// Layout of the work: a record is one (Gaussian, view) pair that survives a
+// conservative frustum test; records are numbered Gaussian-major (all views
+// of Gaussian 0, then Gaussian 1, ...) so that the build can accumulate a
+// Gaussian's views without atomics.  Records are sorted by FP32 depth (stable,
+// so equal depths keep index order), expanded into one instance per touched
+// 16x16 tile, and the instances are stably sorted by global tile id: every
+// tile's list is then in increasing (depth, Gaussian) order, the front-to-back
+// order that Alg. 2 and Alg. 6 composite in.
+#include "gv_device.hpp"
+#include "gv_launch.hpp"
+
+#include <type_traits>
+
+namespace gv {
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill_dev_u32(uint32_t *__restrict__ p, const uint32_t *__restrict__ n_dev, uint32_t mult,
+                               uint32_t value) {
+    const uint64_t n = (uint64_t)(*n_dev) * mult;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------- Gaussian loads
+
+template <typename TG>
+struct GaussIn {
+    const TG *means;
+    const TG *scales;
+    const TG *quats;
+    const TG *opac;
+    const float *anchors;
+    int32_t anchor_block;
+    int64_t n;
+    int64_t n_virtual;
+
+    __device__ __forceinline__ void mean(int64_t g, float m[3]) const {
+        if constexpr (std::is_same<TG, float>::value) {
+            m[0] = means[3 * g];
+            m[1] = means[3 * g + 1];
+            m[2] = means[3 * g + 2];
+        } else {
+            const int64_t b = g / anchor_block;
+            m[0] = anchors[3 * b] + load_f(means, 3 * g);
+            m[1] = anchors[3 * b + 1] + load_f(means, 3 * g + 1);
+            m[2] = anchors[3 * b + 2] + load_f(means, 3 * g + 2);
+        }
+    }
+    __device__ __forceinline__ void scale(int64_t g, float s[3]) const {
+        s[0] = load_f(scales, 3 * g);
+        s[1] = load_f(scales, 3 * g + 1);
+        s[2] = load_f(scales, 3 * g + 2);
+    }
+    __device__ __forceinline__ void quat(int64_t g, float q[4]) const {
+        q[0] = load_f(quats, 4 * g);
+        q[1] = load_f(quats, 4 * g + 1);
+        q[2] = load_f(quats, 4 * g + 2);
+        q[3] = load_f(quats, 4 * g + 3);
+    }
+    __device__ __forceinline__ float opacity(int64_t g) const { return load_f(opac, g); }
+};
+
+// ---------------------------------------------------------------- culling
+
+// Conservative in-view test, evaluated identically by the count, measure and
+// projection kernels (no FP contraction, so every kernel takes the same
+// decision).  It keeps every Gaussian whose exact EWA ellipse bounding box can
+// touch the image: the 2D x-variance is at most |J_x R|^2 s_max^2 + lowpass,
+// with |J_x R|^2 = (fx/z)^2 (1 + (x/z)^2).
+__device__ __forceinline__ bool cons_visible(const float m[3], float smax, const ViewDev &V, float znear,
+                                          float lowpass, float cut) {
+#pragma clang fp contract(off)
+    const float pz = V.R[6] * m[0] + V.R[7] * m[1] + V.R[8] * m[2] + V.t[2];
+    const float amax = fmaxf(fmaxf(fabsf(m[0]), fabsf(m[1])), fmaxf(fabsf(m[2]), 1.0f)) +
+                       fmaxf(fmaxf(fabsf(V.t[0]), fabsf(V.t[1])), fabsf(V.t[2]));
+    const float mg = 1e-4f * (1.0f + fabsf(pz) + amax);
+    if (!(pz > znear - mg)) return false;
+    if (pz < znear + mg) return true;
+    const float px = V.R[0] * m[0] + V.R[1] * m[1] + V.R[2] * m[2] + V.t[0];
+    const float py = V.R[3] * m[0] + V.R[4] * m[1] + V.R[5] * m[2] + V.t[1];
+    const float iz = 1.0f / pz;
+    const float ax = px * iz, ay = py * iz;
+    const float s2 = smax * smax;
+    const float wx2 = V.fx * V.fx * iz * iz * (1.0f + ax * ax);
+    const float wy2 = V.fy * V.fy * iz * iz * (1.0f + ay * ay);
+    const float rx = sqrtf(cut * (wx2 * s2 + lowpass)) * 1.01f + 2.0f;
+    const float ry = sqrtf(cut * (wy2 * s2 + lowpass)) * 1.01f + 2.0f;
+    const float ux = V.fx * ax + V.cx, uy = V.fy * ay + V.cy;
+    const float slx = 1e-4f * (fabsf(ux) + V.fx * fabsf(ax) + 1.0f);
+    const float sly = 1e-4f * (fabsf(uy) + V.fy * fabsf(ay) + 1.0f);
+    return (ux + rx + slx >= 0.0f) && (ux - rx - slx <= (float)V.w) && (uy + ry + sly >= 0.0f) &&
+           (uy - ry - sly <= (float)V.h);
+}
+
+// 3D covariance (R_q S)(R_q S)^T of one Gaussian in FP64: s00 s01 s02 s11 s12 s22.
+__device__ __forceinline__ void cov3d(const float s[3], const float q[4], double S[6]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double qn = sqrt(w * w + x * x + y * y + z * z);
+    const double iq = qn > 0.0 ? 1.0 / qn : 0.0;
+    w *= iq; x *= iq; y *= iq; z *= iq;
+    const double r00 = 1 - 2 * (y * y + z * z), r01 = 2 * (x * y - w * z), r02 = 2 * (x * z + w * y);
+    const double r10 = 2 * (x * y + w * z), r11 = 1 - 2 * (x * x + z * z), r12 = 2 * (y * z - w * x);
+    const double r20 = 2 * (x * z - w * y), r21 = 2 * (y * z + w * x), r22 = 1 - 2 * (x * x + y * y);
+    const double a = s[0], b = s[1], c = s[2];
+    const double m00 = r00 * a, m01 = r01 * b, m02 = r02 * c;
+    const double m10 = r10 * a, m11 = r11 * b, m12 = r12 * c;
+    const double m20 = r20 * a, m21 = r21 * b, m22 = r22 * c;
+    S[0] = m00 * m00 + m01 * m01 + m02 * m02;
+    S[1] = m00 * m10 + m01 * m11 + m02 * m12;
+    S[2] = m00 * m20 + m01 * m21 + m02 * m22;
+    S[3] = m10 * m10 + m11 * m11 + m12 * m12;
+    S[4] = m10 * m20 + m11 * m21 + m12 * m22;
+    S[5] = m20 * m20 + m21 * m21 + m22 * m22;
+}
+
+struct Proj {
+    bool ok;
+    double z, ux, uy, ca, cb, cc;
+    int x0, x1, y0, y1;   // tile rectangle, half open
+};
+
+// Exact EWA projection in FP64 (the camera values and the attributes are the
+// FP32 inputs): z, centre u, conic = inverse of J R S3 R^T J^T + lowpass I,
+// and the tiles whose pixel centres can lie inside the m <= cut ellipse.
+__device__ __forceinline__ void project_exact(const float m[3], const double S[6], const ViewDev &V, float znear,
+                                           float lowpass, float cut, Proj &P) {
+#pragma clang fp contract(off)
+    P.ok = false;
+    const double mx = m[0], my = m[1], mz = m[2];
+    const double px = (double)V.R[0] * mx + (double)V.R[1] * my + (double)V.R[2] * mz + (double)V.t[0];
+    const double py = (double)V.R[3] * mx + (double)V.R[4] * my + (double)V.R[5] * mz + (double)V.t[1];
+    const double pz = (double)V.R[6] * mx + (double)V.R[7] * my + (double)V.R[8] * mz + (double)V.t[2];
+    P.z = pz;
+    if (!(pz > (double)znear)) return;
+    const double iz = 1.0 / pz;
+    const double fx = V.fx, fy = V.fy;
+    const double jx0 = fx * iz, jx2 = -fx * px * iz * iz;
+    const double jy1 = fy * iz, jy2 = -fy * py * iz * iz;
+    // W = J R (2x3)
+    const double w00 = jx0 * V.R[0] + jx2 * V.R[6], w01 = jx0 * V.R[1] + jx2 * V.R[7], w02 = jx0 * V.R[2] + jx2 * V.R[8];
+    const double w10 = jy1 * V.R[3] + jy2 * V.R[6], w11 = jy1 * V.R[4] + jy2 * V.R[7], w12 = jy1 * V.R[5] + jy2 * V.R[8];
+    const double t0 = S[0] * w00 + S[1] * w01 + S[2] * w02;
+    const double t1 = S[1] * w00 + S[3] * w01 + S[4] * w02;
+    const double t2 = S[2] * w00 + S[4] * w01 + S[5] * w02;
+    const double u0 = S[0] * w10 + S[1] * w11 + S[2] * w12;
+    const double u1 = S[1] * w10 + S[3] * w11 + S[4] * w12;
+    const double u2 = S[2] * w10 + S[4] * w11 + S[5] * w12;
+    const double a = w00 * t0 + w01 * t1 + w02 * t2 + (double)lowpass;
+    const double b = w10 * t0 + w11 * t1 + w12 * t2;
+    const double c = w10 * u0 + w11 * u1 + w12 * u2 + (double)lowpass;
+    const double det = a * c - b * b;
+    if (!(det > 1e-12)) return;
+    const double idet = 1.0 / det;
+    P.ca = c * idet;
+    P.cb = -b * idet;
+    P.cc = a * idet;
+    P.ux = fx * px * iz + (double)V.cx;
+    P.uy = fy * py * iz + (double)V.cy;
+    const double rx = sqrt((double)cut * a) * (1.0 + 1e-6) + 1e-4;
+    const double ry = sqrt((double)cut * c) * (1.0 + 1e-6) + 1e-4;
+    double i0 = ceil(P.ux - rx - 0.5), i1 = floor(P.ux + rx - 0.5);
+    double j0 = ceil(P.uy - ry - 0.5), j1 = floor(P.uy + ry - 0.5);
+    i0 = fmax(i0, 0.0); j0 = fmax(j0, 0.0);
+    i1 = fmin(i1, (double)(V.w - 1)); j1 = fmin(j1, (double)(V.h - 1));
+    if (!(i0 <= i1) || !(j0 <= j1)) return;
+    P.x0 = (int)i0 >> TILE_SHIFT;
+    P.x1 = ((int)i1 >> TILE_SHIFT) + 1;
+    P.y0 = (int)j0 >> TILE_SHIFT;
+    P.y1 = ((int)j1 >> TILE_SHIFT) + 1;
+    P.ok = true;
+}
+
+template <typename TG>
+__global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
+                                              float znear, float lowpass, float cut, uint32_t *__restrict__ cnt) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= G.n) return;
+    float m[3], s[3];
+    G.mean(g, m);
+    G.scale(g, s);
+    const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
+    uint32_t c = 0;
+    for (int v = 0; v < nv; ++v) c += cons_visible(m, smax, views[v], znear, lowpass, cut) ? 1u : 0u;
+    cnt[g] = c;
+}
+
+// Sizing pass: counts records (conservative test) and exact instances.
+template <typename TG>
+__global__ __launch_bounds__(WG) void k_measure(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
+                                                float znear, float lowpass, float cut,
+                                                unsigned long long *__restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    unsigned long long rc = 0, mc = 0;
+    if (g < G.n) {
+        float m[3], s[3], q[4];
+        G.mean(g, m);
+        G.scale(g, s);
+        G.quat(g, q);
+        const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
+        double S[6];
+        cov3d(s, q, S);
+        for (int v = 0; v < nv; ++v) {
+            if (!cons_visible(m, smax, views[v], znear, lowpass, cut)) continue;
+            ++rc;
+            Proj P;
+            project_exact(m, S, views[v], znear, lowpass, cut, P);
+            if (P.ok) mc += (unsigned long long)(P.x1 - P.x0) * (unsigned long long)(P.y1 - P.y0);
+        }
+    }
+    // wave totals, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        rc += __shfl_xor(rc, off);
+        mc += __shfl_xor(mc, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[0], rc);
+        atomicAdd(&out[1], mc);
+    }
+}
+
+// Projection of every surviving (Gaussian, view) pair into its record slot.
+// QUERY: also evaluates the visibility field in the direction camera ->
+// Gaussian (Alg. 4): V~ = sum_k gamma_k Y_k(d), clamped to [0, |P|], then
+// V = 1 - (1 - V~/|P|)^|P| computed as 1 - exp(|P| log1p(-V~/|P|)).
+template <typename TG, typename TGam, bool QUERY, int L>
+__global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
+                                                float znear, float lowpass, float cut,
+                                                const uint32_t *__restrict__ offs, const Status *__restrict__ st,
+                                                uint32_t rcap, const TGam *__restrict__ gamma, float n_train,
+                                                Rec *__restrict__ rec, uint32_t *__restrict__ key,
+                                                Bin *__restrict__ bin) {
+    constexpr int K = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= G.n) return;
+    if (st->overflow & 1u) return;
+    float m[3], s[3], q[4];
+    G.mean(g, m);
+    G.scale(g, s);
+    G.quat(g, q);
+    const float o = G.opacity(g);
+    const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
+    double S[6];
+    cov3d(s, q, S);
+    float gam[K > 0 ? K : 1];
+    const bool virt = g >= G.n - G.n_virtual;
+    if constexpr (QUERY) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) gam[k] = load_f(gamma, (int64_t)k * G.n + g);
+    }
+    uint32_t r = offs[g];
+    const uint32_t rend = offs[g + 1];
+    const double sc = 0.8493218002880191;   // sqrt(log2(e) / 2)
+    for (int v = 0; v < nv; ++v) {
+        const ViewDev &V = views[v];
+        if (!cons_visible(m, smax, V, znear, lowpass, cut)) continue;
+        if (r >= rend || r >= rcap) break;
+        Proj P;
+        project_exact(m, S, V, znear, lowpass, cut, P);
+        Bin b;
+        b.view = v;
+        if (!P.ok) {
+            b.x0y0 = b.x1y1 = b.ntiles = 0;
+            bin[r] = b;
+            key[r] = DEAD_KEY;
+            rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            ++r;
+            continue;
+        }
+        b.x0y0 = (uint32_t)P.x0 | ((uint32_t)P.y0 << 16);
+        b.x1y1 = (uint32_t)P.x1 | ((uint32_t)P.y1 << 16);
+        b.ntiles = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+        const double ax = fmin(fmax(rint(P.ux), -32768.0), 32767.0);
+        const double ay = fmin(fmax(rint(P.uy), -32768.0), 32767.0);
+        Rec R;
+        R.uv = (int32_t)(((uint32_t)(int)ax & 0xFFFFu) | ((uint32_t)(int)ay << 16));
+        R.fx = (float)(P.ux - ax);
+        R.fy = (float)(P.uy - ay);
+        const double l11 = sqrt(P.ca);
+        const double l21 = P.cb / l11;
+        const double l22 = sqrt(fmax(P.cc - l21 * l21, 0.0));
+        R.l11 = (float)(sc * l11);
+        R.l21 = (float)(sc * l21);
+        R.l22 = (float)(sc * l22);
+        R.o = o;
+        float vis = 0.0f;
+        if constexpr (QUERY) {
+            if (!virt && n_train > 0.0f) {
+                float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+                const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+                if (nrm > 0.0f) {
+                    const float inv = 1.0f / nrm;
+                    dx *= inv; dy *= inv; dz *= inv;
+                    float Y[K];
+                    sh_eval<L>(dx, dy, dz, Y);
+                    float vt = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) vt = fmaf(gam[k], Y[k], vt);
+                    vt = fminf(fmaxf(vt, 0.0f), n_train);
+                    vis = (vt >= n_train) ? 1.0f : 1.0f - expf(n_train * log1pf(-vt / n_train));
+                }
+            }
+        }
+        R.v = vis;
+        rec[r] = R;
+        key[r] = __float_as_uint((float)P.z);
+        bin[r] = b;
+        ++r;
+    }
+}
+
+// ---------------------------------------------------------------- device exclusive scan
+
+// Three phases over up to n = min(*n_dev or n_host, cap) uint32 values:
+// block sums, a single-block scan of the block sums (64-bit totals), and the
+// per-block scan.  out[n] receives the total (wrapped to 32 bits); the
+// 64-bit total goes to *total and min(total, tcap) to *eff; a total above
+// tcap sets `flag_bit` in *overflow.
+
+__device__ __forceinline__ uint64_t scan_n(const uint32_t *n_dev, uint64_t n_host) {
+    return n_dev ? (uint64_t)(*n_dev) : n_host;
+}
+
+__global__ __launch_bounds__(WG) void k_scan_reduce(const uint32_t *__restrict__ in, const uint32_t *n_dev,
+                                                    uint64_t n_host, unsigned long long *__restrict__ blk) {
+    const uint64_t n = scan_n(n_dev, n_host);
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
+    if (base >= n) {
+        if (threadIdx.x == 0) blk[blockIdx.x] = 0ull;
+        return;
+    }
+    unsigned long long s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const uint64_t i = base + (uint64_t)k * WG + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    __shared__ unsigned long long red[WAVES];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < WAVES; ++w) t += red[w];
+        blk[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(unsigned long long *__restrict__ blk, const uint32_t *n_dev,
+                                                      uint64_t n_host, unsigned long long *total, uint32_t *eff,
+                                                      uint64_t tcap, uint32_t *overflow, uint32_t flag_bit) {
+    const uint64_t n = scan_n(n_dev, n_host);
+    const uint64_t nb = n / SCAN_BLOCK + 1;   // includes the block that holds out[n]
+    __shared__ unsigned long long buf[1024];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t s = 0; s < nb; s += 1024) {
+        const uint64_t i = s + threadIdx.x;
+        const unsigned long long x = i < nb ? blk[i] : 0ull;
+        buf[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            buf[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nb) blk[i] = carry + buf[threadIdx.x] - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long t = carry;
+        if (total) *total = t;
+        if (eff) *eff = (uint32_t)(t < tcap ? t : tcap);
+        if (t > tcap && overflow) atomicOr(overflow, flag_bit);
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                  const uint32_t *n_dev, uint64_t n_host,
+                                                  const unsigned long long *__restrict__ blk) {
+    const uint64_t n = scan_n(n_dev, n_host);
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
+    if (base > n) return;
+    // each thread owns SCAN_ITEMS consecutive elements
+    const uint64_t my = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    unsigned long long s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (my + k < n) ? in[my + k] : 0u;
+        s += v[k];
+    }
+    __shared__ unsigned long long buf[WG];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < WG; off <<= 1) {
+        const unsigned long long y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        buf[threadIdx.x] += y;
+        __syncthreads();
+    }
+    unsigned long long run = blk[blockIdx.x] + buf[threadIdx.x] - s;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (my + k < n) out[my + k] = (uint32_t)run;
+        else if (my + k == n) out[n] = (uint32_t)run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------- LSD radix sort
+
+// Each pass sorts (key, value) pairs stably by an 8-bit digit.  The n pairs
+// are cut into RADIX_BLOCKS contiguous chunks (multiples of 256); block b
+// histograms its chunk, the histograms are scanned digit-major, and block b
+// scatters its chunk in 256-element tiles, ranking equal digits inside a wave
+// by ballot matching and across the four waves through LDS counts.
+
+__device__ __forceinline__ void radix_chunk(uint64_t n, uint64_t &start, uint64_t &end) {
+    uint64_t ch = (n + RADIX_BLOCKS - 1) / RADIX_BLOCKS;
+    ch = (ch + WG - 1) / WG * WG;
+    if (ch == 0) ch = WG;
+    start = (uint64_t)blockIdx.x * ch;
+    end = start + ch;
+    if (end > n) end = n;
+    if (start > n) start = n;
+}
+
+__global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
+                                                   int shift, int nbits, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[RADIX];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t start, end;
+    radix_chunk(*n_dev, start, end);
+    const uint32_t mask = (1u << nbits) - 1u;
+    for (uint64_t i = start + threadIdx.x; i < end; i += WG) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    hist[(size_t)threadIdx.x * RADIX_BLOCKS + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's RADIX_BLOCKS counts.
+__global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t *__restrict__ dtot) {
+    constexpr int PER = RADIX_BLOCKS / WG;
+    uint32_t *row = hist + (size_t)blockIdx.x * RADIX_BLOCKS;
+    uint32_t v[PER];
+    uint32_t s = 0;
+    for (int k = 0; k < PER; ++k) {
+        v[k] = row[threadIdx.x * PER + k];
+        s += v[k];
+    }
+    __shared__ uint32_t buf[WG];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < WG; off <<= 1) {
+        const uint32_t y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+        __syncthreads();
+        buf[threadIdx.x] += y;
+        __syncthreads();
+    }
+    uint32_t run = buf[threadIdx.x] - s;
+    for (int k = 0; k < PER; ++k) {
+        row[threadIdx.x * PER + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == WG - 1) dtot[blockIdx.x] = buf[WG - 1];
+}
+
+__global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                      const uint32_t *n_dev, int shift, int nbits,
+                                                      const uint32_t *__restrict__ hist,
+                                                      const uint32_t *__restrict__ dtot) {
+    __shared__ uint32_t run[RADIX];
+    __shared__ uint32_t wcnt[2][WAVES][RADIX];
+    __shared__ uint32_t scan[RADIX];
+    const int t = threadIdx.x, w = t >> 6;
+    // digit bases: exclusive scan of the digit totals plus this block's offset
+    {
+        const uint32_t d = dtot[t];
+        scan[t] = d;
+        __syncthreads();
+        for (int off = 1; off < RADIX; off <<= 1) {
+            const uint32_t y = t >= off ? scan[t - off] : 0u;
+            __syncthreads();
+            scan[t] += y;
+            __syncthreads();
+        }
+        run[t] = scan[t] - d + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
+        for (int ww = 0; ww < WAVES; ++ww) {
+            wcnt[0][ww][t] = 0;
+            wcnt[1][ww][t] = 0;
+        }
+    }
+    __syncthreads();
+    uint64_t start, end;
+    radix_chunk(*n_dev, start, end);
+    const uint32_t mask = (1u << nbits) - 1u;
+    int buf = 0;
+    for (uint64_t s = start; s < end; s += WG) {
+        const uint64_t i = s + t;
+        const bool valid = i < end;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+        const uint32_t d = (k >> shift) & mask;
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = lanes_below(peers);
+        if (valid && rank == 0) wcnt[buf][w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // digit t: offsets of the four waves, then advance the running base
+            uint32_t acc = run[t];
+            for (int ww = 0; ww < WAVES; ++ww) {
+                const uint32_t c = wcnt[buf][ww][t];
+                wcnt[buf][ww][t] = acc;
+                acc += c;
+                wcnt[buf ^ 1][ww][t] = 0;
+            }
+            run[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[buf][w][d] + rank;
+            kout[pos] = k;
+            vout[pos] = val;
+        }
+        buf ^= 1;
+    }
+}
+
+// ---------------------------------------------------------------- binning
+
+// Tile count of every record, in depth order.
+__global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
+                                                      const uint32_t *n_dev, uint32_t *__restrict__ icnt) {
+    const uint64_t n = *n_dev;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
+        icnt[i] = bin[sval[i]].ntiles;
+}
+
+// One (global tile id, record) instance per tile of every record, written in
+// depth order so that a stable sort by tile id keeps depth order in a tile.
+__global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
+                                             const uint32_t *__restrict__ ioff, const ViewDev *__restrict__ views,
+                                             const Status *__restrict__ st, uint32_t *__restrict__ ikey,
+                                             uint32_t *__restrict__ ival) {
+    if (st->overflow) return;
+    const uint64_t n = st->R_eff;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint32_t r = sval[i];
+        const Bin b = bin[r];
+        if (b.ntiles == 0) continue;
+        const ViewDev &V = views[b.view];
+        uint32_t o = ioff[i];
+        const int x0 = b.x0y0 & 0xFFFF, y0 = b.x0y0 >> 16, x1 = b.x1y1 & 0xFFFF, y1 = b.x1y1 >> 16;
+        for (int ty = y0; ty < y1; ++ty)
+            for (int tx = x0; tx < x1; ++tx) {
+                ikey[o] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+                ival[o] = r;
+                ++o;
+            }
+    }
+}
+
+// [start, end) of every tile's run in the sorted instance list.
+__global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key, const Status *__restrict__ st,
+                                               uint2 *__restrict__ ranges) {
+    if (st->overflow) return;
+    const uint64_t n = st->M_eff;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint32_t k = key[i];
+        if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
+        if (i + 1 == n || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+
+static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u * 4u) {
+    uint64_t g = (n + WG - 1) / WG;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 4096)), dim3(WG), 0, s, p, n, value);
+}
+
+void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_dev_u32, dim3(2048), dim3(WG), 0, s, p, n_dev, mult, value);
+}
+
+template <typename TG>
+static GaussIn<TG> gin(const GaussArgs &a) {
+    GaussIn<TG> G;
+    G.means = (const TG *)a.means;
+    G.scales = (const TG *)a.scales;
+    G.quats = (const TG *)a.quats;
+    G.opac = (const TG *)a.opacity;
+    G.anchors = a.anchors;
+    G.anchor_block = a.anchor_block > 0 ? a.anchor_block : 1;
+    G.n = a.n;
+    G.n_virtual = a.n_virtual;
+    return G;
+}
+
+void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, hipStream_t s) {
+    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    if (grid == 0) return;
+    switch (a.dtype) {
+    case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
+    case 1: hipLaunchKernelGGL(k_count<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
+    default: hipLaunchKernelGGL(k_count<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
+    }
+}
+
+void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
+                    hipStream_t s) {
+    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    if (grid == 0) return;
+    switch (a.dtype) {
+    case 0: hipLaunchKernelGGL(k_measure<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, out); break;
+    case 1: hipLaunchKernelGGL(k_measure<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, out); break;
+    default: hipLaunchKernelGGL(k_measure<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, out); break;
+    }
+}
+
+template <typename TG, typename TGam, bool QUERY>
+static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
+                               const uint32_t *offs, const Status *st, uint32_t rcap, const void *gamma,
+                               float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    const TGam *gm = (const TGam *)gamma;
+    switch (L) {
+    case 0: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 0>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
+    case 1: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 1>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
+    case 2: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 2>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
+    default: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 3>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
+    }
+}
+
+template <typename TG>
+static void project_dispatch_gam(int gdt, bool query, int L, const GaussArgs &a, const ViewDev *views, int nv,
+                                 const GeomArgs &p, const uint32_t *offs, const Status *st, uint32_t rcap,
+                                 const void *gamma, float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+    if (!query) {
+        project_dispatch_L<TG, float, false>(0, a, views, nv, p, offs, st, rcap, nullptr, 0.f, rec, key, bin, s);
+        return;
+    }
+    switch (gdt) {
+    case 0: project_dispatch_L<TG, float, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 1: project_dispatch_L<TG, _Float16, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    default: project_dispatch_L<TG, uint16_t, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    }
+}
+
+void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
+                    const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
+                    float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+    if (a.n == 0) return;
+    switch (a.dtype) {
+    case 0: project_dispatch_gam<float>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 1: project_dispatch_gam<_Float16>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    default: project_dispatch_gam<uint16_t>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    }
+}
+
+void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
+                 unsigned long long *blk, unsigned long long *total, uint32_t *eff, uint64_t tcap,
+                 uint32_t *overflow, uint32_t flag_bit, hipStream_t s) {
+    const unsigned nb = (unsigned)((n_cap + SCAN_BLOCK) / SCAN_BLOCK);   // covers out[n] too
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(WG), 0, s, in, n_dev, n_host, blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, n_dev, n_host, total, eff, tcap, overflow, flag_bit);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(WG), 0, s, in, out, n_dev, n_host, blk);
+}
+
+size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / SCAN_BLOCK) + 1; }
+
+// Sorts n = *n_dev pairs on key bits [0, bits).  Returns 0 if the result is
+// in (k0, v0), 1 if it is in (k1, v1).  With iota set, the input values are
+// the indices 0..n-1 and v0 is only used as a buffer.
+int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
+                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s) {
+    int cur = 0;
+    const uint32_t *vin = iota ? nullptr : v0;
+    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
+        const int nb = bits - shift < RADIX_BITS ? bits - shift : RADIX_BITS;
+        uint32_t *ki = cur ? k1 : k0, *ko = cur ? k0 : k1;
+        uint32_t *vo = cur ? v0 : v1;
+        hipLaunchKernelGGL(k_radix_hist, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, n_dev, shift, nb, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, hist, dtot);
+        cur ^= 1;
+        vin = cur ? v1 : v0;
+    }
+    return cur;
+}
+
+void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_ntiles, dim3(2048), dim3(WG), 0, s, sval, bin, n_dev, icnt);
+}
+
+void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const ViewDev *views, const Status *st,
+                 uint32_t *ikey, uint32_t *ival, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, views, st, ikey, ival);
+}
+
+void launch_ranges(const uint32_t *key, const Status *st, uint2 *ranges, hipStream_t s) {
+    hipLaunchKernelGGL(k_ranges, dim3(4096), dim3(WG), 0, s, key, st, ranges);
+}
+
+}  // namespace gv

@@ -1,0 +1,628 @@
+// gv_capi.cpp -- C ABI of the visibility-field path: argument checks,
+// workspace planning, and the launch sequence of one call.
+//
+// Every call runs the same pipeline over all the views it is given:
+//   count (conservative culling)  -> scan -> project (+ VF query)
+//   -> radix sort by depth -> per-record tile counts -> scan -> emit
+//   -> radix sort by tile -> tile ranges -> raster (VF CONST or VF QUERY)
+//   -> VF accumulation (build) or per-view scores (query).
+// No host synchronisation happens inside the sequence: record and instance
+// counts stay on the device, every kernel reads them from the workspace's
+// status words and is launched with a grid that does not depend on them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gavis.h"
+#include "gv_device.hpp"
+#include "gv_launch.hpp"
+
+using namespace gv;
+
+namespace {
+
+thread_local std::string g_err;
+
+gv_status fail(gv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define GV_HIP(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) return fail(GV_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GV_TRY(x)                   \
+    do {                            \
+        gv_status s_ = (x);         \
+        if (s_ != GV_OK) return s_; \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int old = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) == hipSuccess && old != dev) (void)hipSetDevice(dev);
+        else old = -1;
+    }
+    ~DeviceGuard() {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+// Modified spherical Bessel function i_l(x) for the vMF constants
+// a_l = 4 pi e^{-kappa} i_l(kappa): ascending series for small arguments,
+// upward recurrence from i_0 = sinh x / x, i_1 = (x cosh x - sinh x) / x^2
+// for large ones.
+double bessel_i(int l, double x) {
+    if (x == 0.0) return l == 0 ? 1.0 : 0.0;
+    if (x < 8.0) {
+        double lead = 1.0;
+        for (int k = 1; k <= l; ++k) lead *= x / (2.0 * k + 1.0);
+        double term = 1.0, sum = 1.0;
+        const double h = 0.5 * x * x;
+        for (int k = 1; k < 200 && std::fabs(term) > 1e-17 * sum; ++k) {
+            term *= h / (k * (2.0 * l + 2.0 * k + 1.0));
+            sum += term;
+        }
+        return lead * sum;
+    }
+    double im1 = std::sinh(x) / x;
+    if (l == 0) return im1;
+    double i = (x * std::cosh(x) - std::sinh(x)) / (x * x);
+    for (int k = 1; k < l; ++k) {
+        const double nx = im1 - (2.0 * k + 1.0) / x * i;
+        im1 = i;
+        i = nx;
+    }
+    return i;
+}
+
+bool finite_cam(const gv_camera &c) {
+    for (float v : c.R)
+        if (!std::isfinite(v)) return false;
+    for (float v : c.t)
+        if (!std::isfinite(v)) return false;
+    return std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) && c.fx > 0.f &&
+           c.fy > 0.f;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t status, views, cnt, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
+    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, total;
+};
+
+Layout make_layout(const gv_workspace &p) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al256(bytes > 0 ? bytes : 1);
+        return at;
+    };
+    const uint64_t N = (uint64_t)p.n, R = (uint64_t)p.max_records, M = (uint64_t)p.max_instances;
+    const uint64_t T = (uint64_t)p.total_tiles, V = (uint64_t)p.n_views;
+    const int K = (p.sh_degree + 1) * (p.sh_degree + 1);
+    L.status = take(sizeof(Status));
+    L.views = take(V * sizeof(ViewDev));
+    L.cnt = take(N * 4);
+    L.offs = take((N + 1) * 4);
+    L.blk = take(scan_blk_count(std::max(N, R)) * 8);
+    L.rec = take(R * sizeof(Rec));
+    L.bin = take(R * sizeof(Bin));
+    L.key0 = take(R * 4);
+    L.val0 = take(R * 4);
+    L.key1 = take(R * 4);
+    L.val1 = take(R * 4);
+    L.icnt = take(R * 4);
+    L.ioff = take((R + 1) * 4);
+    L.ikey0 = take(M * 4);
+    L.ival0 = take(M * 4);
+    L.ikey1 = take(M * 4);
+    L.ival1 = take(M * 4);
+    L.ranges = take(T * 8);
+    L.hist = take((size_t)RADIX * RADIX_BLOCKS * 4);
+    L.dtot = take((size_t)RADIX * 4);
+    if (p.kind == 0) {
+        L.accT = take(R * 4);
+        L.accC = take(R * 4);
+        L.gam32 = take(N * (uint64_t)K * 4);
+    } else {
+        L.tpart = take(T * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+int bits_for(uint64_t n) {   // bits needed to hold values 0..n-1
+    int b = 1;
+    while (b < 32 && ((uint64_t)1 << b) < n) ++b;
+    return b;
+}
+
+}  // namespace
+
+struct gv_context {
+    int device = 0;
+    unsigned long long *dev_counters = nullptr;   // sizing counters
+    int32_t *dev_best = nullptr;
+    ViewDev *dev_views = nullptr;                 // view table for sizing passes
+    size_t dev_views_cap = 0;
+    std::vector<ViewDev> host_views;
+};
+
+// Fills host view descriptors; returns total tiles and pixels.
+static gv_status make_views(const gv_camera *cams, int32_t n, std::vector<ViewDev> &out, int64_t &tiles,
+                            int64_t &pixels) {
+    out.resize((size_t)n);
+    tiles = 0;
+    pixels = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const gv_camera &c = cams[i];
+        if (c.width < 1 || c.height < 1 || c.width > GV_MAX_IMAGE_SIDE || c.height > GV_MAX_IMAGE_SIDE)
+            return fail(GV_ERR_INVALID_ARG, "camera %d: image size %dx%d outside 1..%d", i, c.width, c.height,
+                        GV_MAX_IMAGE_SIDE);
+        if (!finite_cam(c)) return fail(GV_ERR_INVALID_ARG, "camera %d: non-finite or non-positive parameters", i);
+        ViewDev &V = out[(size_t)i];
+        std::memset(&V, 0, sizeof(V));
+        std::memcpy(V.R, c.R, sizeof(V.R));
+        std::memcpy(V.t, c.t, sizeof(V.t));
+        V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+        for (int k = 0; k < 3; ++k) {
+            const double C = -((double)c.R[0 * 3 + k] * c.t[0] + (double)c.R[1 * 3 + k] * c.t[1] +
+                               (double)c.R[2 * 3 + k] * c.t[2]);
+            V.C[k] = (float)C;
+        }
+        V.w = c.width;
+        V.h = c.height;
+        V.tiles_x = (c.width + TILE - 1) / TILE;
+        V.tiles_y = (c.height + TILE - 1) / TILE;
+        V.tile_base = (int32_t)tiles;
+        V.pix_base = pixels;
+        tiles += (int64_t)V.tiles_x * V.tiles_y;
+        pixels += (int64_t)c.width * c.height;
+        if (tiles > (int64_t)1 << 30) return fail(GV_ERR_INVALID_ARG, "too many tiles in one call");
+    }
+    return GV_OK;
+}
+
+static gv_status check_gauss(const gv_gaussians *g) {
+    if (!g) return fail(GV_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n_virtual < 0 || g->n_virtual > g->n)
+        return fail(GV_ERR_INVALID_ARG, "bad Gaussian counts n=%lld n_virtual=%lld", (long long)g->n,
+                    (long long)g->n_virtual);
+    if (g->n > ((int64_t)1 << 31) - 2) return fail(GV_ERR_INVALID_ARG, "n too large");
+    if (g->dtype != GV_F32 && g->dtype != GV_F16 && g->dtype != GV_BF16)
+        return fail(GV_ERR_INVALID_ARG, "bad Gaussian dtype %d", (int)g->dtype);
+    if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity))
+        return fail(GV_ERR_INVALID_ARG, "NULL Gaussian attribute pointer");
+    if (g->dtype != GV_F32 && g->n > 0 && (!g->anchors || g->anchor_block < 1))
+        return fail(GV_ERR_INVALID_ARG, "half-precision means need anchors and anchor_block >= 1");
+    return GV_OK;
+}
+
+static GaussArgs gargs(const gv_gaussians *g) {
+    GaussArgs a;
+    a.n = g->n;
+    a.n_virtual = g->n_virtual;
+    a.dtype = (int)g->dtype;
+    a.means = g->means;
+    a.scales = g->scales;
+    a.quats = g->quats;
+    a.opacity = g->opacity;
+    a.anchors = g->anchors;
+    a.anchor_block = g->anchor_block;
+    return a;
+}
+
+static gv_status geom_ok(float znear, float lowpass, float cut, float eps_T) {
+    if (!(std::isfinite(znear) && znear > 0.f)) return fail(GV_ERR_INVALID_ARG, "znear must be > 0");
+    if (!(std::isfinite(lowpass) && lowpass >= 0.f)) return fail(GV_ERR_INVALID_ARG, "lowpass must be >= 0");
+    if (!(std::isfinite(cut) && cut > 0.f)) return fail(GV_ERR_INVALID_ARG, "cut must be > 0");
+    if (!(std::isfinite(eps_T) && eps_T > 0.f && eps_T < 1.f)) return fail(GV_ERR_INVALID_ARG, "eps_T must be in (0, 1)");
+    return GV_OK;
+}
+
+// Measures one set of views: conservative records and exact instances.
+static gv_status measure(gv_context *ctx, const gv_gaussians *g, const std::vector<ViewDev> &views,
+                         const GeomArgs &geo, uint64_t &R, uint64_t &M, hipStream_t s) {
+    R = M = 0;
+    if (views.empty() || g->n == 0) return GV_OK;
+    const size_t need = views.size() * sizeof(ViewDev);
+    if (need > ctx->dev_views_cap) {
+        if (ctx->dev_views) (void)hipFree(ctx->dev_views);
+        ctx->dev_views = nullptr;
+        ctx->dev_views_cap = 0;
+        if (hipMalloc((void **)&ctx->dev_views, need) != hipSuccess)
+            return fail(GV_ERR_OUT_OF_MEMORY, "cannot allocate %zu bytes for a view table", need);
+        ctx->dev_views_cap = need;
+    }
+    GV_HIP(hipMemcpyAsync(ctx->dev_views, views.data(), need, hipMemcpyHostToDevice, s));
+    GV_HIP(hipMemsetAsync(ctx->dev_counters, 0, 4 * sizeof(unsigned long long), s));
+    launch_measure(gargs(g), ctx->dev_views, (int)views.size(), geo, ctx->dev_counters, s);
+    GV_HIP(hipGetLastError());
+    unsigned long long h[2] = {0, 0};
+    GV_HIP(hipMemcpyAsync(h, ctx->dev_counters, sizeof(h), hipMemcpyDeviceToHost, s));
+    GV_HIP(hipStreamSynchronize(s));
+    R = h[0];
+    M = h[1];
+    return GV_OK;
+}
+
+static gv_status plan_check(const gv_workspace *plan, const void *ws, int kind, int64_t n, int32_t nv,
+                            int64_t tiles, int64_t pixels) {
+    if (!plan || !ws) return fail(GV_ERR_INVALID_ARG, "NULL workspace or plan");
+    if (plan->kind != kind) return fail(GV_ERR_INVALID_ARG, "workspace plan made for the other call");
+    if (plan->n != n) return fail(GV_ERR_INVALID_ARG, "workspace plan made for n=%lld, got %lld",
+                                  (long long)plan->n, (long long)n);
+    if (nv > plan->n_views || tiles > plan->total_tiles || pixels > plan->total_pixels)
+        return fail(GV_ERR_CAPACITY, "workspace plan too small for these views");
+    if (plan->max_records < 0 || plan->max_instances < 0 || plan->max_records > 0x7fffffffLL ||
+        plan->max_instances > 0x7fffffffLL)
+        return fail(GV_ERR_INVALID_ARG, "workspace capacities out of range");
+    if (plan->bytes < make_layout(*plan).total) return fail(GV_ERR_CAPACITY, "workspace plan bytes too small");
+    return GV_OK;
+}
+
+// The shared binning sequence; returns the sorted tile keys/values buffers.
+struct Binned {
+    const uint32_t *sval;   // record ids in depth order
+    const uint32_t *ival;   // record ids in (tile, depth) order
+};
+
+static gv_status run_binning(const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
+                             int64_t tiles, const GeomArgs &geo, bool query, int sh, const void *gamma, int gdt,
+                             float n_train, hipStream_t s, Binned &out) {
+    Status *st = at<Status>(ws, L.status);
+    ViewDev *views = at<ViewDev>(ws, L.views);
+    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs);
+    unsigned long long *blk = at<unsigned long long>(ws, L.blk);
+    Rec *rec = at<Rec>(ws, L.rec);
+    Bin *bin = at<Bin>(ws, L.bin);
+    uint32_t *k0 = at<uint32_t>(ws, L.key0), *v0 = at<uint32_t>(ws, L.val0);
+    uint32_t *k1 = at<uint32_t>(ws, L.key1), *v1 = at<uint32_t>(ws, L.val1);
+    uint32_t *icnt = at<uint32_t>(ws, L.icnt), *ioff = at<uint32_t>(ws, L.ioff);
+    uint32_t *ik0 = at<uint32_t>(ws, L.ikey0), *iv0 = at<uint32_t>(ws, L.ival0);
+    uint32_t *ik1 = at<uint32_t>(ws, L.ikey1), *iv1 = at<uint32_t>(ws, L.ival1);
+    uint2 *ranges = at<uint2>(ws, L.ranges);
+    uint32_t *hist = at<uint32_t>(ws, L.hist), *dtot = at<uint32_t>(ws, L.dtot);
+    const uint64_t R = (uint64_t)p.max_records, M = (uint64_t)p.max_instances;
+
+    launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
+    launch_count(a, views, nv, geo, cnt, s);
+    launch_scan(cnt, offs, nullptr, (uint64_t)a.n, (uint64_t)a.n, blk, &st->R_total, &st->R_eff, R, &st->overflow,
+                1u, s);
+    launch_project(a, views, nv, geo, offs, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
+    const int dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s);
+    const uint32_t *sval = dres ? v1 : v0;
+    launch_gather_ntiles(sval, bin, &st->R_eff, icnt, s);
+    launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
+    launch_emit(sval, bin, ioff, views, st, ik0, iv0, s);
+    const int tres =
+        launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s);
+    const uint32_t *skey = tres ? ik1 : ik0;
+    launch_ranges(skey, st, ranges, s);
+    out.sval = sval;
+    out.ival = tres ? iv1 : iv0;
+    return GV_OK;
+}
+
+// ============================================================================ C ABI
+
+extern "C" {
+
+const char *gv_last_error(void) { return g_err.c_str(); }
+
+void gv_default_vf_params(gv_vf_params *p) {
+    if (!p) return;
+    p->sh_degree = 2;
+    p->kappa = 1.0f;
+    p->eps_T = 1e-4f;
+    p->znear = 0.2f;
+    p->lowpass = 0.3f;
+    p->cut = 9.0f;
+    p->views_per_pass = 0;
+    p->accumulate = 0;
+}
+
+void gv_default_uq_params(gv_uq_params *p) {
+    if (!p) return;
+    p->beta = 0.5f;
+    p->o0 = 0.15f;
+    p->half_logdet_Q0 = 0.0f;
+    p->half_logdet_Qc = (float)(3.0 * std::log(0.1));
+    p->eps_T = 1e-4f;
+    p->znear = 0.2f;
+    p->lowpass = 0.3f;
+    p->cut = 9.0f;
+    p->write_maps = 0;
+    p->use_graph = 0;
+}
+
+gv_status gv_create(int device, gv_context **out) {
+    if (!out) return fail(GV_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    GV_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(GV_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, ndev);
+    DeviceGuard dg(device);
+    gv_context *c = new gv_context();
+    c->device = device;
+    if (hipMalloc((void **)&c->dev_counters, 8 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&c->dev_best, 64) != hipSuccess) {
+        if (c->dev_counters) (void)hipFree(c->dev_counters);
+        delete c;
+        return fail(GV_ERR_OUT_OF_MEMORY, "cannot allocate context counters");
+    }
+    *out = c;
+    return GV_OK;
+}
+
+void gv_destroy(gv_context *ctx) {
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    if (ctx->dev_counters) (void)hipFree(ctx->dev_counters);
+    if (ctx->dev_best) (void)hipFree(ctx->dev_best);
+    if (ctx->dev_views) (void)hipFree(ctx->dev_views);
+    delete ctx;
+}
+
+size_t gv_workspace_bytes(const gv_workspace *plan) {
+    if (!plan) return 0;
+    return make_layout(*plan).total;
+}
+
+gv_status vf_build_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                                  const gv_vf_params *prm, gv_workspace *plan, void *hip_stream) {
+    if (!ctx || !prm || !plan) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_train < 0 || (n_train > 0 && !train)) return fail(GV_ERR_INVALID_ARG, "bad training views");
+    if (prm->sh_degree < 0 || prm->sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", prm->sh_degree, GV_MAX_SH_DEGREE);
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int32_t vp = prm->views_per_pass > 0 ? std::min(prm->views_per_pass, std::max(n_train, 1)) : std::max(n_train, 1);
+    std::memset(plan, 0, sizeof(*plan));
+    plan->kind = 0;
+    plan->n = g->n;
+    plan->sh_degree = prm->sh_degree;
+    plan->n_views = vp;
+    const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
+    for (int32_t v0 = 0; v0 < n_train; v0 += vp) {
+        const int32_t nv = std::min(vp, n_train - v0);
+        std::vector<ViewDev> views;
+        int64_t tiles, pixels;
+        GV_TRY(make_views(train + v0, nv, views, tiles, pixels));
+        uint64_t R, M;
+        GV_TRY(measure(ctx, g, views, geo, R, M, s));
+        plan->max_records = std::max<int64_t>(plan->max_records, (int64_t)R);
+        plan->max_instances = std::max<int64_t>(plan->max_instances, (int64_t)M);
+        plan->total_tiles = (int32_t)std::max<int64_t>(plan->total_tiles, tiles);
+        plan->total_pixels = std::max<int64_t>(plan->total_pixels, pixels);
+    }
+    if (plan->max_records > 0x7fffffffLL || plan->max_instances > 0x7fffffffLL)
+        return fail(GV_ERR_CAPACITY, "one pass needs more than 2^31 records or instances; lower views_per_pass");
+    plan->bytes = make_layout(*plan).total;
+    return GV_OK;
+}
+
+gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *cand, int32_t n_cand,
+                                  const gv_uq_params *prm, int32_t sh_degree, gv_workspace *plan, void *hip_stream) {
+    if (!ctx || !prm || !plan) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_cand < 1 || !cand) return fail(GV_ERR_INVALID_ARG, "need at least one candidate view");
+    if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", sh_degree, GV_MAX_SH_DEGREE);
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<ViewDev> views;
+    int64_t tiles, pixels;
+    GV_TRY(make_views(cand, n_cand, views, tiles, pixels));
+    uint64_t R, M;
+    GV_TRY(measure(ctx, g, views, GeomArgs{prm->znear, prm->lowpass, prm->cut}, R, M, s));
+    std::memset(plan, 0, sizeof(*plan));
+    plan->kind = 1;
+    plan->n = g->n;
+    plan->sh_degree = sh_degree;
+    plan->n_views = n_cand;
+    plan->max_records = (int64_t)R;
+    plan->max_instances = (int64_t)M;
+    plan->total_tiles = (int32_t)tiles;
+    plan->total_pixels = pixels;
+    if (plan->max_records > 0x7fffffffLL || plan->max_instances > 0x7fffffffLL)
+        return fail(GV_ERR_CAPACITY, "more than 2^31 records or instances in one call; split the views");
+    plan->bytes = make_layout(*plan).total;
+    return GV_OK;
+}
+
+gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                   const gv_vf_params *prm, void *gamma, gv_dtype gamma_dtype, const gv_workspace *plan,
+                   void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_train < 0 || (n_train > 0 && !train)) return fail(GV_ERR_INVALID_ARG, "bad training views");
+    if (prm->sh_degree < 0 || prm->sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", prm->sh_degree, GV_MAX_SH_DEGREE);
+    if (!(std::isfinite(prm->kappa) && prm->kappa >= 0.f)) return fail(GV_ERR_INVALID_ARG, "kappa must be >= 0");
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
+        return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
+    if (g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
+    if (!plan || !workspace) return fail(GV_ERR_INVALID_ARG, "NULL workspace or plan");
+    if (plan->sh_degree != prm->sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int L = prm->sh_degree;
+    const int K = (L + 1) * (L + 1);
+    float al[4] = {0, 0, 0, 0};
+    for (int l = 0; l <= L; ++l) al[l] = (float)(4.0 * M_PI * std::exp(-(double)prm->kappa) * bessel_i(l, prm->kappa));
+    const int32_t vp = prm->views_per_pass > 0 ? std::min(prm->views_per_pass, std::max(n_train, 1)) : std::max(n_train, 1);
+    const Layout Lay = make_layout(*plan);
+    const GaussArgs a = gargs(g);
+    const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
+    const float qcut = (float)(0.5 * prm->cut / std::log(2.0));
+    const bool half_out = gamma_dtype != GV_F32;
+    float *gam32 = at<float>(workspace, Lay.gam32);
+    // target of the per-pass accumulation: the FP32 output directly, or an
+    // FP32 copy that is rounded to the half output at the end
+    void *acc_target = half_out ? (void *)gam32 : gamma;
+    if (g->n == 0) return GV_OK;
+    if (n_train == 0) {
+        if (!prm->accumulate) {
+            if (half_out) launch_fill_u32((uint32_t *)gamma, ((uint64_t)g->n * K + 1) / 2, 0u, s);
+            else launch_fill_u32((uint32_t *)gamma, (uint64_t)g->n * K, 0u, s);
+        }
+        GV_HIP(hipGetLastError());
+        return GV_OK;
+    }
+    bool acc = prm->accumulate != 0;
+    if (half_out) {
+        // FP32 staging of the half output: start from it (accumulate) or from 0
+        if (acc) launch_convert(gamma, (int)gamma_dtype, gam32, 0, (uint64_t)g->n * K, s);
+        else launch_fill_u32((uint32_t *)gam32, (uint64_t)g->n * K, 0u, s);
+        acc = true;
+    }
+    for (int32_t v0 = 0; v0 < n_train; v0 += vp) {
+        const int32_t nv = std::min(vp, n_train - v0);
+        std::vector<ViewDev> &views = ctx->host_views;
+        int64_t tiles, pixels;
+        GV_TRY(make_views(train + v0, nv, views, tiles, pixels));
+        GV_TRY(plan_check(plan, workspace, 0, g->n, nv, tiles, pixels));
+        GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
+                              hipMemcpyHostToDevice, s));
+        Binned bz;
+        GV_TRY(run_binning(*plan, Lay, workspace, a, nv, tiles, geo, false, L, nullptr, 0, 0.f, s, bz));
+        Status *st = at<Status>(workspace, Lay.status);
+        float *accT = at<float>(workspace, Lay.accT);
+        uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
+        launch_fill_dev_u32(reinterpret_cast<uint32_t *>(accT), &st->R_eff, 1, 0u, s);
+        launch_fill_dev_u32(accC, &st->R_eff, 1, 0u, s);
+        launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                          bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC, s);
+        launch_vf_accum(a, at<ViewDev>(workspace, Lay.views), at<uint32_t>(workspace, Lay.offs),
+                        at<Bin>(workspace, Lay.bin), accT, accC, st, L, al, acc_target,
+                        half_out ? 0 : (int)gamma_dtype, acc, s);
+        GV_HIP(hipGetLastError());
+        if (v0 + vp < n_train) {
+            // the next pass reuses the workspace; its status must be read now
+            // to report an overflow of this pass
+            Status h;
+            GV_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+            GV_HIP(hipStreamSynchronize(s));
+            if (h.overflow) return fail(GV_ERR_CAPACITY, "workspace too small for views %d..%d", v0, v0 + nv - 1);
+        }
+        acc = true;
+    }
+    if (half_out) launch_convert(gam32, 0, gamma, (int)gamma_dtype, (uint64_t)g->n * K, s);
+    GV_HIP(hipGetLastError());
+    return GV_OK;
+}
+
+gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                         const gv_uq_params *prm, float *scores, float *maps, const gv_workspace *plan,
+                         void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_cand < 1 || !cand) return fail(GV_ERR_INVALID_ARG, "need at least one candidate view");
+    if (!scores) return fail(GV_ERR_INVALID_ARG, "scores is NULL");
+    if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", sh_degree, GV_MAX_SH_DEGREE);
+    if (n_train < 0) return fail(GV_ERR_INVALID_ARG, "n_train < 0");
+    if (n_train > 0 && g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
+    if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
+        return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    if (!(prm->beta >= 0.f && prm->beta <= 1.f && prm->o0 >= 0.f && prm->o0 <= 1.f))
+        return fail(GV_ERR_INVALID_ARG, "beta and o0 must lie in [0, 1]");
+    if (!std::isfinite(prm->half_logdet_Q0) || !std::isfinite(prm->half_logdet_Qc))
+        return fail(GV_ERR_INVALID_ARG, "non-finite covariance log-determinants");
+    if (prm->write_maps && !maps) return fail(GV_ERR_INVALID_ARG, "write_maps set but maps is NULL");
+    if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<ViewDev> &views = ctx->host_views;
+    int64_t tiles, pixels;
+    GV_TRY(make_views(cand, n_cand, views, tiles, pixels));
+    GV_TRY(plan_check(plan, workspace, 1, g->n, n_cand, tiles, pixels));
+    const Layout Lay = make_layout(*plan);
+    GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
+                          hipMemcpyHostToDevice, s));
+    const GaussArgs a = gargs(g);
+    const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
+    Binned bz;
+    GV_TRY(run_binning(*plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma, (int)gamma_dtype,
+                       (float)n_train, s, bz));
+    const double c3 = 1.5 * std::log(2.0 * M_PI * M_E);
+    UqArgs u;
+    u.beta = prm->beta;
+    u.o0 = prm->o0;
+    u.cQc = (float)(prm->half_logdet_Qc + c3);
+    u.cQ0 = (float)(prm->half_logdet_Q0 + c3);
+    u.eps_T = prm->eps_T;
+    u.qcut = (float)(0.5 * prm->cut / std::log(2.0));
+    float *tpart = at<float>(workspace, Lay.tpart);
+    launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                     bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, prm->write_maps ? maps : nullptr, s);
+    launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
+    GV_HIP(hipGetLastError());
+    return GV_OK;
+}
+
+gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace, int64_t out[3],
+                             void *hip_stream) {
+    if (!ctx || !plan || !workspace) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Layout Lay = make_layout(*plan);
+    Status h;
+    GV_HIP(hipMemcpyAsync(&h, static_cast<const char *>(workspace) + Lay.status, sizeof(h), hipMemcpyDeviceToHost, s));
+    GV_HIP(hipStreamSynchronize(s));
+    if (out) {
+        out[0] = (int64_t)h.R_total;
+        out[1] = (int64_t)h.M_total;
+        out[2] = (int64_t)h.overflow;
+    }
+    if (h.overflow) return fail(GV_ERR_CAPACITY, "workspace capacity exceeded (records %llu, instances %llu)",
+                                h.R_total, h.M_total);
+    return GV_OK;
+}
+
+gv_status select_next_view(gv_context *ctx, const float *scores, int32_t n, int32_t *best, void *hip_stream) {
+    if (!ctx || !scores || !best) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1) return fail(GV_ERR_INVALID_ARG, "n must be >= 1");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    launch_argmax(scores, n, ctx->dev_best, s);
+    GV_HIP(hipGetLastError());
+    int32_t h = -1;
+    GV_HIP(hipMemcpyAsync(&h, ctx->dev_best, sizeof(h), hipMemcpyDeviceToHost, s));
+    GV_HIP(hipStreamSynchronize(s));
+    *best = h;
+    return GV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// gv_device.hpp -- data layouts and device helpers shared by the HIP kernels
+// of the visibility-field path (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gv {
+
+// Raster tile: 16x16 pixels, one 256-thread workgroup (4 waves of 64), one
+// pixel per lane.  Each wave covers a 16x4 strip of the tile.
+constexpr int TILE = 16;
+constexpr int TILE_SHIFT = 4;
+constexpr int WG = 256;
+constexpr int WAVES = WG / 64;
+
+// LSD radix sort: 8-bit digits, a fixed number of blocks per pass.
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int RADIX_BLOCKS = 1024;
+
+// Device exclusive scan: elements per block.
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_BLOCK = WG * SCAN_ITEMS;
+
+constexpr int MAX_K = 16;  // (L+1)^2 for L <= 3
+
+// One camera as the kernels see it.  The projection reads it with uniform
+// (scalar) loads, the raster with one lookup per workgroup.
+struct ViewDev {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float C[3];          // camera centre in world coordinates
+    int32_t w, h;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_base;   // first global tile id of this view
+    int32_t pad0;
+    int64_t pix_base;    // first pixel of this view in the packed maps
+};
+static_assert(sizeof(ViewDev) == 112, "ViewDev layout");
+
+// One (Gaussian, view) record after projection: 32 bytes, gathered by the
+// raster through the sorted tile lists.
+//   uv        anchor pixel of the projected centre, int16 x | int16 y << 16
+//   fx, fy    projected centre minus the anchor (|f| <= 0.5 unless clamped)
+//   l11..l22  lower Cholesky factor of the 2D conic, times sqrt(log2(e)/2),
+//             so that (l11 dx + l21 dy)^2 + (l22 dy)^2 = log2(e) m / 2
+//   o         opacity
+//   v         queried visibility (query path), unused by the build
+struct Rec {
+    int32_t uv;
+    float fx, fy;
+    float l11, l21, l22;
+    float o;
+    float v;
+};
+static_assert(sizeof(Rec) == 32, "Rec layout");
+
+// Tile rectangle [x0, x1) x [y0, y1) of a record and its tile count.
+struct Bin {
+    int32_t view;
+    uint32_t x0y0;
+    uint32_t x1y1;
+    uint32_t ntiles;
+};
+
+// Status words at the start of every workspace.
+struct Status {
+    unsigned long long R_total;   // records produced by culling
+    unsigned long long M_total;   // instances produced by binning
+    uint32_t R_eff;               // min(R_total, capacity)
+    uint32_t M_eff;
+    uint32_t overflow;            // bit 0 records, bit 1 instances
+    int32_t best;                 // argmax scratch
+    unsigned long long measure[4];
+};
+
+constexpr uint32_t DEAD_KEY = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------- wave helpers
+
+template <int CTRL, int ROWM = 0xF, int BANKM = 0xF>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWM, BANKM, true));
+}
+
+// Sum of x over the 64 lanes of the wave; every lane must be active.  The
+// total lands in lane 63 and is broadcast through a scalar register.
+__device__ __forceinline__ float wave_sum(float x) {
+    x += dpp_f<0x111>(x);                 // row_shr:1
+    x += dpp_f<0x112>(x);                 // row_shr:2
+    x += dpp_f<0x114>(x);                 // row_shr:4
+    x += dpp_f<0x118>(x);                 // row_shr:8
+    x += dpp_f<0x142, 0xA>(x);            // row_bcast:15 into rows 1, 3
+    x += dpp_f<0x143, 0xC>(x);            // row_bcast:31 into rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ---------------------------------------------------------------- real SH, L <= 3
+
+// Real spherical harmonics of a unit direction (x, y, z), index l^2 + l + m,
+// in the basis built from the complex Y_l^m with the Condon-Shortley phase:
+// sqrt(2) (-1)^m Im Y_l^|m| for m < 0, Y_l^0, sqrt(2) (-1)^m Re Y_l^m for m > 0.
+template <int L>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float *Y) {
+    Y[0] = 0.28209479177387814f;
+    if (L >= 1) {
+        Y[1] = 0.4886025119029199f * y;
+        Y[2] = 0.4886025119029199f * z;
+        Y[3] = 0.4886025119029199f * x;
+    }
+    if (L >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484305920792f * x * y;
+        Y[5] = 1.0925484305920792f * y * z;
+        Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+        Y[7] = 1.0925484305920792f * x * z;
+        Y[8] = 0.5462742152960396f * (xx - yy);
+        if (L >= 3) {
+            Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+            Y[10] = 2.890611442640554f * x * y * z;
+            Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+            Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+            Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+            Y[14] = 1.445305721320277f * z * (xx - yy);
+            Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- storage types
+
+__device__ __forceinline__ float load_f(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float load_f(const _Float16 *p, int64_t i) { return (float)p[i]; }
+__device__ __forceinline__ float load_f(const uint16_t *p, int64_t i) {   // bfloat16 bits
+    return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+
+}  // namespace gv

@@ -1,0 +1,67 @@
+// gv_launch.hpp -- host-side launchers of the HIP kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gv_device.hpp"
+
+namespace gv {
+
+struct GaussArgs {
+    int64_t n;
+    int64_t n_virtual;
+    int dtype;               // 0 f32, 1 f16, 2 bf16
+    const void *means, *scales, *quats, *opacity;
+    const float *anchors;
+    int32_t anchor_block;
+};
+
+struct GeomArgs {
+    float znear, lowpass, cut;
+};
+
+// Per-pixel constants of the uncertainty rasterisation (Alg. 6).
+struct UqArgs {
+    float beta, o0;
+    float cQc;       // 1/2 log|Q_c| + 3/2 log(2 pi e)
+    float cQ0;       // 1/2 log|Q0| + 3/2 log(2 pi e)
+    float eps_T;
+    float qcut;      // log2(e) cut / 2, the overlap threshold on the scaled quadratic form
+};
+
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
+void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s);
+
+void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, hipStream_t s);
+void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
+                    hipStream_t s);
+void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
+                    const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
+                    float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s);
+
+size_t scan_blk_count(uint64_t n_cap);
+void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
+                 unsigned long long *blk, unsigned long long *total, uint32_t *eff, uint64_t tcap,
+                 uint32_t *overflow, uint32_t flag_bit, hipStream_t s);
+int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
+                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s);
+void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
+void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
+void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const ViewDev *views, const Status *st,
+                 uint32_t *ikey, uint32_t *ival, hipStream_t s);
+void launch_ranges(const uint32_t *key, const Status *st, uint2 *ranges, hipStream_t s);
+
+void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s);
+void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, hipStream_t s);
+void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
+                   hipStream_t s);
+void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);
+void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+                     const float *acc_T, const uint32_t *acc_c, const Status *st, int L, const float *al,
+                     void *gamma, int gamma_dtype, bool accumulate, hipStream_t s);
+
+}  // namespace gv

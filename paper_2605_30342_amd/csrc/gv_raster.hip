@@ -1,0 +1,408 @@
+// gv_raster.hip -- per-tile front-to-back blending for gfx950.
+//
+//   k_raster_vis  single-view particle visibility (Alg. 2): every pixel walks
+//                 its tile's depth-sorted list; each Gaussian that overlaps the
+//                 pixel (Mahalanobis^2 <= cut) and is reached before T < eps_T
+//                 receives the pixel's transmittance and a count.  The 64
+//                 contributions of a wave are summed with DPP and the four
+//                 waves' sums combined in LDS, so each (tile, Gaussian) pair
+//                 costs one pair of global atomics.
+//   k_raster_uq   uncertainty rasterisation (Alg. 6): compensated opacity
+//                 (eq. alpha_comp), per-pixel entropy bound (eq. huber) and
+//                 per-tile partial sums of the score.
+//   k_vf_accum    SH accumulation (Alg. 3): gamma_k += (sum T / count) a_l Y_k(d).
+//
+// Workgroup = one 16x16 tile, 256 threads, one pixel per lane.  The tile's
+// list is staged through LDS in batches of 256 records; a batch loop stops
+// as soon as every pixel of the tile has terminated.
+#include "gv_device.hpp"
+#include "gv_launch.hpp"
+
+namespace gv {
+
+constexpr float LN2 = 0.6931471805599453f;
+
+__device__ __forceinline__ int find_view(const ViewDev *__restrict__ views, int nv, int gt) {
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= gt) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// Record -> tile-local form: centre relative to the tile origin, computed from
+// the integer anchor and the FP32 fraction so that it keeps full precision.
+__device__ __forceinline__ void local_centre(const Rec &R, int ox, int oy, float &ux, float &uy) {
+    const int ax = (int)(int16_t)(R.uv & 0xFFFF);
+    const int ay = R.uv >> 16;
+    ux = (float)(ax - ox) + R.fx;
+    uy = (float)(ay - oy) + R.fy;
+}
+
+// ---------------------------------------------------------------- VF CONST raster (Alg. 2)
+
+__global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
+                                                   const uint2 *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
+                                                   float eps_T, float qcut, float *__restrict__ acc_T,
+                                                   uint32_t *__restrict__ acc_c) {
+    __shared__ float4 sA[WG];          // ux, uy, l11, l21
+    __shared__ float2 sB[WG];          // l22, o
+    __shared__ uint32_t sR[WG];        // record index
+    __shared__ float part[WAVES][WG];
+    __shared__ uint32_t cpart[WAVES][WG];
+
+    const int gt = blockIdx.x;
+    const int vi = find_view(views, nv, gt);
+    const ViewDev &V = views[vi];
+    const int lt = gt - V.tile_base;
+    const int ox = (lt % V.tiles_x) * TILE, oy = (lt / V.tiles_x) * TILE;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lx = t & (TILE - 1), ly = t >> TILE_SHIFT;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    bool done = (ox + lx >= V.w) || (oy + ly >= V.h);
+    float T = 1.0f;
+    const uint2 rg = ranges[gt];
+
+    for (uint32_t b = rg.x; b < rg.y; b += WG) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t idx = b + t;
+        if (idx < rg.y) {
+            const uint32_t r = ival[idx];
+            const Rec R = rec[r];
+            float ux, uy;
+            local_centre(R, ox, oy, ux, uy);
+            sA[t] = make_float4(ux, uy, R.l11, R.l21);
+            sB[t] = make_float2(R.l22, R.o);
+            sR[t] = r;
+        }
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) {
+            part[ww][t] = 0.0f;
+            cpart[ww][t] = 0u;
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)WG, rg.y - b);
+        for (int j = 0; j < cnt; ++j) {
+            const float4 A = sA[j];
+            const float2 B = sB[j];
+            const float dx = px - A.x, dy = py - A.y;
+            const float w1 = fmaf(A.z, dx, A.w * dy);
+            const float w2 = B.x * dy;
+            const float p = fmaf(w1, w1, w2 * w2);
+            const bool hit = (p <= qcut) && !done;
+            const unsigned long long bal = __ballot(hit);
+            if (bal) {
+                const float s = wave_sum(hit ? T : 0.0f);
+                if (lane == 0) {
+                    part[w][j] = s;
+                    cpart[w][j] = (uint32_t)__popcll(bal);
+                }
+                if (hit) {
+                    const float alpha = B.y * fast_exp2(-p);
+                    T = fmaf(-T, alpha, T);
+                    done = T < eps_T;
+                }
+            }
+        }
+        __syncthreads();
+        if (t < cnt) {
+            float s = 0.0f;
+            uint32_t c = 0;
+#pragma unroll
+            for (int ww = 0; ww < WAVES; ++ww) {
+                s += part[ww][t];
+                c += cpart[ww][t];
+            }
+            if (c) {
+                atomicAdd(&acc_T[sR[t]], s);
+                atomicAdd(&acc_c[sR[t]], c);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
+
+template <bool MAPS>
+__global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
+                                                  const uint2 *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
+                                                  UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps) {
+    __shared__ float4 sA[WG];          // ux, uy, l11, l21
+    __shared__ float4 sB[WG];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
+    __shared__ float red[WAVES];
+
+    const int gt = blockIdx.x;
+    const int vi = find_view(views, nv, gt);
+    const ViewDev &V = views[vi];
+    const int lt = gt - V.tile_base;
+    const int ox = (lt % V.tiles_x) * TILE, oy = (lt / V.tiles_x) * TILE;
+    const int t = threadIdx.x, w = t >> 6;
+    const int lx = t & (TILE - 1), ly = t >> TILE_SHIFT;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const bool inside = (ox + lx < V.w) && (oy + ly < V.h);
+    bool done = !inside;
+    float T = 1.0f, H = 0.0f, w0 = 0.0f;
+    const uint2 rg = ranges[gt];
+    const float ob = u.o0 * (1.0f - u.beta);
+
+    for (uint32_t b = rg.x; b < rg.y; b += WG) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t idx = b + t;
+        if (idx < rg.y) {
+            const Rec R = rec[ival[idx]];
+            float ux, uy;
+            local_centre(R, ox, oy, ux, uy);
+            const float v = R.v;
+            sA[t] = make_float4(ux, uy, R.l11, R.l21);
+            sB[t] = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)WG, rg.y - b);
+        for (int j = 0; j < cnt; ++j) {
+            const float4 A = sA[j];
+            const float4 B = sB[j];
+            const float dx = px - A.x, dy = py - A.y;
+            const float w1 = fmaf(A.z, dx, A.w * dy);
+            const float w2 = B.x * dy;
+            const float p = fmaf(w1, w1, w2 * w2);
+            if (p <= u.qcut && !done) {
+                const float as = fmaf(B.y, fast_exp2(-p), B.z);    // alpha*
+                const float wt = as * T;                           // w*
+                const float x = wt * B.w;                          // w* v
+                const float lg = fast_log2(fmaxf(x, 1e-30f));
+                H = fmaf(x, fmaf(-LN2, lg, u.cQc), H);
+                w0 += wt - x;                                      // w* (1 - v)
+                T -= wt;                                           // T (1 - alpha*)
+                done = T < u.eps_T;
+            }
+        }
+        __syncthreads();
+    }
+    if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
+    if (!inside) H = 0.0f;
+    if (MAPS && inside) maps[V.pix_base + (int64_t)(oy + ly) * V.w + (ox + lx)] = H;
+    const float s = wave_sum(H);
+    if ((t & 63) == 0) red[w] = s;
+    __syncthreads();
+    if (t == 0) {
+        float tot = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) tot += red[ww];
+        tile_part[gt] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- scores and argmax
+
+// S_v = sum of the view's tile partials, accumulated in FP64.
+__global__ __launch_bounds__(WG) void k_scores(const ViewDev *__restrict__ views, const float *__restrict__ tile_part,
+                                               const Status *__restrict__ st, float *__restrict__ scores) {
+    const ViewDev &V = views[blockIdx.x];
+    const int n = V.tiles_x * V.tiles_y;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += WG) s += (double)tile_part[V.tile_base + i];
+    __shared__ double red[WG];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = WG / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scores[blockIdx.x] = st->overflow ? __int_as_float(0x7fc00000) : (float)red[0];
+}
+
+__device__ __forceinline__ bool better(float a, int ia, float b, int ib) {
+    if (ia < 0) return false;
+    if (ib < 0) return true;
+    return a > b || (a == b && ia < ib);
+}
+
+__global__ __launch_bounds__(1024) void k_argmax(const float *__restrict__ scores, int n, int32_t *__restrict__ best) {
+    float bv = 0.0f;
+    int bi = -1;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const float v = scores[i];
+        if (v != v) continue;
+        if (better(v, i, bv, bi)) { bv = v; bi = i; }
+    }
+    __shared__ float sv[1024];
+    __shared__ int si[1024];
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            if (better(sv[threadIdx.x + off], si[threadIdx.x + off], sv[threadIdx.x], si[threadIdx.x])) {
+                sv[threadIdx.x] = sv[threadIdx.x + off];
+                si[threadIdx.x] = si[threadIdx.x + off];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *best = si[0];
+}
+
+// ---------------------------------------------------------------- VF accumulation (Alg. 3)
+
+struct ALs { float a[4]; };
+
+__device__ __forceinline__ void store_f(float *p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void store_f(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
+__device__ __forceinline__ void store_f(uint16_t *p, int64_t i, float v) {   // bfloat16, round to nearest even
+    uint32_t b = __float_as_uint(v);
+    if ((b & 0x7f800000u) != 0x7f800000u) b += 0x7fffu + ((b >> 16) & 1u);
+    p[i] = (uint16_t)(b >> 16);
+}
+
+template <typename TG, typename TGam, int L>
+__global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__restrict__ views,
+                                                 const uint32_t *__restrict__ offs, const Bin *__restrict__ bin,
+                                                 const float *__restrict__ acc_T, const uint32_t *__restrict__ acc_c,
+                                                 const Status *__restrict__ st, ALs al, TGam *__restrict__ gamma,
+                                                 bool accumulate) {
+    constexpr int K = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= a.n) return;
+    if (st->overflow) return;
+    float m[3];
+    {
+        const TG *mp = (const TG *)a.means;
+        if constexpr (sizeof(TG) == 4) {
+            m[0] = load_f(mp, 3 * g); m[1] = load_f(mp, 3 * g + 1); m[2] = load_f(mp, 3 * g + 2);
+        } else {
+            const int64_t blk = g / (a.anchor_block > 0 ? a.anchor_block : 1);
+            m[0] = a.anchors[3 * blk] + load_f(mp, 3 * g);
+            m[1] = a.anchors[3 * blk + 1] + load_f(mp, 3 * g + 1);
+            m[2] = a.anchors[3 * blk + 2] + load_f(mp, 3 * g + 2);
+        }
+    }
+    float acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = accumulate ? load_f((const TGam *)gamma, (int64_t)k * a.n + g) : 0.0f;
+    const uint32_t r0 = offs[g], r1 = min(offs[g + 1], st->R_eff);
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t c = acc_c[r];
+        if (c == 0) continue;
+        const float v = acc_T[r] / (float)c;
+        const ViewDev &V = views[bin[r].view];
+        float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+        const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+        if (!(nrm > 0.0f)) continue;
+        const float inv = 1.0f / nrm;
+        dx *= inv; dy *= inv; dz *= inv;
+        float Y[K];
+        sh_eval<L>(dx, dy, dz, Y);
+#pragma unroll
+        for (int l = 0; l <= L; ++l) {
+            const float va = v * al.a[l];
+#pragma unroll
+            for (int k = l * l; k < (l + 1) * (l + 1); ++k) acc[k] = fmaf(va, Y[k], acc[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) store_f(gamma, (int64_t)k * a.n + g, acc[k]);
+}
+
+// ---------------------------------------------------------------- dtype conversion
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(WG) void k_convert(const TS *__restrict__ src, TD *__restrict__ dst, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
+        store_f(dst, (int64_t)i, load_f(src, (int64_t)i));
+}
+
+template <typename TS>
+static void convert_to(const TS *src, void *dst, int ddt, uint64_t n, hipStream_t s) {
+    const dim3 grid(4096), block(WG);
+    switch (ddt) {
+    case 0: hipLaunchKernelGGL((k_convert<TS, float>), grid, block, 0, s, src, (float *)dst, n); break;
+    case 1: hipLaunchKernelGGL((k_convert<TS, _Float16>), grid, block, 0, s, src, (_Float16 *)dst, n); break;
+    default: hipLaunchKernelGGL((k_convert<TS, uint16_t>), grid, block, 0, s, src, (uint16_t *)dst, n); break;
+    }
+}
+
+void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s) {
+    if (n == 0) return;
+    switch (sdt) {
+    case 0: convert_to((const float *)src, dst, ddt, n, s); break;
+    case 1: convert_to((const _Float16 *)src, dst, ddt, n, s); break;
+    default: convert_to((const uint16_t *)src, dst, ddt, n, s); break;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
+    if (total_tiles <= 0) return;
+    hipLaunchKernelGGL(k_raster_vis, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
+                       acc_T, acc_c);
+}
+
+void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, hipStream_t s) {
+    if (total_tiles <= 0) return;
+    if (maps)
+        hipLaunchKernelGGL(k_raster_uq<true>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, u,
+                           tile_part, maps);
+    else
+        hipLaunchKernelGGL(k_raster_uq<false>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, u,
+                           tile_part, maps);
+}
+
+void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
+                   hipStream_t s) {
+    if (nv <= 0) return;
+    hipLaunchKernelGGL(k_scores, dim3(nv), dim3(WG), 0, s, views, tile_part, st, scores);
+}
+
+void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s) {
+    hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, s, scores, n, best);
+}
+
+template <typename TG, typename TGam>
+static void accum_L(int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+                    const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
+                    bool accumulate, hipStream_t s) {
+    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    TGam *gm = (TGam *)gamma;
+    switch (L) {
+    case 0: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 0>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
+    case 1: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 1>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
+    case 2: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 2>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
+    default: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 3>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
+    }
+}
+
+template <typename TG>
+static void accum_gam(int gdt, int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+                      const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
+                      bool accumulate, hipStream_t s) {
+    switch (gdt) {
+    case 0: accum_L<TG, float>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    case 1: accum_L<TG, _Float16>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    default: accum_L<TG, uint16_t>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    }
+}
+
+void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+                     const float *acc_T, const uint32_t *acc_c, const Status *st, int L, const float *al_in,
+                     void *gamma, int gamma_dtype, bool accumulate, hipStream_t s) {
+    if (a.n == 0) return;
+    ALs al;
+    for (int l = 0; l < 4; ++l) al.a[l] = l <= L ? al_in[l] : 0.0f;
+    switch (a.dtype) {
+    case 0: accum_gam<float>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    case 1: accum_gam<_Float16>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    default: accum_gam<uint16_t>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    }
+}
+
+}  // namespace gv

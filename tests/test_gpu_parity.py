@@ -1,0 +1,314 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (floating point, FP32 kernels vs FP64 oracle):
+  maps     |a - b| <= 1e-4 (|b| + max|b_map|) on pixels the oracle does not
+           flag as near ties (boundary pairs, transmittance at eps_T, equal
+           depths); the flagged fraction is asserted small;
+  gamma    |d gamma_gk| <= 1e-4 ||gamma_g||_inf + 2 allow_gk, where allow is the
+           oracle's first-order bound on the effect of near-tie decisions;
+  scores   |d S_v| <= 1e-4 sum_px |H| + the GPU-vs-oracle difference summed
+           over flagged pixels;
+  argmax   bit-exact, or inside the oracle's near-tie set when scores lie
+           within 2e-4 max sum|H| of the best.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_30342_amd import scenes
+from paper_2605_30342_amd.scenes import Cameras, Scene
+from tests._gpu import compare_gamma, compare_maps, gpu_build, gpu_query, oracle_params, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_30342_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _dsc(scene, dtype="f32"):
+    from paper_2605_30342_amd.api import DeviceScene
+    return DeviceScene(scene, dtype=dtype)
+
+
+def _check_scores(s_gpu, ora, mp_gpu):
+    ref = ora["scores"]
+    off = 0
+    for v, m in enumerate(ora["maps"]):
+        n = m.size
+        absH = np.abs(ora["maps_flat"][off:off + n]).sum()
+        f = ora["flags_flat"][off:off + n]
+        flagged = np.abs(mp_gpu[off:off + n] - ora["maps_flat"][off:off + n])[f].sum() if mp_gpu is not None else 0.0
+        assert abs(s_gpu[v] - ref[v]) <= 1e-4 * absH + flagged + 1e-6, (v, s_gpu[v], ref[v])
+        off += n
+
+
+def _check_argmax(ctx, s_gpu, ora):
+    import torch
+    best = ctx.select_next_view(torch.from_numpy(s_gpu.astype(np.float32)).cuda())
+    absH = []
+    off = 0
+    for m in ora["maps"]:
+        absH.append(np.abs(ora["maps_flat"][off:off + m.size]).sum())
+        off += m.size
+    near = oracle.near_tie_set(ora["scores"], absH)
+    if len(near) == 1:
+        assert best == oracle.argmax(ora["scores"])
+    else:
+        assert best in near
+
+
+# ---------------------------------------------------------------- select_next_view
+
+def test_select_next_view_ties_and_nan(ctx):
+    import torch
+    say("case: select_next_view small arrays")
+    cases = [[1.0, 3.0, 3.0, 2.0], [float("nan"), -1.0, -1.0], [5.0], [0.0] * 7 + [1e-30],
+             list(np.random.default_rng(3).standard_normal(3000))]
+    for c in cases:
+        s = torch.tensor(c, dtype=torch.float32, device="cuda")
+        assert ctx.select_next_view(s) == oracle.argmax(np.asarray(c, np.float32).astype(np.float64))
+    s = torch.tensor([float("nan")] * 4, dtype=torch.float32, device="cuda")
+    assert ctx.select_next_view(s) == -1
+
+
+# ---------------------------------------------------------------- tiny workload
+
+@pytest.fixture(scope="module")
+def tiny():
+    return scenes.workload("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_ref(tiny):
+    prm = oracle_params()
+    b = oracle.vf_build(tiny.scene, tiny.train, 2, prm)
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(tiny.scene, g32, 2, tiny.train.n, tiny.cand, prm)
+    return b, g32, q
+
+
+def test_build_tiny_matches_oracle(ctx, tiny, tiny_ref):
+    say("case: vf_build tiny 2000 Gaussians, 8 views 128x128, L=2")
+    b, _, _ = tiny_ref
+    g = gpu_build(ctx, _dsc(tiny.scene), tiny.train, 2)
+    worst, frac = compare_gamma(g, b)
+    say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
+    assert worst <= 1.0
+    assert frac < 0.05
+
+
+def test_query_tiny_matches_oracle(ctx, tiny, tiny_ref):
+    say("case: vf_query_views tiny, 4 views 128x128")
+    _, g32, q = tiny_ref
+    s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, tiny.train.n, tiny.cand)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
+    assert worst <= 1.0
+    assert flagged < 0.01
+    _check_scores(s, q, mp)
+    _check_argmax(ctx, s, q)
+
+
+def test_build_then_query_end_to_end(ctx, tiny):
+    say("case: GPU build -> GPU query, tiny")
+    prm = oracle_params()
+    dsc = _dsc(tiny.scene)
+    g = gpu_build(ctx, dsc, tiny.train, 2)
+    s, mp, _ = gpu_query(ctx, dsc, g, 2, tiny.train.n, tiny.cand)
+    q = oracle.vf_query(tiny.scene, g.astype(np.float32).astype(np.float64), 2, tiny.train.n, tiny.cand, prm)
+    worst, _ = compare_maps(mp, q)
+    assert worst <= 1.0
+
+
+def test_build_multi_pass_equals_single_pass(ctx, tiny, tiny_ref):
+    say("case: vf_build views_per_pass=3 vs one pass")
+    b, _, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    g1 = gpu_build(ctx, dsc, tiny.train, 2)
+    g3 = gpu_build(ctx, dsc, tiny.train, 2, views_per_pass=3)
+    scale = np.abs(g1).max(1, keepdims=True) + 1e-30
+    assert np.all(np.abs(g3 - g1) <= 1e-5 * scale)
+    worst, _ = compare_gamma(g3, b)
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("L", [0, 1, 3])
+def test_build_and_query_other_degrees(ctx, tiny, L):
+    say(f"case: degree L={L}")
+    prm = oracle_params()
+    sc = scenes.subset_scene(tiny.scene, np.arange(800))
+    b = oracle.vf_build(sc, tiny.train, L, prm)
+    g = gpu_build(ctx, _dsc(sc), tiny.train, L)
+    assert compare_gamma(g, b)[0] <= 1.0
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, L, tiny.train.n, tiny.cand.subset([0, 1]), prm)
+    s, mp, _ = gpu_query(ctx, _dsc(sc), g32, L, tiny.train.n, tiny.cand.subset([0, 1]))
+    assert compare_maps(mp, q)[0] <= 1.0
+
+
+def test_kappa_zero_isotropic_on_gpu(ctx, tiny):
+    say("case: kappa = 0 build")
+    prm = oracle_params(kappa=0.0)
+    sc = scenes.subset_scene(tiny.scene, np.arange(600))
+    b = oracle.vf_build(sc, tiny.train, 2, prm)
+    g = gpu_build(ctx, _dsc(sc), tiny.train, 2, kappa=0.0)
+    assert np.all(g[:, 1:] == 0.0)
+    assert compare_gamma(g, b)[0] <= 1.0
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_ragged_and_mixed_resolutions_in_one_call(ctx, tiny, tiny_ref):
+    say("case: ragged/mixed resolutions 37x23, 1x1, 128x96, 200x17, 16x16")
+    _, g32, _ = tiny_ref
+    prm = oracle_params()
+    C = tiny.cand.centers[:1].repeat(5, 0)
+    sizes = [(37, 23), (1, 1), (128, 96), (200, 17), (16, 16)]
+    cams = Cameras.concat([scenes.make_cameras(C[i:i + 1], np.zeros((1, 3)), w, h, 60.0)
+                           for i, (w, h) in enumerate(sizes)])
+    q = oracle.vf_query(tiny.scene, g32, 2, tiny.train.n, cams, prm)
+    s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, tiny.train.n, cams)
+    assert compare_maps(mp, q)[0] <= 1.0
+    _check_scores(s, q, mp)
+    bo = oracle.vf_build(tiny.scene, cams, 2, prm)
+    bg = gpu_build(ctx, _dsc(tiny.scene), cams, 2)
+    assert compare_gamma(bg, bo)[0] <= 1.0
+
+
+def test_no_training_views_means_invisible(ctx, tiny, tiny_ref):
+    say("case: n_train = 0")
+    _, g32, _ = tiny_ref
+    prm = oracle_params()
+    cams = tiny.cand.subset([0])
+    q = oracle.vf_query(tiny.scene, g32, 2, 0, cams, prm)
+    s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, 0, cams)
+    assert compare_maps(mp, q)[0] <= 1.0
+
+
+def test_virtual_particles_query_zero(ctx, tiny, tiny_ref):
+    say("case: virtual particle tail")
+    _, g32, _ = tiny_ref
+    prm = oracle_params()
+    sc = Scene(tiny.scene.means, tiny.scene.scales, tiny.scene.quats, tiny.scene.opacity, n_virtual=300)
+    cams = tiny.cand.subset([2])
+    q = oracle.vf_query(sc, g32, 2, tiny.train.n, cams, prm)
+    s, mp, _ = gpu_query(ctx, _dsc(sc), g32, 2, tiny.train.n, cams)
+    assert compare_maps(mp, q)[0] <= 1.0
+
+
+def test_everything_behind_camera_and_empty_scene(ctx, tiny, tiny_ref):
+    say("case: all Gaussians behind the camera; empty scene")
+    _, g32, _ = tiny_ref
+    cams = scenes.make_cameras([[3.0, 0, 0]], [[6.0, 0.5, 0.2]], 64, 48, 60.0)   # looks away from the cloud
+    s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, tiny.train.n, cams)
+    assert np.all(mp == 0.0) and s[0] == 0.0
+    g = gpu_build(ctx, _dsc(tiny.scene), cams, 2)
+    assert np.all(g == 0.0)
+    empty = scenes.subset_scene(tiny.scene, np.arange(0))
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd.api import DeviceScene
+    d = DeviceScene(empty)
+    prm = _lib.default_uq_params()
+    ws = ctx.query_workspace(d, tiny.cand, prm, 2)
+    sc, mp2 = ctx.vf_query_views(d, torch.zeros((9, 0), device="cuda"), 2, 3, tiny.cand, prm, ws, want_maps=True)
+    torch.cuda.synchronize()
+    assert torch.all(sc == 0) and torch.all(mp2 == 0)
+
+
+def test_invalid_arguments_are_rejected(ctx, tiny):
+    say("case: argument validation")
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd._lib import GvError
+    dsc = _dsc(tiny.scene)
+    with pytest.raises(GvError):
+        ctx.vf_build(dsc, tiny.train, 4, _lib.default_vf_params(sh_degree=4))
+    bad = Cameras(tiny.cand.R[:1].copy(), tiny.cand.t[:1].copy(), tiny.cand.K[:1].copy(),
+                  np.array([[0, 10]], np.int32))
+    with pytest.raises(GvError):
+        ctx.query_workspace(dsc, bad, _lib.default_uq_params(), 2)
+    prm = _lib.default_uq_params()
+    ws = ctx.query_workspace(dsc, tiny.cand.subset([0]), prm, 2)
+    g = torch.zeros((9, tiny.scene.n), device="cuda")
+    with pytest.raises(GvError):   # plan made for 1 view, called with 4
+        ctx.vf_query_views(dsc, g, 2, 8, tiny.cand, prm, ws)
+
+
+def test_capacity_overflow_is_reported(ctx, tiny, tiny_ref):
+    say("case: workspace too small -> overflow flag, NaN scores, no fault")
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    prm = _lib.default_uq_params()
+    ws = ctx.query_workspace(dsc, tiny.cand, prm, 2)
+    ws.plan.max_instances = max(1, ws.plan.max_instances // 3)
+    ws.plan.bytes = ctx.L.gv_workspace_bytes(__import__("ctypes").byref(ws.plan))
+    g = torch.from_numpy(g32.T.astype(np.float32).copy()).cuda()
+    s, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws)
+    st, counts = ctx.check_workspace(ws)
+    assert st == _lib.GV_ERR_CAPACITY and counts[2] != 0
+    assert torch.all(torch.isnan(s))
+
+
+# ---------------------------------------------------------------- room scenes
+
+@pytest.fixture(scope="module")
+def room_small():
+    return scenes.workload("room", scale=0.1)
+
+
+def test_room_subset_build_and_query(ctx, room_small):
+    say("case: room scene 20k Gaussians, L=3, 3 training views 800x800, 4 candidates 400x400")
+    w = room_small
+    prm = oracle_params()
+    train = w.train.subset([0, 3, 7])
+    b = oracle.vf_build(w.scene, train, 3, prm)
+    g = gpu_build(ctx, _dsc(w.scene), train, 3)
+    worst, frac = compare_gamma(g, b)
+    say(f"  gamma worst {worst:.3f} allowance frac {frac:.4f}")
+    assert worst <= 1.0
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    cand = w.cand.subset([0, 1, 2, 3])
+    q = oracle.vf_query(w.scene, g32, 3, train.n, cand, prm)
+    s, mp, _ = gpu_query(ctx, _dsc(w.scene), g32, 3, train.n, cand)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(s, q, mp)
+    _check_argmax(ctx, s, q)
+
+
+def test_room_full_size_sampled(ctx):
+    """The room workload at full size (200k Gaussians, 64 candidates 400x400,
+    as the benchmark runs it, all views in one call): the oracle recomputes
+    two of the views; the build is checked on two full-size training views."""
+    w = scenes.workload("room")
+    prm = oracle_params()
+    say("case: room full size build on 2 of the 100 training views")
+    train = w.train.subset([10, 60])
+    b = oracle.vf_build(w.scene, train, 3, prm)
+    dsc = _dsc(w.scene)
+    g = gpu_build(ctx, dsc, train, 3)
+    assert compare_gamma(g, b)[0] <= 1.0
+    say("case: room full size query, 64 views in one call, oracle on views 5 and 40")
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    s, mp, _ = gpu_query(ctx, dsc, g32, 3, train.n, w.cand)
+    sub = w.cand.subset([5, 40])
+    q = oracle.vf_query(w.scene, g32, 3, train.n, sub, prm)
+    npx = 400 * 400
+    mp_sub = np.concatenate([mp[5 * npx:6 * npx], mp[40 * npx:41 * npx]])
+    worst, flagged = compare_maps(mp_sub, q)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(np.array([s[5], s[40]]), q, mp_sub)
