@@ -111,6 +111,8 @@ typedef struct {
     int32_t write_maps;         /* 1: also write the per-pixel entropy maps */
     int32_t use_graph;          /* 1: capture the launch sequence in a hipGraph and
                                    replay it while shapes and pointers repeat */
+    int32_t count_pairs;        /* 1: count composited (pixel, Gaussian) pairs, read
+                                   back by gv_workspace_check (costs one add per pair) */
 } gv_uq_params;
 
 /* Workspace plan, filled by the *_workspace_size calls.  The caller
@@ -179,11 +181,25 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
                          const gv_uq_params *params, float *scores, float *maps,
                          const gv_workspace *plan, void *workspace, void *hip_stream);
 
-/* Synchronises hip_stream and reads the workspace's status words:
- * out[0] records used, out[1] instances needed, out[2] overflow flag (1 if a
- * capacity was exceeded).  Returns GV_ERR_CAPACITY on overflow. */
+/* Synchronises hip_stream and reads the workspace's status words of the last
+ * call (the last pass of a multi-pass build): out[0] records, out[1]
+ * instances, out[2] overflow flags (nonzero if a capacity was exceeded),
+ * out[3] composited (pixel, Gaussian) pairs -- always counted by vf_build,
+ * counted by vf_query_views when params->count_pairs is set.  Returns
+ * GV_ERR_CAPACITY on overflow. */
 gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace,
-                             int64_t out[3], void *hip_stream);
+                             int64_t out[4], void *hip_stream);
+
+/* Stage timing for measurement.  While enabled, the context records a pair
+ * of HIP events around each stage of every call on the call's stream.
+ * gv_profile_read synchronises `hip_stream`, adds the elapsed times of all
+ * completed stages into ms[stage] and their launch counts into calls[stage]
+ * (arrays of GV_PROFILE_STAGES entries, caller-owned host memory) and clears
+ * the accumulators.  gv_profile_stage_name gives the stage names. */
+#define GV_PROFILE_STAGES 9
+gv_status gv_profile_enable(gv_context *ctx, int32_t on);
+gv_status gv_profile_read(gv_context *ctx, double *ms, int64_t *calls, void *hip_stream);
+const char *gv_profile_stage_name(int32_t stage);
 
 /* Bytes needed for a plan whose capacities the caller edited. */
 size_t gv_workspace_bytes(const gv_workspace *plan);

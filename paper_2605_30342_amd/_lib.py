@@ -22,7 +22,9 @@ EXPORTS = (
     "gv_create", "gv_destroy", "gv_last_error", "gv_default_vf_params", "gv_default_uq_params",
     "vf_build_workspace_size", "vf_build", "vf_query_workspace_size", "vf_query_views",
     "gv_workspace_check", "gv_workspace_bytes", "select_next_view",
+    "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name",
 )
+GV_PROFILE_STAGES = 9
 
 
 class GvError(RuntimeError):
@@ -53,7 +55,7 @@ class gv_uq_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_float), ("o0", ctypes.c_float), ("half_logdet_Q0", ctypes.c_float),
                 ("half_logdet_Qc", ctypes.c_float), ("eps_T", ctypes.c_float), ("znear", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("cut", ctypes.c_float), ("write_maps", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("count_pairs", ctypes.c_int32)]
 
 
 class gv_workspace(ctypes.Structure):
@@ -104,6 +106,12 @@ def load(path: str = LIB_PATH):
     L.gv_workspace_bytes.restype = ctypes.c_size_t
     L.select_next_view.argtypes = [vp, vp, i32, P(i32), vp]
     L.select_next_view.restype = st
+    L.gv_profile_enable.argtypes = [vp, i32]
+    L.gv_profile_enable.restype = st
+    L.gv_profile_read.argtypes = [vp, P(ctypes.c_double), P(i64), vp]
+    L.gv_profile_read.restype = st
+    L.gv_profile_stage_name.argtypes = [i32]
+    L.gv_profile_stage_name.restype = ctypes.c_char_p
     _lib = L
     return L
 

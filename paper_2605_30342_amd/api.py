@@ -177,9 +177,20 @@ class Context:
         return scores, maps
 
     def check_workspace(self, ws: Workspace, stream=None):
-        out = (ctypes.c_int64 * 3)()
+        """(status, (records, instances, overflow flags, pairs composited))."""
+        out = (ctypes.c_int64 * 4)()
         st = self.L.gv_workspace_check(self.h, ctypes.byref(ws.plan), _ptr(ws.buf), out, _stream(stream))
-        return st, (int(out[0]), int(out[1]), int(out[2]))
+        return st, (int(out[0]), int(out[1]), int(out[2]), int(out[3]))
+
+    def profile(self, on: bool = True):
+        check(self.L.gv_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, stream=None) -> dict:
+        n = _lib.GV_PROFILE_STAGES
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int64 * n)()
+        check(self.L.gv_profile_read(self.h, ms, calls, _stream(stream)))
+        return {self.L.gv_profile_stage_name(i).decode(): (float(ms[i]), int(calls[i])) for i in range(n)}
 
     def select_next_view(self, scores: torch.Tensor, stream=None) -> int:
         best = ctypes.c_int32(-1)

@@ -162,6 +162,17 @@ int bits_for(uint64_t n) {   // bits needed to hold values 0..n-1
 
 }  // namespace
 
+namespace {
+const char *const kStageNames[GV_PROFILE_STAGES] = {"cull", "project", "sort_depth", "emit", "sort_tile",
+                                                     "ranges", "raster_vis", "vf_accum", "raster_uq"};
+enum Stage { ST_CULL, ST_PROJECT, ST_SORT_DEPTH, ST_EMIT, ST_SORT_TILE, ST_RANGES, ST_RASTER_VIS, ST_ACCUM,
+             ST_RASTER_UQ };
+struct ProfEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+}  // namespace
+
 struct gv_context {
     int device = 0;
     unsigned long long *dev_counters = nullptr;   // sizing counters
@@ -169,7 +180,42 @@ struct gv_context {
     ViewDev *dev_views = nullptr;                 // view table for sizing passes
     size_t dev_views_cap = 0;
     std::vector<ViewDev> host_views;
+    // stage timing
+    bool prof_on = false;
+    std::vector<ProfEvent> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    hipEvent_t prof_event() {
+        if (!prof_pool.empty()) {
+            hipEvent_t e = prof_pool.back();
+            prof_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
 };
+
+namespace {
+// Records a pair of events around one stage while profiling is enabled.
+struct StageScope {
+    gv_context *c;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageScope(gv_context *c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
+        if (c && c->prof_on) {
+            a = c->prof_event();
+            if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+        }
+    }
+    ~StageScope() {
+        if (!a) return;
+        hipEvent_t b = c->prof_event();
+        if (b && hipEventRecord(b, s) == hipSuccess) c->prof_pending.push_back({stage, a, b});
+    }
+};
+}  // namespace
 
 // Fills host view descriptors; returns total tiles and pixels.
 static gv_status make_views(const gv_camera *cams, int32_t n, std::vector<ViewDev> &out, int64_t &tiles,
@@ -290,7 +336,7 @@ struct Binned {
     const uint32_t *ival;   // record ids in (tile, depth) order
 };
 
-static gv_status run_binning(const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
+static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
                              int64_t tiles, const GeomArgs &geo, bool query, int sh, const void *gamma, int gdt,
                              float n_train, hipStream_t s, Binned &out) {
     Status *st = at<Status>(ws, L.status);
@@ -308,21 +354,40 @@ static gv_status run_binning(const gv_workspace &p, const Layout &L, void *ws, c
     uint32_t *hist = at<uint32_t>(ws, L.hist), *dtot = at<uint32_t>(ws, L.dtot);
     const uint64_t R = (uint64_t)p.max_records, M = (uint64_t)p.max_instances;
 
-    launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
-    launch_count(a, views, nv, geo, cnt, s);
-    launch_scan(cnt, offs, nullptr, (uint64_t)a.n, (uint64_t)a.n, blk, &st->R_total, &st->R_eff, R, &st->overflow,
-                1u, s);
-    launch_project(a, views, nv, geo, offs, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
-    const int dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s);
+    {
+        StageScope sc(ctx, ST_CULL, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
+        launch_count(a, views, nv, geo, cnt, s);
+        launch_scan(cnt, offs, nullptr, (uint64_t)a.n, (uint64_t)a.n, blk, &st->R_total, &st->R_eff, R,
+                    &st->overflow, 1u, s);
+    }
+    {
+        StageScope sc(ctx, ST_PROJECT, s);
+        launch_project(a, views, nv, geo, offs, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
+    }
+    int dres;
+    {
+        StageScope sc(ctx, ST_SORT_DEPTH, s);
+        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s);
+    }
     const uint32_t *sval = dres ? v1 : v0;
-    launch_gather_ntiles(sval, bin, &st->R_eff, icnt, s);
-    launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
-    launch_emit(sval, bin, ioff, views, st, ik0, iv0, s);
-    const int tres =
-        launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s);
+    {
+        StageScope sc(ctx, ST_EMIT, s);
+        launch_gather_ntiles(sval, bin, &st->R_eff, icnt, s);
+        launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
+        launch_emit(sval, bin, ioff, views, st, ik0, iv0, s);
+    }
+    int tres;
+    {
+        StageScope sc(ctx, ST_SORT_TILE, s);
+        tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s);
+    }
     const uint32_t *skey = tres ? ik1 : ik0;
-    launch_ranges(skey, st, ranges, s);
+    {
+        StageScope sc(ctx, ST_RANGES, s);
+        launch_ranges(skey, st, ranges, s);
+    }
     out.sval = sval;
     out.ival = tres ? iv1 : iv0;
     return GV_OK;
@@ -385,6 +450,11 @@ void gv_destroy(gv_context *ctx) {
     if (ctx->dev_counters) (void)hipFree(ctx->dev_counters);
     if (ctx->dev_best) (void)hipFree(ctx->dev_best);
     if (ctx->dev_views) (void)hipFree(ctx->dev_views);
+    for (const ProfEvent &e : ctx->prof_pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -514,17 +584,24 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
         Binned bz;
-        GV_TRY(run_binning(*plan, Lay, workspace, a, nv, tiles, geo, false, L, nullptr, 0, 0.f, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, false, L, nullptr, 0, 0.f, s, bz));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
         launch_fill_dev_u32(reinterpret_cast<uint32_t *>(accT), &st->R_eff, 1, 0u, s);
         launch_fill_dev_u32(accC, &st->R_eff, 1, 0u, s);
-        launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                          bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC, s);
-        launch_vf_accum(a, at<ViewDev>(workspace, Lay.views), at<uint32_t>(workspace, Lay.offs),
-                        at<Bin>(workspace, Lay.bin), accT, accC, st, L, al, acc_target,
-                        half_out ? 0 : (int)gamma_dtype, acc, s);
+        {
+            StageScope sc(ctx, ST_RASTER_VIS, s);
+            launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                              bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
+                              &st->measure[0], s);
+        }
+        {
+            StageScope sc(ctx, ST_ACCUM, s);
+            launch_vf_accum(a, at<ViewDev>(workspace, Lay.views), at<uint32_t>(workspace, Lay.offs),
+                            at<Bin>(workspace, Lay.bin), accT, accC, st, L, al, acc_target,
+                            half_out ? 0 : (int)gamma_dtype, acc, s);
+        }
         GV_HIP(hipGetLastError());
         if (v0 + vp < n_train) {
             // the next pass reuses the workspace; its status must be read now
@@ -574,8 +651,8 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     const GaussArgs a = gargs(g);
     const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
     Binned bz;
-    GV_TRY(run_binning(*plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma, (int)gamma_dtype,
-                       (float)n_train, s, bz));
+    GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma,
+                       (int)gamma_dtype, (float)n_train, s, bz));
     const double c3 = 1.5 * std::log(2.0 * M_PI * M_E);
     UqArgs u;
     u.beta = prm->beta;
@@ -585,14 +662,19 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     u.eps_T = prm->eps_T;
     u.qcut = (float)(0.5 * prm->cut / std::log(2.0));
     float *tpart = at<float>(workspace, Lay.tpart);
-    launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                     bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, prm->write_maps ? maps : nullptr, s);
+    {
+        StageScope sc(ctx, ST_RASTER_UQ, s);
+        Status *st = at<Status>(workspace, Lay.status);
+        launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                         bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, prm->write_maps ? maps : nullptr,
+                         prm->count_pairs ? &st->measure[0] : nullptr, s);
+    }
     launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
     GV_HIP(hipGetLastError());
     return GV_OK;
 }
 
-gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace, int64_t out[3],
+gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace, int64_t out[4],
                              void *hip_stream) {
     if (!ctx || !plan || !workspace) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     DeviceGuard dg(ctx->device);
@@ -605,10 +687,43 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
         out[0] = (int64_t)h.R_total;
         out[1] = (int64_t)h.M_total;
         out[2] = (int64_t)h.overflow;
+        out[3] = (int64_t)h.measure[0];
     }
     if (h.overflow) return fail(GV_ERR_CAPACITY, "workspace capacity exceeded (records %llu, instances %llu)",
                                 h.R_total, h.M_total);
     return GV_OK;
+}
+
+gv_status gv_profile_enable(gv_context *ctx, int32_t on) {
+    if (!ctx) return fail(GV_ERR_INVALID_ARG, "NULL context");
+    ctx->prof_on = on != 0;
+    return GV_OK;
+}
+
+gv_status gv_profile_read(gv_context *ctx, double *ms, int64_t *calls, void *hip_stream) {
+    if (!ctx || !ms || !calls) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    GV_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    for (int i = 0; i < GV_PROFILE_STAGES; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    for (const ProfEvent &e : ctx->prof_pending) {
+        float t = 0.f;
+        if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+            ms[e.stage] += t;
+            calls[e.stage] += 1;
+        }
+        ctx->prof_pool.push_back(e.a);
+        ctx->prof_pool.push_back(e.b);
+    }
+    ctx->prof_pending.clear();
+    return GV_OK;
+}
+
+const char *gv_profile_stage_name(int32_t stage) {
+    if (stage < 0 || stage >= GV_PROFILE_STAGES) return "";
+    return kStageNames[stage];
 }
 
 gv_status select_next_view(gv_context *ctx, const float *scores, int32_t n, int32_t *best, void *hip_stream) {

@@ -54,9 +54,11 @@ void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, con
 void launch_ranges(const uint32_t *key, const Status *st, uint2 *ranges, hipStream_t s);
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s);
+                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
+                       unsigned long long *pairs, hipStream_t s);
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, hipStream_t s);
+                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
+                      hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);

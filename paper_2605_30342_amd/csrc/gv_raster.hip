@@ -33,6 +33,21 @@ __device__ __forceinline__ int find_view(const ViewDev *__restrict__ views, int 
 }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Adds the block's total of a per-thread count to *out (one atomic per block).
+__device__ __forceinline__ void block_count(uint32_t c, unsigned long long *out) {
+    if (!out) return;
+    __shared__ unsigned long long red[WAVES];
+    unsigned long long x = c;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int w = 0; w < WAVES; ++w) tot += red[w];
+        if (tot) atomicAdd(out, tot);
+    }
+}
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
 // Record -> tile-local form: centre relative to the tile origin, computed from
@@ -50,7 +65,8 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
                                                    const uint2 *__restrict__ ranges,
                                                    const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
-                                                   uint32_t *__restrict__ acc_c) {
+                                                   uint32_t *__restrict__ acc_c,
+                                                   unsigned long long *__restrict__ pairs) {
     __shared__ float4 sA[WG];          // ux, uy, l11, l21
     __shared__ float2 sB[WG];          // l22, o
     __shared__ uint32_t sR[WG];        // record index
@@ -68,6 +84,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     bool done = (ox + lx >= V.w) || (oy + ly >= V.h);
     float T = 1.0f;
     const uint2 rg = ranges[gt];
+    uint32_t npairs = 0;
 
     for (uint32_t b = rg.x; b < rg.y; b += WG) {
         if (__syncthreads_count(!done) == 0) break;
@@ -122,18 +139,21 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             if (c) {
                 atomicAdd(&acc_T[sR[t]], s);
                 atomicAdd(&acc_c[sR[t]], c);
+                npairs += c;
             }
         }
     }
+    block_count(npairs, pairs);
 }
 
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
 
-template <bool MAPS>
+template <bool MAPS, bool COUNT>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
-                                                  UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps) {
+                                                  UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
+                                                  unsigned long long *__restrict__ pairs) {
     __shared__ float4 sA[WG];          // ux, uy, l11, l21
     __shared__ float4 sB[WG];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
     __shared__ float red[WAVES];
@@ -149,6 +169,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const bool inside = (ox + lx < V.w) && (oy + ly < V.h);
     bool done = !inside;
     float T = 1.0f, H = 0.0f, w0 = 0.0f;
+    uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
 
@@ -181,6 +202,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                 w0 += wt - x;                                      // w* (1 - v)
                 T -= wt;                                           // T (1 - alpha*)
                 done = T < u.eps_T;
+                if (COUNT) ++npairs;
             }
         }
         __syncthreads();
@@ -197,6 +219,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         for (int ww = 0; ww < WAVES; ++ww) tot += red[ww];
         tile_part[gt] = tot;
     }
+    if (COUNT) block_count(npairs, pairs);
 }
 
 // ---------------------------------------------------------------- scores and argmax
@@ -340,21 +363,26 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 // ---------------------------------------------------------------- launchers
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
+                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
+                       unsigned long long *pairs, hipStream_t s) {
     if (total_tiles <= 0) return;
     hipLaunchKernelGGL(k_raster_vis, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
-                       acc_T, acc_c);
+                       acc_T, acc_c, pairs);
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, hipStream_t s) {
+                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
+                      hipStream_t s) {
     if (total_tiles <= 0) return;
-    if (maps)
-        hipLaunchKernelGGL(k_raster_uq<true>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, u,
-                           tile_part, maps);
+    const dim3 g(total_tiles), b(WG);
+    if (maps && pairs)
+        hipLaunchKernelGGL((k_raster_uq<true, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    else if (maps)
+        hipLaunchKernelGGL((k_raster_uq<true, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    else if (pairs)
+        hipLaunchKernelGGL((k_raster_uq<false, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
     else
-        hipLaunchKernelGGL(k_raster_uq<false>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, u,
-                           tile_part, maps);
+        hipLaunchKernelGGL((k_raster_uq<false, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
 }
 
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
