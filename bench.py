@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=2, help="candidate views the CPU baseline runs")
+    ap.add_argument("--cpu-views", type=int, default=24, help="candidate views the CPU baseline runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
