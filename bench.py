@@ -179,6 +179,37 @@ def main():
         uq_frac = {"achieved": round(a, 3), "peak": round(VALU_PEAK_TOPS, 2), "frac": round(a / VALU_PEAK_TOPS, 4),
                    "avg_launch_ms": round(per_launch["raster_uq"], 4), "pairs": int(pairs_uq)}
 
+    # batching: the same candidates as one call per view (plain form), as one
+    # call for all views, and as one replay of the captured graph
+    def timed(fn, reps=5):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    singles = [w.cand.subset([v]) for v in range(w.cand.n)]
+    one = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def plain():
+        for c in singles:
+            ctx.vf_query_views(dsc, gamma, L, w.train.n, c, uprm, ws_q, scores=one)
+    gprm = _lib.default_uq_params(use_graph=1)
+    side = torch.cuda.Stream()
+    plain_ms = timed(plain)
+    batched_ms = timed(lambda: ctx.vf_query_views(dsc, gamma, L, w.train.n, w.cand, uprm, ws_q, scores=scores))
+    with torch.cuda.stream(side):
+        graph_ms = timed(lambda: ctx.vf_query_views(dsc, gamma, L, w.train.n, w.cand, gprm, ws_q, scores=scores))
+    torch.cuda.synchronize()
+    batching = {"plain_per_view_ms": round(plain_ms, 4), "batched_call_ms": round(batched_ms, 4),
+                "graph_replay_ms": round(graph_ms, 4), "speedup_batched_vs_plain": round(plain_ms / batched_ms, 3),
+                "speedup_graph_vs_plain": round(plain_ms / graph_ms, 3)}
+    log(f"batching {batching}")
+
     if args.calib_copy_mib:
         n = args.calib_copy_mib * 2**20 // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -227,6 +258,7 @@ def main():
         "pairs": {"raster_vis": int(pairs_vis), "raster_uq": int(pairs_uq)},
         "roofline": roof,
         "raster_uq_roofline": uq_frac,
+        "batching": batching,
         "cpu_baseline": cpu,
     }
     ctx.close()

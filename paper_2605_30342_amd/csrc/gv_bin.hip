@@ -182,15 +182,17 @@ __device__ __forceinline__ void project_exact(const float m[3], const double S[6
 template <typename TG>
 __global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                               float znear, float lowpass, float cut, uint32_t *__restrict__ cnt) {
-    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t g = e / PROJ_SPLIT;
     if (g >= G.n) return;
+    const int sub = (int)(e % PROJ_SPLIT);
     float m[3], s[3];
     G.mean(g, m);
     G.scale(g, s);
     const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
     uint32_t c = 0;
-    for (int v = 0; v < nv; ++v) c += cons_visible(m, smax, views[v], znear, lowpass, cut) ? 1u : 0u;
-    cnt[g] = c;
+    for (int v = sub; v < nv; v += PROJ_SPLIT) c += cons_visible(m, smax, views[v], znear, lowpass, cut) ? 1u : 0u;
+    cnt[e] = c;
 }
 
 // Sizing pass: counts records (conservative test) and exact instances.
@@ -198,7 +200,9 @@ template <typename TG>
 __global__ __launch_bounds__(WG) void k_measure(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                                 float znear, float lowpass, float cut,
                                                 unsigned long long *__restrict__ out) {
-    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t g = e / PROJ_SPLIT;
+    const int sub = (int)(e % PROJ_SPLIT);
     unsigned long long rc = 0, mc = 0;
     if (g < G.n) {
         float m[3], s[3], q[4];
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(WG) void k_measure(GaussIn<TG> G, const ViewDev *__
         const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
         double S[6];
         cov3d(s, q, S);
-        for (int v = 0; v < nv; ++v) {
+        for (int v = sub; v < nv; v += PROJ_SPLIT) {
             if (!cons_visible(m, smax, views[v], znear, lowpass, cut)) continue;
             ++rc;
             Proj P;
@@ -239,8 +243,10 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                 Bin *__restrict__ bin) {
     constexpr int K = (L + 1) * (L + 1);
-    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t g = e / PROJ_SPLIT;
     if (g >= G.n) return;
+    const int sub = (int)(e % PROJ_SPLIT);
     if (st->overflow & 1u) return;
     float m[3], s[3], q[4];
     G.mean(g, m);
@@ -256,10 +262,10 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
 #pragma unroll
         for (int k = 0; k < K; ++k) gam[k] = load_f(gamma, (int64_t)k * G.n + g);
     }
-    uint32_t r = offs[g];
-    const uint32_t rend = offs[g + 1];
+    uint32_t r = offs[e];
+    const uint32_t rend = offs[e + 1];
     const double sc = 0.8493218002880191;   // sqrt(log2(e) / 2)
-    for (int v = 0; v < nv; ++v) {
+    for (int v = sub; v < nv; v += PROJ_SPLIT) {
         const ViewDev &V = views[v];
         if (!cons_visible(m, smax, V, znear, lowpass, cut)) continue;
         if (r >= rend || r >= rcap) break;
@@ -419,16 +425,22 @@ __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ i
 
 // ---------------------------------------------------------------- LSD radix sort
 
-// Each pass sorts (key, value) pairs stably by an 8-bit digit.  The n pairs
-// are cut into RADIX_BLOCKS contiguous chunks (multiples of 256); block b
-// histograms its chunk, the histograms are scanned digit-major, and block b
-// scatters its chunk in 256-element tiles, ranking equal digits inside a wave
-// by ballot matching and across the four waves through LDS counts.
+// Each pass sorts (key, value) pairs stably by one digit of up to 8 bits.
+// The n pairs are cut into RADIX_BLOCKS contiguous chunks of whole tiles
+// (RTILE = 2048 pairs).  Block b histograms its chunk; the histograms are
+// scanned digit-major; block b then walks its chunk tile by tile.  In a tile,
+// wave w owns pairs [w * 512, (w + 1) * 512) and loads all eight of its keys
+// per lane up front; it ranks equal digits with ballot matching, sub-round by
+// sub-round, against wave-private LDS counters (no barrier), and one
+// block-wide step turns the four waves' counts into output offsets.
+constexpr int RITEMS = 8;
+constexpr int RTILE = WG * RITEMS;
+constexpr int RWAVE = 64 * RITEMS;
 
 __device__ __forceinline__ void radix_chunk(uint64_t n, uint64_t &start, uint64_t &end) {
     uint64_t ch = (n + RADIX_BLOCKS - 1) / RADIX_BLOCKS;
-    ch = (ch + WG - 1) / WG * WG;
-    if (ch == 0) ch = WG;
+    ch = (ch + RTILE - 1) / RTILE * RTILE;
+    if (ch == 0) ch = RTILE;
     start = (uint64_t)blockIdx.x * ch;
     end = start + ch;
     if (end > n) end = n;
@@ -437,15 +449,29 @@ __device__ __forceinline__ void radix_chunk(uint64_t n, uint64_t &start, uint64_
 
 __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                    int shift, int nbits, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[RADIX];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[WAVES][RADIX];
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) h[q][t] = 0;
     __syncthreads();
     uint64_t start, end;
     radix_chunk(*n_dev, start, end);
     const uint32_t mask = (1u << nbits) - 1u;
-    for (uint64_t i = start + threadIdx.x; i < end; i += WG) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    for (uint64_t s = start; s < end; s += RTILE) {
+        uint32_t k[RITEMS];
+#pragma unroll
+        for (int i = 0; i < RITEMS; ++i) {
+            const uint64_t e = s + (uint64_t)i * WG + t;
+            k[i] = e < end ? keys[e] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < RITEMS; ++i) {
+            const uint64_t e = s + (uint64_t)i * WG + t;
+            if (e < end) atomicAdd(&h[w][(k[i] >> shift) & mask], 1u);
+        }
+    }
     __syncthreads();
-    hist[(size_t)threadIdx.x * RADIX_BLOCKS + blockIdx.x] = h[threadIdx.x];
+    hist[(size_t)t * RADIX_BLOCKS + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
 // One block per digit: exclusive scan of that digit's RADIX_BLOCKS counts.
@@ -481,11 +507,10 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ hist,
                                                       const uint32_t *__restrict__ dtot) {
     __shared__ uint32_t run[RADIX];
-    __shared__ uint32_t wcnt[2][WAVES][RADIX];
+    __shared__ uint32_t wcnt[WAVES][RADIX];
     __shared__ uint32_t scan[RADIX];
-    const int t = threadIdx.x, w = t >> 6;
-    // digit bases: exclusive scan of the digit totals plus this block's offset
-    {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    {   // digit bases: exclusive scan of the digit totals plus this block's offset
         const uint32_t d = dtot[t];
         scan[t] = d;
         __syncthreads();
@@ -496,48 +521,69 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
             __syncthreads();
         }
         run[t] = scan[t] - d + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
-        for (int ww = 0; ww < WAVES; ++ww) {
-            wcnt[0][ww][t] = 0;
-            wcnt[1][ww][t] = 0;
-        }
     }
     __syncthreads();
     uint64_t start, end;
     radix_chunk(*n_dev, start, end);
     const uint32_t mask = (1u << nbits) - 1u;
-    int buf = 0;
-    for (uint64_t s = start; s < end; s += WG) {
-        const uint64_t i = s + t;
-        const bool valid = i < end;
-        const uint32_t k = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
-        const uint32_t d = (k >> shift) & mask;
-        unsigned long long peers = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const unsigned long long bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
+    for (uint64_t s = start; s < end; s += RTILE) {
+        const uint64_t base = s + (uint64_t)w * RWAVE + lane;
+        uint32_t k[RITEMS], v[RITEMS], pos[RITEMS];
+#pragma unroll
+        for (int i = 0; i < RITEMS; ++i) {
+            const uint64_t e = base + (uint64_t)i * 64;
+            k[i] = e < end ? kin[e] : 0u;
+            v[i] = e < end ? (vin ? vin[e] : (uint32_t)e) : 0u;
         }
-        const uint32_t rank = lanes_below(peers);
-        if (valid && rank == 0) wcnt[buf][w][d] = (uint32_t)__popcll(peers);
+        // this wave's counters start the tile at zero (wave-private row)
+#pragma unroll
+        for (int q = 0; q < RADIX / 64; ++q) wcnt[w][q * 64 + lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int i = 0; i < RITEMS; ++i) {
+            const bool valid = base + (uint64_t)i * 64 < end;
+            const uint32_t d = (k[i] >> shift) & mask;
+            unsigned long long peers = __builtin_amdgcn_ballot_w64(valid);
+            for (int bb = 0; bb < nbits; ++bb) {
+                const bool bit = (d >> bb) & 1u;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const uint32_t rank = lanes_below(peers);
+            const uint32_t before = wcnt[w][d];
+            pos[i] = before + rank;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (valid && rank == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         __syncthreads();
         {   // digit t: offsets of the four waves, then advance the running base
             uint32_t acc = run[t];
+#pragma unroll
             for (int ww = 0; ww < WAVES; ++ww) {
-                const uint32_t c = wcnt[buf][ww][t];
-                wcnt[buf][ww][t] = acc;
+                const uint32_t c = wcnt[ww][t];
+                wcnt[ww][t] = acc;
                 acc += c;
-                wcnt[buf ^ 1][ww][t] = 0;
             }
             run[t] = acc;
         }
         __syncthreads();
-        if (valid) {
-            const uint32_t pos = wcnt[buf][w][d] + rank;
-            kout[pos] = k;
-            vout[pos] = val;
+#pragma unroll
+        for (int i = 0; i < RITEMS; ++i) {
+            if (base + (uint64_t)i * 64 < end) {
+                const uint32_t d = (k[i] >> shift) & mask;
+                const uint32_t o = wcnt[w][d] + pos[i];
+                kout[o] = k[i];
+                vout[o] = v[i];
+            }
         }
-        buf ^= 1;
+        // no barrier here: until the next tile's first barrier a wave only
+        // touches its own counter row, which no other wave reads meanwhile
     }
 }
 
@@ -553,25 +599,69 @@ __global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict
 
 // One (global tile id, record) instance per tile of every record, written in
 // depth order so that a stable sort by tile id keeps depth order in a tile.
+// Each wave takes 64 consecutive records and writes their instances as one
+// contiguous range, lane j writing output j, j + 64, ...; the record that
+// owns an output is found by binary search over the wave's offsets in LDS.
 __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
                                              const uint32_t *__restrict__ ioff, const ViewDev *__restrict__ views,
                                              const Status *__restrict__ st, uint32_t *__restrict__ ikey,
                                              uint32_t *__restrict__ ival) {
+    __shared__ uint32_t soff[WAVES][65];
+    __shared__ uint32_t sa[WAVES][64], sb[WAVES][64], sr[WAVES][64], stb[WAVES][64], stx[WAVES][64];
     if (st->overflow) return;
     const uint64_t n = st->R_eff;
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
-        const uint32_t r = sval[i];
-        const Bin b = bin[r];
-        if (b.ntiles == 0) continue;
-        const ViewDev &V = views[b.view];
-        uint32_t o = ioff[i];
-        const int x0 = b.x0y0 & 0xFFFF, y0 = b.x0y0 >> 16, x1 = b.x1y1 & 0xFFFF, y1 = b.x1y1 >> 16;
-        for (int ty = y0; ty < y1; ++ty)
-            for (int tx = x0; tx < x1; ++tx) {
-                ikey[o] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-                ival[o] = r;
-                ++o;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t nwaves = (uint64_t)gridDim.x * WAVES;
+    for (uint64_t c = (uint64_t)blockIdx.x * WAVES + w; c * 64 < n; c += nwaves) {
+        const uint64_t i = c * 64 + lane;
+        const bool valid = i < n;
+        uint32_t r = 0, o = 0, nt = 0, a0 = 0, a1 = 0, tb = 0, tx = 1;
+        if (valid) {
+            r = sval[i];
+            const Bin B = bin[r];
+            o = ioff[i];
+            nt = B.ntiles;
+            a0 = B.x0y0;
+            a1 = B.x1y1;
+            if (nt) {
+                const ViewDev &V = views[B.view];
+                tb = (uint32_t)V.tile_base;
+                tx = (uint32_t)V.tiles_x;
             }
+        }
+        const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
+        // exclusive offsets inside the wave's range; invalid lanes sit at the end
+        uint32_t rel = valid ? o - o0 : 0xFFFFFFFFu;
+        soff[w][lane] = rel;
+        sa[w][lane] = a0;
+        sb[w][lane] = a1;
+        sr[w][lane] = r;
+        stb[w][lane] = tb;
+        stx[w][lane] = tx;
+        // total = largest (rel + nt) over valid lanes
+        uint32_t endv = valid ? rel + nt : 0u;
+        for (int off = 32; off > 0; off >>= 1) endv = max(endv, (uint32_t)__shfl_xor((int)endv, off));
+        if (lane == 0) soff[w][64] = 0xFFFFFFFFu;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t j = lane; j < endv; j += 64) {
+            // last q with soff[q] <= j (soff is nondecreasing over valid lanes)
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (soff[w][mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t k = j - soff[w][lo];
+            const uint32_t x0 = sa[w][lo] & 0xFFFF, y0 = sa[w][lo] >> 16, x1 = sb[w][lo] & 0xFFFF;
+            const uint32_t wx = x1 - x0;
+            const uint32_t ty = k / wx, txx = k - ty * wx;
+            ikey[o0 + j] = stb[w][lo] + (y0 + ty) * stx[w][lo] + x0 + txx;
+            ival[o0 + j] = sr[w][lo];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -620,7 +710,7 @@ static GaussIn<TG> gin(const GaussArgs &a) {
 }
 
 void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
     if (grid == 0) return;
     switch (a.dtype) {
     case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
@@ -631,7 +721,7 @@ void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomAr
 
 void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
                     hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
     if (grid == 0) return;
     switch (a.dtype) {
     case 0: hipLaunchKernelGGL(k_measure<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, out); break;
@@ -644,7 +734,7 @@ template <typename TG, typename TGam, bool QUERY>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                const uint32_t *offs, const Status *st, uint32_t rcap, const void *gamma,
                                float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
+    const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
     const TGam *gm = (const TGam *)gamma;
     switch (L) {
     case 0: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 0>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;

@@ -120,9 +120,9 @@ Layout make_layout(const gv_workspace &p) {
     const int K = (p.sh_degree + 1) * (p.sh_degree + 1);
     L.status = take(sizeof(Status));
     L.views = take(V * sizeof(ViewDev));
-    L.cnt = take(N * 4);
-    L.offs = take((N + 1) * 4);
-    L.blk = take(scan_blk_count(std::max(N, R)) * 8);
+    L.cnt = take(N * PROJ_SPLIT * 4);
+    L.offs = take((N * PROJ_SPLIT + 1) * 4);
+    L.blk = take(scan_blk_count(std::max(N * PROJ_SPLIT, R)) * 8);
     L.rec = take(R * sizeof(Rec));
     L.bin = take(R * sizeof(Bin));
     L.key0 = take(R * 4);
@@ -180,6 +180,15 @@ struct gv_context {
     ViewDev *dev_views = nullptr;                 // view table for sizing passes
     size_t dev_views_cap = 0;
     std::vector<ViewDev> host_views;
+    // captured query sequences, most recent last
+    struct Graph {
+        std::vector<unsigned char> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     // stage timing
     bool prof_on = false;
     std::vector<ProfEvent> prof_pending;
@@ -204,7 +213,7 @@ struct StageScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     StageScope(gv_context *c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
-        if (c && c->prof_on) {
+        if (c && c->prof_on && !c->capturing) {
             a = c->prof_event();
             if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
         }
@@ -358,8 +367,8 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
         StageScope sc(ctx, ST_CULL, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
         launch_count(a, views, nv, geo, cnt, s);
-        launch_scan(cnt, offs, nullptr, (uint64_t)a.n, (uint64_t)a.n, blk, &st->R_total, &st->R_eff, R,
-                    &st->overflow, 1u, s);
+        const uint64_t ne = (uint64_t)a.n * PROJ_SPLIT;
+        launch_scan(cnt, offs, nullptr, ne, ne, blk, &st->R_total, &st->R_eff, R, &st->overflow, 1u, s);
     }
     {
         StageScope sc(ctx, ST_PROJECT, s);
@@ -455,6 +464,11 @@ void gv_destroy(gv_context *ctx) {
         (void)hipEventDestroy(e.b);
     }
     for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+    for (auto &gr : ctx->graphs) {
+        (void)hipGraphExecDestroy(gr.exec);
+        (void)hipGraphDestroy(gr.graph);
+    }
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -650,9 +664,6 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
                           hipMemcpyHostToDevice, s));
     const GaussArgs a = gargs(g);
     const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
-    Binned bz;
-    GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma,
-                       (int)gamma_dtype, (float)n_train, s, bz));
     const double c3 = 1.5 * std::log(2.0 * M_PI * M_E);
     UqArgs u;
     u.beta = prm->beta;
@@ -661,16 +672,82 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     u.cQ0 = (float)(prm->half_logdet_Q0 + c3);
     u.eps_T = prm->eps_T;
     u.qcut = (float)(0.5 * prm->cut / std::log(2.0));
-    float *tpart = at<float>(workspace, Lay.tpart);
-    {
-        StageScope sc(ctx, ST_RASTER_UQ, s);
-        Status *st = at<Status>(workspace, Lay.status);
-        launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                         bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, prm->write_maps ? maps : nullptr,
-                         prm->count_pairs ? &st->measure[0] : nullptr, s);
+    float *mp = prm->write_maps ? maps : nullptr;
+    auto enqueue = [&]() -> gv_status {
+        Binned bz;
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma,
+                           (int)gamma_dtype, (float)n_train, s, bz));
+        float *tpart = at<float>(workspace, Lay.tpart);
+        {
+            StageScope sc(ctx, ST_RASTER_UQ, s);
+            Status *st = at<Status>(workspace, Lay.status);
+            launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                             bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, mp,
+                             prm->count_pairs ? &st->measure[0] : nullptr, s);
+        }
+        launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
+        return GV_OK;
+    };
+    if (!prm->use_graph) {
+        GV_TRY(enqueue());
+        GV_HIP(hipGetLastError());
+        return GV_OK;
     }
-    launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
-    GV_HIP(hipGetLastError());
+    // Graph path: every kernel argument and grid of the sequence is fixed by
+    // the key below (the cameras themselves live in the view table, uploaded
+    // above on the same stream before the replay).
+    struct Key {
+        const void *ws, *gamma, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
+        int64_t n, n_virtual, n_train, rcap, mcap, tiles, nbytes;
+        int32_t n_cand, sh, gdt, dtype, anchor_block, count;
+        float f[8];
+    } key;
+    std::memset(&key, 0, sizeof(key));
+    key.ws = workspace; key.gamma = gamma; key.scores = scores; key.maps = mp;
+    key.means = g->means; key.scales = g->scales; key.quats = g->quats; key.opac = g->opacity; key.anchors = g->anchors;
+    key.n = g->n; key.n_virtual = g->n_virtual; key.n_train = n_train; key.rcap = plan->max_records;
+    key.mcap = plan->max_instances; key.tiles = tiles; key.nbytes = (int64_t)plan->bytes;
+    key.n_cand = n_cand; key.sh = sh_degree; key.gdt = (int)gamma_dtype; key.dtype = (int)g->dtype;
+    key.anchor_block = g->anchor_block; key.count = prm->count_pairs;
+    const float fv[8] = {prm->beta, prm->o0, prm->half_logdet_Q0, prm->half_logdet_Qc, prm->eps_T, prm->znear,
+                         prm->lowpass, prm->cut};
+    std::memcpy(key.f, fv, sizeof(fv));
+    const unsigned char *kb = reinterpret_cast<const unsigned char *>(&key);
+    std::vector<unsigned char> kv(kb, kb + sizeof(key));
+    for (size_t i = 0; i < ctx->graphs.size(); ++i) {
+        if (ctx->graphs[i].key == kv) {
+            GV_HIP(hipGraphLaunch(ctx->graphs[i].exec, s));
+            return GV_OK;
+        }
+    }
+    gv_context::Graph gr;
+    gr.key = kv;
+    if (!ctx->cap_stream) GV_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // record on the private stream (the caller's may be the legacy default
+    // stream, which cannot be captured), replay on the caller's stream
+    const hipStream_t user_s = s;
+    s = ctx->cap_stream;
+    GV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    const gv_status est = enqueue();
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    s = user_s;
+    if (est != GV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return est;
+    }
+    if (ce != hipSuccess) return fail(GV_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+    gr.graph = graph;
+    GV_HIP(hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0));
+    if (ctx->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        (void)hipGraphDestroy(ctx->graphs.front().graph);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(gr);
+    GV_HIP(hipGraphLaunch(gr.exec, s));
     return GV_OK;
 }
 

@@ -17,7 +17,12 @@ constexpr int WAVES = WG / 64;
 // LSD radix sort: 8-bit digits, a fixed number of blocks per pass.
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int RADIX_BLOCKS = 1024;
+constexpr int RADIX_BLOCKS = 4096;
+
+// Projection: PROJ_SPLIT threads per Gaussian, thread s of Gaussian g handles
+// views s, s + PROJ_SPLIT, ...; records are numbered by (g, s, view), so a
+// Gaussian's records stay contiguous.
+constexpr int PROJ_SPLIT = 4;
 
 // Device exclusive scan: elements per block.
 constexpr int SCAN_ITEMS = 16;

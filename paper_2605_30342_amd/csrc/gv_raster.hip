@@ -59,19 +59,129 @@ __device__ __forceinline__ void local_centre(const Rec &R, int ox, int oy, float
     uy = (float)(ay - oy) + R.fy;
 }
 
+// Lane `lane` of v takes the uniform value x (v_writelane_b32 ignores EXEC;
+// the lane select must be an inline constant, so the switch below folds to a
+// single instruction once the caller's loop is unrolled).
+template <int J>
+__device__ __forceinline__ uint32_t write_lane_c(uint32_t v, uint32_t x) {
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "i"(J));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t x, int lane) {
+    switch (lane) {
+    case 0: return write_lane_c<0>(v, x);
+    case 1: return write_lane_c<1>(v, x);
+    case 2: return write_lane_c<2>(v, x);
+    case 3: return write_lane_c<3>(v, x);
+    case 4: return write_lane_c<4>(v, x);
+    case 5: return write_lane_c<5>(v, x);
+    case 6: return write_lane_c<6>(v, x);
+    case 7: return write_lane_c<7>(v, x);
+    case 8: return write_lane_c<8>(v, x);
+    case 9: return write_lane_c<9>(v, x);
+    case 10: return write_lane_c<10>(v, x);
+    case 11: return write_lane_c<11>(v, x);
+    case 12: return write_lane_c<12>(v, x);
+    case 13: return write_lane_c<13>(v, x);
+    case 14: return write_lane_c<14>(v, x);
+    default: return write_lane_c<15>(v, x);
+    }
+}
+
+// ---------------------------------------------------------------- batch staging
+
+// A 16x16 tile is split into four 8x8 quadrants, one per wave.  Lane l of wave
+// w owns pixel ((w & 1) * 8 + (l & 7), (w >> 1) * 8 + (l >> 3)) of the tile.
+__device__ __forceinline__ void quadrant_pixel(int t, int &qx, int &qy) {
+    const int w = t >> 6, l = t & 63;
+    qx = ((w & 1) << 3) + (l & 7);
+    qy = ((w >> 1) << 3) + (l >> 3);
+}
+
+// Bit w set when the record's ellipse bounding box (m <= cut) can reach a
+// pixel centre of quadrant w.  The box half-widths follow from the scaled
+// Cholesky factor L = [[a, 0], [b, c]] of the conic: the covariance is
+// (L L^T)^-1, so sigma_xx = (b^2 + c^2) / (a c)^2 and sigma_yy = 1 / c^2, and
+// the box is sqrt(qcut sigma) wide (widened slightly to stay conservative).
+__device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, float b, float c, float qcut) {
+    const float ic = 1.0f / c;
+    const float rx = sqrtf(qcut * fmaf(b, b, c * c)) * ic / a * 1.001f + 0.01f;
+    const float ry = sqrtf(qcut) * ic * 1.001f + 0.01f;
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const float x0 = ((w & 1) << 3) + 0.5f, y0 = ((w >> 1) << 3) + 0.5f;
+        const bool in = (ux + rx >= x0) && (ux - rx <= x0 + 7.0f) && (uy + ry >= y0) && (uy - ry <= y0 + 7.0f);
+        m |= in ? (1u << w) : 0u;
+    }
+    return m;
+}
+
+// Records staged per batch, and the capacity of a per-quadrant list (the
+// lists are padded with never-hit entries up to a multiple of LGROUP).
+constexpr int RB = 128;
+constexpr int LGROUP = 16;
+constexpr int LCAP = RB + LGROUP;
+
+// Positions of this thread's record in the four per-quadrant lists, each in
+// batch (= depth) order; -1 where the record does not touch the quadrant.
+// Also publishes the list lengths in slen[].  Two barriers.
+__device__ __forceinline__ void list_positions(uint32_t mask, int pos[WAVES], int *scnt, int *slen) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    uint32_t pre[WAVES];
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) {
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(((mask >> q) & 1u) != 0u);
+        pre[q] = lanes_below(bal);
+        if (lane == 0) scnt[w * WAVES + q] = (int)__popcll(bal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) {
+        int off = 0;
+        for (int ww = 0; ww < w; ++ww) off += scnt[ww * WAVES + q];
+        pos[q] = ((mask >> q) & 1u) ? off + (int)pre[q] : -1;
+    }
+    if (t < WAVES) {
+        int n = 0;
+        for (int ww = 0; ww < WAVES; ++ww) n += scnt[ww * WAVES + t];
+        slen[t] = n;
+    }
+    __syncthreads();
+}
+
+// Index of the first pad slot that thread t fills with a never-hit entry, or
+// -1 (threads 0..63 pad the four lists up to a multiple of LGROUP).
+__device__ __forceinline__ int pad_slot(const int *slen, int &q) {
+    const int t = threadIdx.x;
+    q = t >> 4;
+    if (t >= WAVES * LGROUP) return -1;
+    const int n = slen[q];
+    const int k = n + (t & (LGROUP - 1));
+    return k < ((n + LGROUP - 1) / LGROUP) * LGROUP ? k : -1;
+}
+
 // ---------------------------------------------------------------- VF CONST raster (Alg. 2)
 
+// Contributions of LGROUP consecutive list entries are kept per lane (acc[])
+// and summed over the wave's 64 pixels with one transpose through LDS,
+// instead of a cross-lane reduction per Gaussian.
 __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
                                                    const uint2 *__restrict__ ranges,
                                                    const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
                                                    uint32_t *__restrict__ acc_c,
                                                    unsigned long long *__restrict__ pairs) {
-    __shared__ float4 sA[WG];          // ux, uy, l11, l21
-    __shared__ float2 sB[WG];          // l22, o
-    __shared__ uint32_t sR[WG];        // record index
-    __shared__ float part[WAVES][WG];
-    __shared__ uint32_t cpart[WAVES][WG];
+    __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
+    __shared__ float2 wB[WAVES][LCAP];     // l22, o
+    __shared__ uint16_t wS[WAVES][LCAP];   // batch slot of the entry
+    __shared__ uint32_t sR[RB];            // record index of each batch slot
+    __shared__ int scnt[WAVES * WAVES];
+    __shared__ int slen[WAVES];
+    __shared__ float part[RB];
+    __shared__ uint32_t cpart[RB];
+    __shared__ float scr[WAVES][LGROUP][65];
 
     const int gt = blockIdx.x;
     const int vi = find_view(views, nv, gt);
@@ -79,65 +189,101 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     const int lt = gt - V.tile_base;
     const int ox = (lt % V.tiles_x) * TILE, oy = (lt / V.tiles_x) * TILE;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int lx = t & (TILE - 1), ly = t >> TILE_SHIFT;
-    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    bool done = (ox + lx >= V.w) || (oy + ly >= V.h);
-    float T = 1.0f;
+    int qx, qy;
+    quadrant_pixel(t, qx, qy);
+    const float px = (float)qx + 0.5f, py = (float)qy + 0.5f;
+    // transmittance; pixels outside the image start inactive (T = 0 < eps_T)
+    float T = (ox + qx < V.w && oy + qy < V.h) ? 1.0f : 0.0f;
     const uint2 rg = ranges[gt];
     uint32_t npairs = 0;
 
-    for (uint32_t b = rg.x; b < rg.y; b += WG) {
-        if (__syncthreads_count(!done) == 0) break;
+    for (uint32_t b = rg.x; b < rg.y; b += RB) {
+        if (__syncthreads_count(T >= eps_T) == 0) break;
         const uint32_t idx = b + t;
-        if (idx < rg.y) {
+        uint32_t mask = 0;
+        Rec R;
+        float ux = 0.f, uy = 0.f;
+        if (t < RB && idx < rg.y) {
             const uint32_t r = ival[idx];
-            const Rec R = rec[r];
-            float ux, uy;
+            R = rec[r];
             local_centre(R, ox, oy, ux, uy);
-            sA[t] = make_float4(ux, uy, R.l11, R.l21);
-            sB[t] = make_float2(R.l22, R.o);
             sR[t] = r;
+            mask = quadrant_mask(ux, uy, R.l11, R.l21, R.l22, qcut);
         }
+        if (t < RB) {
+            part[t] = 0.0f;
+            cpart[t] = 0u;
+        }
+        int pos[WAVES];
+        list_positions(mask, pos, scnt, slen);
 #pragma unroll
-        for (int ww = 0; ww < WAVES; ++ww) {
-            part[ww][t] = 0.0f;
-            cpart[ww][t] = 0u;
+        for (int q = 0; q < WAVES; ++q) {
+            if (pos[q] >= 0) {
+                wA[q][pos[q]] = make_float4(ux, uy, R.l11, R.l21);
+                wB[q][pos[q]] = make_float2(R.l22, R.o);
+                wS[q][pos[q]] = (uint16_t)t;
+            }
+        }
+        {
+            int q;
+            const int k = pad_slot(slen, q);
+            if (k >= 0) {
+                wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
+                wB[q][k] = make_float2(1.0f, 0.0f);
+                wS[q][k] = 0;
+            }
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)WG, rg.y - b);
-        for (int j = 0; j < cnt; ++j) {
-            const float4 A = sA[j];
-            const float2 B = sB[j];
-            const float dx = px - A.x, dy = py - A.y;
-            const float w1 = fmaf(A.z, dx, A.w * dy);
-            const float w2 = B.x * dy;
-            const float p = fmaf(w1, w1, w2 * w2);
-            const bool hit = (p <= qcut) && !done;
-            const unsigned long long bal = __ballot(hit);
-            if (bal) {
-                const float s = wave_sum(hit ? T : 0.0f);
-                if (lane == 0) {
-                    part[w][j] = s;
-                    cpart[w][j] = (uint32_t)__popcll(bal);
-                }
-                if (hit) {
-                    const float alpha = B.y * fast_exp2(-p);
+        const int len = __builtin_amdgcn_readfirstlane(slen[w]);
+        for (int i0 = 0; i0 < len; i0 += LGROUP) {
+            if (__builtin_amdgcn_ballot_w64(T >= eps_T) == 0) break;
+            float acc[LGROUP];
+            uint32_t cv = 0;
+#pragma unroll
+            for (int jj = 0; jj < LGROUP; ++jj) {
+                const float4 A = wA[w][i0 + jj];
+                const float2 B = wB[w][i0 + jj];
+                const float dx = px - A.x, dy = py - A.y;
+                const float w1 = fmaf(A.z, dx, A.w * dy);
+                const float w2 = B.x * dy;
+                const float p = fmaf(w1, w1, w2 * w2);
+                const bool ov = p <= qcut;
+                const bool hit = ov && (T >= eps_T);
+                acc[jj] = hit ? T : 0.0f;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
+                if (bal) {
+                    // alpha = 0 outside the ellipse, so T updates only where it overlaps
+                    const float alpha = B.y * fast_exp2(ov ? -p : -256.0f);
                     T = fmaf(-T, alpha, T);
-                    done = T < eps_T;
+                    cv = write_lane(cv, (uint32_t)__popcll(bal), jj);
                 }
+            }
+            // transpose: lane l sums pixels (l >> 4) * 16 .. + 15 of entry l & 15
+#pragma unroll
+            for (int jj = 0; jj < LGROUP; ++jj) scr[w][jj][lane] = acc[jj];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int gi = lane & (LGROUP - 1), qq = lane >> 4;
+            float sum = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sum += scr[w][gi][qq * 16 + q];
+            sum += __shfl_xor(sum, 16);
+            sum += __shfl_xor(sum, 32);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < LGROUP && cv > 0u) {
+                const int slot = wS[w][i0 + lane];
+                atomicAdd(&part[slot], sum);
+                atomicAdd(&cpart[slot], cv);
             }
         }
         __syncthreads();
+        const int cnt = (int)min((uint32_t)RB, rg.y - b);
         if (t < cnt) {
-            float s = 0.0f;
-            uint32_t c = 0;
-#pragma unroll
-            for (int ww = 0; ww < WAVES; ++ww) {
-                s += part[ww][t];
-                c += cpart[ww][t];
-            }
+            const uint32_t c = cpart[t];
             if (c) {
-                atomicAdd(&acc_T[sR[t]], s);
+                atomicAdd(&acc_T[sR[t]], part[t]);
                 atomicAdd(&acc_c[sR[t]], c);
                 npairs += c;
             }
@@ -154,8 +300,10 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                                                   const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   unsigned long long *__restrict__ pairs) {
-    __shared__ float4 sA[WG];          // ux, uy, l11, l21
-    __shared__ float4 sB[WG];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
+    __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21
+    __shared__ float4 wB[WAVES][LCAP];     // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
+    __shared__ int scnt[WAVES * WAVES];
+    __shared__ int slen[WAVES];
     __shared__ float red[WAVES];
 
     const int gt = blockIdx.x;
@@ -163,55 +311,81 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
     const int ox = (lt % V.tiles_x) * TILE, oy = (lt / V.tiles_x) * TILE;
-    const int t = threadIdx.x, w = t >> 6;
-    const int lx = t & (TILE - 1), ly = t >> TILE_SHIFT;
-    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const bool inside = (ox + lx < V.w) && (oy + ly < V.h);
-    bool done = !inside;
-    float T = 1.0f, H = 0.0f, w0 = 0.0f;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    int qx, qy;
+    quadrant_pixel(t, qx, qy);
+    const float px = (float)qx + 0.5f, py = (float)qy + 0.5f;
+    const bool inside = (ox + qx < V.w) && (oy + qy < V.h);
+    float T = inside ? 1.0f : 0.0f, H = 0.0f, w0 = 0.0f;
     uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
 
-    for (uint32_t b = rg.x; b < rg.y; b += WG) {
-        if (__syncthreads_count(!done) == 0) break;
+    for (uint32_t b = rg.x; b < rg.y; b += RB) {
+        if (__syncthreads_count(T >= u.eps_T) == 0) break;
         const uint32_t idx = b + t;
-        if (idx < rg.y) {
+        uint32_t mask = 0;
+        float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
+        if (t < RB && idx < rg.y) {
             const Rec R = rec[ival[idx]];
             float ux, uy;
             local_centre(R, ox, oy, ux, uy);
             const float v = R.v;
-            sA[t] = make_float4(ux, uy, R.l11, R.l21);
-            sB[t] = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
+            a4 = make_float4(ux, uy, R.l11, R.l21);
+            b4 = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
+            mask = quadrant_mask(ux, uy, R.l11, R.l21, R.l22, u.qcut);
+        }
+        int pos[WAVES];
+        list_positions(mask, pos, scnt, slen);
+#pragma unroll
+        for (int q = 0; q < WAVES; ++q) {
+            if (pos[q] >= 0) {
+                wA[q][pos[q]] = a4;
+                wB[q][pos[q]] = b4;
+            }
+        }
+        {
+            int q;
+            const int k = pad_slot(slen, q);
+            if (k >= 0) {
+                wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
+                wB[q][k] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+            }
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)WG, rg.y - b);
-        for (int j = 0; j < cnt; ++j) {
-            const float4 A = sA[j];
-            const float4 B = sB[j];
-            const float dx = px - A.x, dy = py - A.y;
-            const float w1 = fmaf(A.z, dx, A.w * dy);
-            const float w2 = B.x * dy;
-            const float p = fmaf(w1, w1, w2 * w2);
-            if (p <= u.qcut && !done) {
-                const float as = fmaf(B.y, fast_exp2(-p), B.z);    // alpha*
-                const float wt = as * T;                           // w*
-                const float x = wt * B.w;                          // w* v
-                const float lg = fast_log2(fmaxf(x, 1e-30f));
-                H = fmaf(x, fmaf(-LN2, lg, u.cQc), H);
-                w0 += wt - x;                                      // w* (1 - v)
-                T -= wt;                                           // T (1 - alpha*)
-                done = T < u.eps_T;
-                if (COUNT) ++npairs;
+        const int len = __builtin_amdgcn_readfirstlane(slen[w]);
+        for (int i0 = 0; i0 < len; i0 += 4) {
+            if (__builtin_amdgcn_ballot_w64(T >= u.eps_T) == 0) break;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 A = wA[w][i0 + k];
+                const float4 B = wB[w][i0 + k];
+                const float dx = px - A.x, dy = py - A.y;
+                const float w1 = fmaf(A.z, dx, A.w * dy);
+                const float w2 = B.x * dy;
+                const float p = fmaf(w1, w1, w2 * w2);
+                const bool hit = (p <= u.qcut) && (T >= u.eps_T);
+                if (__builtin_amdgcn_ballot_w64(hit)) {
+                    if (hit) {
+                        const float as = fmaf(B.y, fast_exp2(-p), B.z);    // alpha*
+                        const float wt = as * T;                           // w*
+                        const float x = wt * B.w;                          // w* v
+                        const float lg = fast_log2(fmaxf(x, 1e-30f));
+                        H = fmaf(x, fmaf(-LN2, lg, u.cQc), H);
+                        w0 += wt - x;                                      // w* (1 - v)
+                        T -= wt;                                           // T (1 - alpha*)
+                        if (COUNT) ++npairs;
+                    }
+                }
             }
         }
         __syncthreads();
     }
     if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
     if (!inside) H = 0.0f;
-    if (MAPS && inside) maps[V.pix_base + (int64_t)(oy + ly) * V.w + (ox + lx)] = H;
+    if (MAPS && inside) maps[V.pix_base + (int64_t)(oy + qy) * V.w + (ox + qx)] = H;
     const float s = wave_sum(H);
-    if ((t & 63) == 0) red[w] = s;
+    if (lane == 0) red[w] = s;
     __syncthreads();
     if (t == 0) {
         float tot = 0.0f;
@@ -309,7 +483,7 @@ __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__r
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = accumulate ? load_f((const TGam *)gamma, (int64_t)k * a.n + g) : 0.0f;
-    const uint32_t r0 = offs[g], r1 = min(offs[g + 1], st->R_eff);
+    const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t c = acc_c[r];
         if (c == 0) continue;

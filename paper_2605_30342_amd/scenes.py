@@ -245,6 +245,20 @@ def room_candidates(n, seed, extent, width, height, fov=90.0, height_m=1.5, marg
     return make_cameras(c, tgt, width, height, fov)
 
 
+def morton_order(scene: Scene, bits: int = 10) -> np.ndarray:
+    """Permutation that sorts the Gaussians along a 3D Morton (Z-order) curve,
+    so that consecutive blocks are spatially compact (block-anchored half
+    storage of the means relies on it)."""
+    lo = scene.means.min(0)
+    span = np.maximum(scene.means.max(0) - lo, 1e-9)
+    q = np.clip(((scene.means - lo) / span * ((1 << bits) - 1)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(scene.n, dtype=np.int64)
+    for b in range(bits):
+        for a in range(3):
+            code |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return np.argsort(code, kind="stable")
+
+
 def subset_scene(scene: Scene, idx) -> Scene:
     idx = np.asarray(idx)
     return Scene(scene.means[idx].copy(), scene.scales[idx].copy(), scene.quats[idx].copy(),
@@ -301,6 +315,7 @@ def workload(name: str, scale: float = 1.0) -> Workload:
         return Workload(name, sc, train, cand, 3)
     if name == "precision":
         sc = rooms_scene(s(3_000_000), 2, 2, seed=4000)
+        sc = subset_scene(sc, morton_order(sc))
         train = ellipse_path_cameras(s(300), 4001, 640, 480)
         cand = room_candidates(s(512), 4002, sc.extent, 320, 240)
         return Workload(name, sc, train, cand, 3)

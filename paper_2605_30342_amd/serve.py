@@ -1,0 +1,304 @@
+"""Continuous-batching query server over resident scenes.
+
+Scenes (Gaussians + visibility field) stay resident on the device.  Requests
+ask for the uncertainty scores of a set of candidate views of one scene.  The
+server keeps a FIFO of pending requests and a fixed number of slots (HIP
+streams).  Whenever a slot is free it forms a batch from the oldest pending
+request plus the following pending requests of the same scene (up to a view
+budget), asks the backend for the exact workspace size of that batch, and
+admits it if the bytes fit in the free memory budget; otherwise it waits for
+memory to come back (the oldest request is never bypassed, so large requests
+do not starve).  Batches of different scenes run concurrently on different
+slots.  Completion is detected by polling the slot's event; each request's
+latency is completion time minus arrival time.
+
+The backend is an interface, so the scheduling logic is tested on the CPU
+with a simulated backend (memory budget, completion times, failures) and
+runs on the GPU with `GpuBackend`.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Any, Dict, List, Optional
+
+import numpy as np
+
+PENDING, RUNNING, DONE, FAILED, CANCELLED, REJECTED = "pending", "running", "done", "failed", "cancelled", "rejected"
+
+
+@dataclass
+class Request:
+    rid: int
+    scene_id: Any
+    cams: Any                 # scenes.Cameras
+    t_arrival: float
+    status: str = PENDING
+    t_start: Optional[float] = None
+    t_done: Optional[float] = None
+    scores: Optional[np.ndarray] = None
+    error: Optional[str] = None
+
+    @property
+    def n_views(self) -> int:
+        return int(self.cams.n)
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+@dataclass
+class Batch:
+    reqs: List[Request]
+    slot: int
+    handle: Any
+    nbytes: int
+    t_launch: float
+
+
+class BackendError(RuntimeError):
+    pass
+
+
+class Server:
+    def __init__(self, backend, memory_budget: int, n_slots: int = 4, max_batch_views: int = 512,
+                 stuck_timeout: float = 30.0):
+        self.be = backend
+        self.budget = int(memory_budget)
+        self.in_use = 0
+        self.n_slots = n_slots
+        self.free_slots = list(range(n_slots))
+        self.max_batch_views = max_batch_views
+        self.stuck_timeout = stuck_timeout
+        self.pending: deque = deque()
+        self.running: List[Batch] = []
+        self.requests: Dict[int, Request] = {}
+        self._next = 0
+        self.batches_launched = 0
+        self.merged_requests = 0
+
+    # ---------------------------------------------------------------- client side
+    def submit(self, scene_id, cams, t_arrival: Optional[float] = None) -> int:
+        rid = self._next
+        self._next += 1
+        r = Request(rid, scene_id, cams, self.be.now() if t_arrival is None else t_arrival)
+        self.requests[rid] = r
+        self.pending.append(r)
+        return rid
+
+    def cancel(self, rid: int) -> bool:
+        r = self.requests.get(rid)
+        if r is None or r.status != PENDING:
+            return False
+        r.status = CANCELLED
+        self.pending = deque(x for x in self.pending if x.rid != rid)
+        return True
+
+    # ---------------------------------------------------------------- scheduling
+    def _form_batch(self) -> List[Request]:
+        head = self.pending[0]
+        batch, views = [head], head.n_views
+        for r in list(self.pending)[1:]:
+            if r.scene_id == head.scene_id and views + r.n_views <= self.max_batch_views:
+                batch.append(r)
+                views += r.n_views
+        return batch
+
+    def _admit(self) -> None:
+        while self.free_slots and self.pending:
+            batch = self._form_batch()
+            try:
+                nbytes = self.be.plan_bytes(batch[0].scene_id, [r.cams for r in batch])
+            except BackendError as e:
+                self._fail(batch, str(e))
+                continue
+            if nbytes > self.budget - self.in_use and len(batch) > 1:
+                batch = batch[:1]
+                try:
+                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams])
+                except BackendError as e:
+                    self._fail(batch, str(e))
+                    continue
+            if nbytes > self.budget:
+                for r in batch:
+                    r.status, r.error = REJECTED, f"needs {nbytes} bytes, budget {self.budget}"
+                    self.pending.remove(r)
+                continue
+            if nbytes > self.budget - self.in_use:
+                return                                   # wait for memory (FIFO head is not bypassed)
+            slot = self.free_slots.pop(0)
+            try:
+                handle = self.be.launch(batch[0].scene_id, [r.cams for r in batch], slot, nbytes)
+            except BackendError as e:
+                self.free_slots.append(slot)
+                self._fail(batch, str(e))
+                continue
+            t = self.be.now()
+            for r in batch:
+                self.pending.remove(r)
+                r.status, r.t_start = RUNNING, t
+            self.in_use += nbytes
+            self.running.append(Batch(batch, slot, handle, nbytes, t))
+            self.batches_launched += 1
+            self.merged_requests += len(batch) - 1
+
+    def _fail(self, batch: List[Request], msg: str) -> None:
+        for r in batch:
+            r.status, r.error = FAILED, msg
+            if r in self.pending:
+                self.pending.remove(r)
+
+    def _retire(self, b: Batch, status: str, scores=None, msg=None) -> None:
+        t = self.be.now()
+        off = 0
+        for r in b.reqs:
+            r.t_done = t
+            r.status = status
+            r.error = msg
+            if scores is not None:
+                r.scores = np.asarray(scores[off:off + r.n_views])
+            off += r.n_views
+        self.in_use -= b.nbytes
+        self.free_slots.append(b.slot)
+        self.be.release(b.handle)
+
+    def _poll(self) -> List[Request]:
+        finished = []
+        for b in list(self.running):
+            try:
+                ready = self.be.done(b.handle)
+            except BackendError as e:
+                self.running.remove(b)
+                self._retire(b, FAILED, msg=str(e))
+                finished += b.reqs
+                continue
+            if ready:
+                self.running.remove(b)
+                try:
+                    self._retire(b, DONE, scores=self.be.result(b.handle))
+                except BackendError as e:
+                    self._retire(b, FAILED, msg=str(e))
+                finished += b.reqs
+            elif self.be.now() - b.t_launch > self.stuck_timeout:
+                # the device work cannot be recalled; its requests fail and its
+                # slot and memory stay reserved until the backend reports done
+                for r in b.reqs:
+                    if r.status == RUNNING:
+                        r.status, r.error, r.t_done = FAILED, "timed out", self.be.now()
+        return finished
+
+    def step(self) -> List[Request]:
+        done = self._poll()
+        self._admit()
+        return done
+
+    def idle(self) -> bool:
+        return not self.pending and not self.running
+
+    def run_until_idle(self, timeout: float = 60.0, sleep: float = 0.0) -> None:
+        t0 = self.be.now()
+        while not self.idle():
+            self.step()
+            if self.be.now() - t0 > timeout:
+                raise TimeoutError("server did not drain")
+            self.be.wait(sleep)
+
+    # ---------------------------------------------------------------- stats
+    def stats(self) -> dict:
+        done = [r for r in self.requests.values() if r.status == DONE]
+        lat = np.array([r.latency for r in done]) if done else np.zeros(0)
+        views = sum(r.n_views for r in done)
+        if done:
+            span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
+        else:
+            span = 0.0
+        return {"requests_done": len(done), "views_done": views,
+                "p50_latency_ms": float(np.percentile(lat, 50) * 1e3) if done else None,
+                "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if done else None,
+                "views_per_s": views / span if span > 0 else None,
+                "batches": self.batches_launched, "merged_requests": self.merged_requests,
+                "failed": sum(r.status == FAILED for r in self.requests.values()),
+                "rejected": sum(r.status == REJECTED for r in self.requests.values())}
+
+
+# ==================================================================== GPU backend
+
+@dataclass
+class ResidentScene:
+    dsc: Any                  # api.DeviceScene
+    gamma: Any                # torch tensor [K, n]
+    sh_degree: int
+    n_train: int
+
+
+class GpuBackend:
+    """Runs batches through the C ABI, one HIP stream per slot."""
+
+    def __init__(self, ctx, n_slots: int = 4, params=None):
+        import torch
+        from . import _lib
+        self.torch = torch
+        self.ctx = ctx
+        self.scenes: Dict[Any, ResidentScene] = {}
+        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self.plan_stream = torch.cuda.Stream()
+        self.params = params if params is not None else _lib.default_uq_params()
+
+    def add_scene(self, scene_id, dsc, gamma, sh_degree: int, n_train: int) -> None:
+        self.scenes[scene_id] = ResidentScene(dsc, gamma, sh_degree, n_train)
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def wait(self, dt: float) -> None:
+        if dt > 0:
+            time.sleep(dt)
+
+    def _cams(self, cams_list):
+        from .scenes import Cameras
+        return cams_list[0] if len(cams_list) == 1 else Cameras.concat(cams_list)
+
+    def plan_bytes(self, scene_id, cams_list) -> int:
+        from ._lib import GvError
+        sc = self.scenes[scene_id]
+        try:
+            ws = self.ctx.query_workspace(sc.dsc, self._cams(cams_list), self.params, sc.sh_degree,
+                                          stream=self.plan_stream)
+        except GvError as e:
+            raise BackendError(str(e))
+        self._last_plan = (scene_id, ws)
+        return ws.nbytes
+
+    def launch(self, scene_id, cams_list, slot: int, nbytes: int):
+        from ._lib import GvError
+        torch = self.torch
+        sc = self.scenes[scene_id]
+        cams = self._cams(cams_list)
+        sid, ws = getattr(self, "_last_plan", (None, None))
+        if sid != scene_id or ws is None or ws.nbytes != nbytes:
+            ws = self.ctx.query_workspace(sc.dsc, cams, self.params, sc.sh_degree, stream=self.plan_stream)
+        s = self.streams[slot]
+        s.wait_stream(self.plan_stream)
+        with torch.cuda.stream(s):
+            try:
+                scores, _ = self.ctx.vf_query_views(sc.dsc, sc.gamma, sc.sh_degree, sc.n_train, cams, self.params,
+                                                    ws, stream=s)
+            except GvError as e:
+                raise BackendError(str(e))
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"ev": ev, "scores": scores, "ws": ws, "stream": s}
+
+    def done(self, h) -> bool:
+        return bool(h["ev"].query())
+
+    def result(self, h):
+        st, counts = self.ctx.check_workspace(h["ws"], stream=h["stream"])
+        if st != 0:
+            raise BackendError(f"workspace overflow {counts}")
+        return h["scores"].cpu().numpy()
+
+    def release(self, h) -> None:
+        h.clear()

@@ -312,3 +312,159 @@ def test_room_full_size_sampled(ctx):
     say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
     assert worst <= 1.0 and flagged < 0.02
     _check_scores(np.array([s[5], s[40]]), q, mp_sub)
+
+
+# ---------------------------------------------------------------- batching: graph replay
+
+def test_graph_replay_matches_eager(ctx, tiny, tiny_ref):
+    """The whole multi-view query captured once in a hipGraph and replayed:
+    every replay equals the eager call, also after the cameras change (same
+    resolutions) and with other eager work queued between replays."""
+    say("case: hipGraph capture/replay of vf_query_views")
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    g = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    prm_e = _lib.default_uq_params()
+    prm_g = _lib.default_uq_params(use_graph=1)
+    other = scenes.sphere_cameras(tiny.cand.n, 77, width=128, height=128)
+    ws = ctx.query_workspace(dsc, Cameras.concat([tiny.cand, other]), prm_e, 2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for it, cams in enumerate([tiny.cand, tiny.cand, other, tiny.cand, other]):
+            s_e, m_e = ctx.vf_query_views(dsc, g, 2, tiny.train.n, cams, prm_e, ws, want_maps=True)
+            s_e, m_e = s_e.clone(), m_e.clone()
+            junk = torch.randn(1 << 20, device="cuda").sum()          # unrelated eager work
+            s_g, m_g = ctx.vf_query_views(dsc, g, 2, tiny.train.n, cams, prm_g, ws, want_maps=True)
+            stream.synchronize()
+            assert torch.equal(s_g, s_e), it
+            assert torch.equal(m_g, m_e), it
+            del junk
+    # the default (legacy) stream works too: capture happens on a private stream
+    s_e, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm_e, ws)
+    s_e = s_e.clone()
+    s_g, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm_g, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(s_g, s_e)
+
+
+def test_batched_equals_per_view(ctx, tiny, tiny_ref):
+    """All candidates in one call equal one call per candidate."""
+    say("case: batched vs per-view query")
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    g = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    prm = _lib.default_uq_params()
+    ws = ctx.query_workspace(dsc, tiny.cand, prm, 2)
+    s_all, m_all = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws, want_maps=True)
+    s_all, m_all = s_all.clone(), m_all.clone()
+    off = 0
+    for v in range(tiny.cand.n):
+        s1, m1 = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand.subset([v]), prm, ws, want_maps=True)
+        torch.cuda.synchronize()
+        n = int(tiny.cand.wh[v, 0] * tiny.cand.wh[v, 1])
+        assert torch.equal(m1, m_all[off:off + n])
+        assert float(s1[0]) == pytest.approx(float(s_all[v]), rel=1e-6)
+        off += n
+
+
+# ---------------------------------------------------------------- precision: half storage
+
+def _dequantised(dsc, scene):
+    """The scene exactly as the half-storage kernels see it."""
+    import torch
+    return Scene(np.asarray(dsc.dequantised_means, np.float32), dsc.scales.float().cpu().numpy(),
+                 dsc.quats.float().cpu().numpy(), dsc.opacity.float().cpu().numpy(), scene.n_virtual, scene.extent)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_storage_matches_oracle_on_dequantised_inputs(ctx, dtype):
+    """FP16/BF16 attributes (means as half offsets from FP32 block anchors)
+    and half gamma, FP32 arithmetic: equal to the FP64 oracle run on the same
+    dequantised values, to the FP32 tolerances."""
+    say(f"case: {dtype} storage, room scene subset")
+    w = scenes.workload("room", scale=0.05)
+    sc = scenes.subset_scene(w.scene, scenes.morton_order(w.scene))
+    prm = oracle_params()
+    from paper_2605_30342_amd.api import DeviceScene
+    dsc = DeviceScene(sc, dtype=dtype)
+    deq = _dequantised(dsc, sc)
+    train = w.train.subset([0, 5])
+    b = oracle.vf_build(deq, train, 3, prm)
+    g = gpu_build(ctx, dsc, train, 3)
+    worst, _ = compare_gamma(g, b)
+    say(f"  gamma worst {worst:.3f}")
+    assert worst <= 1.0
+    # gamma stored in the same half type
+    import torch
+    gh = torch.from_numpy(b["gamma"].astype(np.float32)).to(
+        torch.float16 if dtype == "f16" else torch.bfloat16).float().numpy().astype(np.float64)
+    cand = w.cand.subset([0, 1])
+    q = oracle.vf_query(deq, gh, 3, train.n, cand, prm)
+    s, mp, _ = gpu_query(ctx, dsc, gh, 3, train.n, cand, gamma_dtype=dtype)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    # storage error against FP64 on the original FP32 inputs: reported, sanity-bounded
+    q32 = oracle.vf_query(sc, b["gamma"], 3, train.n, cand, prm)
+    rel = np.abs(s - q32["scores"]) / np.abs(q32["scores"])
+    say(f"  score error vs FP32 inputs: {rel}")
+    assert np.all(rel < 0.05)
+
+
+def test_half_gamma_output_of_build(ctx, tiny):
+    """vf_build writing gamma in FP16 / BF16 equals the FP32 result rounded."""
+    say("case: half gamma output")
+    import torch
+    dsc = _dsc(tiny.scene)
+    g32 = gpu_build(ctx, dsc, tiny.train, 2)
+    for dt, tt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        gh = gpu_build(ctx, dsc, tiny.train, 2, gamma_dtype=dt)
+        ref = torch.from_numpy(g32.astype(np.float32)).to(tt).float().numpy()
+        assert np.array_equal(gh.astype(np.float32), ref), dt
+
+
+# ---------------------------------------------------------------- serving
+
+def test_serving_results_alone_equal_results_in_the_mix(ctx):
+    """Requests of three resident scenes with mixed view counts and
+    resolutions, served with continuous batching on concurrent streams under
+    a memory budget: every request's scores equal the scores of the same
+    request run alone."""
+    say("case: continuous-batching server, alone vs mix")
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd.api import DeviceScene
+    from paper_2605_30342_amd.serve import DONE, GpuBackend, Server
+    be = GpuBackend(ctx, n_slots=3)
+    rng = np.random.default_rng(5)
+    for k in range(3):
+        sc = scenes.tiny_scene(1500 + 500 * k, seed=50 + k)
+        train = scenes.sphere_cameras(6, 60 + k, width=96, height=96)
+        dsc = DeviceScene(sc)
+        g = ctx.vf_build(dsc, train, 2)
+        be.add_scene(k, dsc, g, 2, train.n)
+    reqs = []
+    for i in range(14):
+        k = int(rng.integers(0, 3))
+        res = [(32, 24), (64, 48), (96, 96)][int(rng.integers(0, 3))]
+        cams = scenes.sphere_cameras(int(rng.integers(1, 6)), 100 + i, width=res[0], height=res[1])
+        reqs.append((k, cams))
+    srv = Server(be, memory_budget=64 << 20, n_slots=3, max_batch_views=12)
+    rids = [srv.submit(k, c) for k, c in reqs]
+    srv.run_until_idle(timeout=120.0)
+    torch.cuda.synchronize()
+    st = srv.stats()
+    say(f"  {st}")
+    assert st["merged_requests"] > 0
+    prm = _lib.default_uq_params()
+    for rid, (k, c) in zip(rids, reqs):
+        r = srv.requests[rid]
+        assert r.status == DONE, r.error
+        sc = be.scenes[k]
+        s, _ = ctx.vf_query_views(sc.dsc, sc.gamma, 2, sc.n_train, c, prm)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(r.scores, s.cpu().numpy(), rtol=1e-6, atol=1e-6)

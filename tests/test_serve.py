@@ -1,0 +1,179 @@
+"""Scheduling logic of the continuous-batching server on the CPU, with a
+simulated backend (virtual clock, memory sizes, completion times, failures)."""
+import numpy as np
+import pytest
+
+from paper_2605_30342_amd import scenes
+from paper_2605_30342_amd.serve import (CANCELLED, DONE, FAILED, REJECTED, BackendError, Server)
+
+
+class FakeBackend:
+    """Batch duration = fixed + per-view time; workspace = per-view bytes.
+    Scores are deterministic per (scene, camera) so mixing can be checked."""
+
+    def __init__(self, bytes_per_view=100, t_fixed=1.0, t_view=0.1, fail_plan=(), fail_launch=(), stuck=()):
+        self.t = 0.0
+        self.bpv = bytes_per_view
+        self.t_fixed, self.t_view = t_fixed, t_view
+        self.fail_plan, self.fail_launch, self.stuck = set(fail_plan), set(fail_launch), set(stuck)
+        self.launches = []
+        self.live = {}
+
+    def now(self):
+        return self.t
+
+    def wait(self, dt):
+        self.t += max(dt, 0.01)
+
+    def plan_bytes(self, scene_id, cams_list):
+        if scene_id in self.fail_plan:
+            raise BackendError("plan failed")
+        return self.bpv * sum(c.n for c in cams_list)
+
+    def launch(self, scene_id, cams_list, slot, nbytes):
+        if scene_id in self.fail_launch:
+            raise BackendError("out of memory")
+        assert slot not in self.live, "slot reused while busy"
+        nv = sum(c.n for c in cams_list)
+        h = {"slot": slot, "end": self.t + self.t_fixed + self.t_view * nv,
+             "scores": np.concatenate([self.score(scene_id, c) for c in cams_list]), "scene": scene_id}
+        self.live[slot] = h
+        self.launches.append((scene_id, nv, slot))
+        return h
+
+    def done(self, h):
+        if h["scene"] in self.stuck:
+            return False
+        return self.t >= h["end"]
+
+    def result(self, h):
+        return h["scores"]
+
+    def release(self, h):
+        self.live.pop(h["slot"], None)
+
+    @staticmethod
+    def score(scene_id, cams):
+        return cams.K[:, 0].astype(np.float64) * 0 + cams.t[:, 0] * 1000 + hash(scene_id) % 97
+
+
+def cams(n, seed):
+    return scenes.room_candidates(n, seed, ((0, 6), (0, 4), (0, 3)), 32, 24)
+
+
+def test_all_requests_complete_with_their_own_scores():
+    be = FakeBackend()
+    srv = Server(be, memory_budget=10_000, n_slots=2, max_batch_views=64)
+    rids = [srv.submit(f"s{i % 3}", cams(4 + i % 5, i)) for i in range(20)]
+    srv.run_until_idle(timeout=1e4)
+    for i, rid in enumerate(rids):
+        r = srv.requests[rid]
+        assert r.status == DONE
+        np.testing.assert_array_equal(r.scores, FakeBackend.score(f"s{i % 3}", r.cams))
+        assert r.latency >= be.t_fixed
+
+
+def test_same_scene_requests_are_merged_and_different_scenes_overlap():
+    be = FakeBackend()
+    srv = Server(be, memory_budget=100_000, n_slots=2, max_batch_views=64)
+    for i in range(6):
+        srv.submit("A", cams(4, i))
+    srv.submit("B", cams(4, 99))
+    srv.step()
+    # first batch: all six A requests merged; second slot: scene B concurrently
+    assert be.launches[0] == ("A", 24, 0)
+    assert be.launches[1] == ("B", 4, 1)
+    assert srv.merged_requests == 5
+    srv.run_until_idle(timeout=1e4)
+    assert all(r.status == DONE for r in srv.requests.values())
+
+
+def test_admission_respects_the_memory_budget():
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=1000, n_slots=4, max_batch_views=64)
+    for i in range(4):
+        srv.submit(f"s{i}", cams(6, i))        # 600 bytes each: only one fits at a time
+    srv.step()
+    assert len(srv.running) == 1 and srv.in_use == 600
+    peak = 0
+    while not srv.idle():
+        srv.step()
+        peak = max(peak, srv.in_use)
+        assert srv.in_use <= 1000
+        be.wait(0.05)
+    assert peak == 600
+    assert all(r.status == DONE for r in srv.requests.values())
+
+
+def test_large_head_request_is_not_starved():
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=1000, n_slots=4, max_batch_views=64)
+    srv.submit("small0", cams(2, 0))
+    srv.submit("big", cams(9, 1))               # 900 bytes: needs the memory of everything else
+    for i in range(5):
+        srv.submit(f"small{i + 1}", cams(2, 10 + i))
+    srv.run_until_idle(timeout=1e4)
+    order = [s for s, _, _ in be.launches]
+    assert order.index("big") == 1               # admitted right after the head, before later smalls
+    assert srv.requests[1].status == DONE
+
+
+def test_too_large_request_is_rejected_and_others_proceed():
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=500, n_slots=2)
+    big = srv.submit("x", cams(8, 0))
+    ok = srv.submit("y", cams(2, 1))
+    srv.run_until_idle(timeout=1e4)
+    assert srv.requests[big].status == REJECTED
+    assert srv.requests[ok].status == DONE
+
+
+def test_backend_failures_fail_only_their_requests():
+    be = FakeBackend(fail_plan={"bad_plan"}, fail_launch={"oom"})
+    srv = Server(be, memory_budget=10_000, n_slots=2)
+    a = srv.submit("bad_plan", cams(2, 0))
+    b = srv.submit("oom", cams(2, 1))
+    c = srv.submit("good", cams(2, 2))
+    srv.run_until_idle(timeout=1e4)
+    assert srv.requests[a].status == FAILED and srv.requests[b].status == FAILED
+    assert srv.requests[c].status == DONE
+    assert srv.in_use == 0 and sorted(srv.free_slots) == [0, 1]
+
+
+def test_cancel_pending_request():
+    be = FakeBackend()
+    srv = Server(be, memory_budget=10_000, n_slots=1)
+    a = srv.submit("A", cams(2, 0))
+    b = srv.submit("B", cams(2, 1))
+    srv.step()                                   # A runs on the only slot, B pending
+    assert srv.cancel(b)
+    assert not srv.cancel(a)                     # running requests cannot be cancelled
+    srv.run_until_idle(timeout=1e4)
+    assert srv.requests[a].status == DONE and srv.requests[b].status == CANCELLED
+
+
+def test_stuck_batch_times_out_without_freeing_its_slot():
+    be = FakeBackend(stuck={"stuck"})
+    srv = Server(be, memory_budget=10_000, n_slots=2, stuck_timeout=5.0)
+    a = srv.submit("stuck", cams(2, 0))
+    b = srv.submit("fine", cams(2, 1))
+    for _ in range(1000):
+        srv.step()
+        be.wait(0.05)
+        if srv.requests[a].status == FAILED and srv.requests[b].status == DONE:
+            break
+    assert srv.requests[a].status == FAILED and srv.requests[a].error == "timed out"
+    assert srv.requests[b].status == DONE
+    assert len(srv.running) == 1                 # the stuck batch still holds its slot
+
+
+def test_latency_stats():
+    be = FakeBackend()
+    srv = Server(be, memory_budget=10_000, n_slots=2)
+    for i in range(10):
+        srv.submit("A" if i % 2 else "B", cams(3, i), t_arrival=0.0)
+    srv.run_until_idle(timeout=1e4)
+    st = srv.stats()
+    assert st["requests_done"] == 10 and st["views_done"] == 30
+    assert st["p50_latency_ms"] <= st["p99_latency_ms"]
+    assert st["views_per_s"] > 0
