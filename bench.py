@@ -58,6 +58,54 @@ def traffic_for(kernel: str):
     return e.get("bytes_per_launch")
 
 
+def serving_bench(ctx, w, dsc, gamma, L, log):
+    """Poisson stream of candidate-view requests over three resident scenes:
+    continuous batching (3 slots, same-scene merging) against a plain queue
+    (one slot, one request at a time)."""
+    import numpy as np
+    import torch
+    from paper_2605_30342_amd import scenes
+    from paper_2605_30342_amd.api import DeviceScene
+    from paper_2605_30342_amd.serve import GpuBackend, Server, replay
+    resident = {"room200k": (dsc, gamma, w.train.n)}
+    for name, n, seed in (("room100k", 100_000, 2100), ("room50k", 50_000, 2200)):
+        sc = scenes.rooms_scene(n, 1, 1, seed=seed)
+        tr = scenes.ellipse_path_cameras(24, seed + 1, 400, 400)
+        d = DeviceScene(sc)
+        resident[name] = (d, ctx.vf_build(d, tr, L), tr.n)
+    names = list(resident)
+    classes = ((160, 120), (320, 240), (400, 400))
+    pool = []
+    rng = np.random.default_rng(77)
+    for i in range(96):
+        nv = int(np.exp(rng.uniform(np.log(16), np.log(64))))
+        wh = classes[int(rng.integers(0, 3))]
+        pool.append((names[int(rng.integers(0, 3))], scenes.room_candidates(nv, 9000 + i, w.scene.extent, *wh)))
+    out = {"requests": len(pool), "views": int(sum(c.n for _, c in pool)), "memory_budget_gib": 8, "rates": {}}
+    backends = {}
+    for label, slots in (("continuous_batching", 3), ("plain_queue", 1)):
+        be = GpuBackend(ctx, n_slots=slots)
+        for k, (d, g, nt) in resident.items():
+            be.add_scene(k, d, g, L, nt)
+        backends[label] = (be, slots)
+    for rate in (300.0, 3000.0, 30000.0):          # Poisson arrivals, requests per second
+        rr = np.random.default_rng(int(rate))
+        t, arrivals = 0.0, []
+        for sid, cams in pool:
+            t += rr.exponential(1.0 / rate)
+            arrivals.append((t, sid, cams))
+        res = {}
+        for label, (be, slots) in backends.items():
+            maxv = 256 if slots > 1 else 0
+            replay(Server(be, memory_budget=8 << 30, n_slots=slots, max_batch_views=maxv), arrivals[:8])
+            torch.cuda.synchronize()
+            st = replay(Server(be, memory_budget=8 << 30, n_slots=slots, max_batch_views=maxv), arrivals)
+            res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            log(f"serving rate {rate:.0f}/s {label}: {res[label]}")
+        out["rates"][str(int(rate))] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +114,9 @@ def main():
     ap.add_argument("--workload", default="room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=24, help="candidate views the CPU baseline runs")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the timed steps (for counter collection): no batching/precision/serving sections")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -179,17 +230,23 @@ def main():
         uq_frac = {"achieved": round(a, 3), "peak": round(VALU_PEAK_TOPS, 2), "frac": round(a / VALU_PEAK_TOPS, 4),
                    "avg_launch_ms": round(per_launch["raster_uq"], 4), "pairs": int(pairs_uq)}
 
+    if args.profile_only:
+        print(json.dumps({"stages_ms_per_launch": per_launch, "pairs": [int(pairs_vis), int(pairs_uq)]}), flush=True)
+        ctx.close()
+        return
+
     # batching: the same candidates as one call per view (plain form), as one
     # call for all views, and as one replay of the captured graph
     def timed(fn, reps=5):
         for _ in range(2):
             fn()
         torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e0.record(cur)
         for _ in range(reps):
             fn()
-        e1.record(stream)
+        e1.record(cur)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
     singles = [w.cand.subset([v]) for v in range(w.cand.n)]
@@ -209,6 +266,38 @@ def main():
                 "graph_replay_ms": round(graph_ms, 4), "speedup_batched_vs_plain": round(plain_ms / batched_ms, 3),
                 "speedup_graph_vs_plain": round(plain_ms / graph_ms, 3)}
     log(f"batching {batching}")
+
+    # precision: attributes and gamma stored in FP16 / BF16, FP32 arithmetic
+    # (the scene is Morton-ordered so that each 256-Gaussian anchor block is compact)
+    precision = {}
+    order = scenes.morton_order(w.scene)
+    sm = scenes.subset_scene(w.scene, order)
+    dm = DeviceScene(sm)
+    gm = gamma[:, torch.from_numpy(order).cuda()].contiguous()
+    wsm = ctx.query_workspace(dm, w.cand, uprm, L)
+    s32 = torch.empty_like(scores)
+    t32 = timed(lambda: ctx.vf_query_views(dm, gm, L, w.train.n, w.cand, uprm, wsm, scores=s32))
+    precision["f32"] = {"query_ms": round(t32, 4), "mpix_s": round(px / (t32 / 1e3) / 1e6, 3),
+                        "scene_bytes": dm.nbytes() + gm.numel() * 4}
+    for dt in ("f16", "bf16"):
+        dh = DeviceScene(sm, dtype=dt)
+        gh = gm.to(torch.float16 if dt == "f16" else torch.bfloat16)
+        wsh = ctx.query_workspace(dh, w.cand, uprm, L)
+        sh = torch.empty_like(scores)
+        t_ms = timed(lambda: ctx.vf_query_views(dh, gh, L, w.train.n, w.cand, uprm, wsh, scores=sh))
+        torch.cuda.synchronize()
+        rel = ((sh.double() - s32.double()).abs() / s32.double().abs())
+        precision[dt] = {"query_ms": round(t_ms, 4), "mpix_s": round(px / (t_ms / 1e3) / 1e6, 3),
+                         "max_rel_score_diff_vs_f32": float(rel.max().item()),
+                         "median_rel_score_diff_vs_f32": float(rel.median().item()),
+                         "scene_bytes": dh.nbytes() + gh.numel() * gh.element_size()}
+        del dh, gh, wsh
+    del dm, gm, wsm
+    log(f"precision {precision}")
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(ctx, w, dsc, gamma, L, log)
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * 2**20 // 4
@@ -259,6 +348,8 @@ def main():
         "roofline": roof,
         "raster_uq_roofline": uq_frac,
         "batching": batching,
+        "precision": precision,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     ctx.close()

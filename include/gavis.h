@@ -162,6 +162,18 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
                    const gv_vf_params *params, void *gamma, gv_dtype gamma_dtype,
                    const gv_workspace *plan, void *workspace, void *hip_stream);
 
+/* Multi-view visibility of the visibility-field density control (Alg. 5):
+ * visibility[g] = 1 - prod over the training views of (1 - v_p[g]), with
+ * v_p[g] the single-view particle visibility of Alg. 2 (device, float [n]).
+ * Virtual particles are passed as ordinary Gaussians with opacity 0: they are
+ * measured but never occlude.  Uses the workspace plan of vf_build (same
+ * scene, views and params).  Enqueue only, except between passes when
+ * views_per_pass splits the views (then it synchronises to check capacity).
+ * The caller keeps the virtual particles with visibility <= eps_v (0.95). */
+gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                                  const gv_vf_params *params, float *visibility, const gv_workspace *plan,
+                                  void *workspace, void *hip_stream);
+
 /* Workspace for vf_query_views over `n_cand` candidate views. */
 gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *cand,
                                   int32_t n_cand, const gv_uq_params *params, int32_t sh_degree,
@@ -189,6 +201,18 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
  * GV_ERR_CAPACITY on overflow. */
 gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace,
                              int64_t out[4], void *hip_stream);
+
+/* Launch schedule of the blend kernels, chosen per workload class by the
+ * autotuner: the number of depth-ordered records a tile stages into LDS per
+ * batch (64, 128 or 256) for the VF CONST and VF QUERY blends.  Larger
+ * batches need fewer barriers, smaller ones use less LDS (more resident
+ * workgroups).  Results do not depend on the choice.  Defaults 128 / 128. */
+typedef struct {
+    int32_t vis_batch;
+    int32_t uq_batch;
+} gv_tuning;
+gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t);
+gv_status gv_get_tuning(const gv_context *ctx, gv_tuning *t);
 
 /* Stage timing for measurement.  While enabled, the context records a pair
  * of HIP events around each stage of every call on the call's stream.

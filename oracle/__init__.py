@@ -60,6 +60,8 @@ def lib():
         L.ora_vf_query.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
                                    d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
         L.ora_vf_query.restype = ctypes.c_int
+        L.ora_multiview_visibility.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, d, d, d, d, i32, vp, vp]
+        L.ora_multiview_visibility.restype = ctypes.c_int
         L.ora_argmax.argtypes = [vp, i32]
         L.ora_argmax.restype = i32
         _lib = L
@@ -209,6 +211,27 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
         off += n
     return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
             "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+
+
+def multiview_visibility(scene, cams, prm: Params = Params(), gather_mode: int = 0):
+    """Alg. 5's multi-view visibility 1 - prod_p (1 - v_p[g]) for every
+    Gaussian (v_p from Alg. 2).  Returns (vis [n], allowance [n])."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    vis = np.zeros(scene.n)
+    allow = np.zeros(scene.n)
+    rc = lib().ora_multiview_visibility(scene.n, _p(m), _p(s), _p(q), _p(o), cams.n, _p(R), _p(t), _p(K), _p(wh),
+                                        prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode, _p(vis), _p(allow))
+    if rc:
+        raise RuntimeError("oracle multiview_visibility failed")
+    return vis, allow
+
+
+def density_control_keep(vis, n_real: int, eps_v: float = 0.95):
+    """Alg. 5's pruning rule: a virtual particle (index >= n_real) is kept
+    when its multi-view visibility is at most eps_v."""
+    vis = np.asarray(vis)
+    return np.nonzero(vis[n_real:] <= eps_v)[0] + n_real
 
 
 def argmax(scores) -> int:

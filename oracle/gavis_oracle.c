@@ -778,3 +778,46 @@ int32_t ora_argmax(const double *scores, int32_t n)
     }
     return best;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Multi-view visibility for density control (Alg. 5)                        */
+/* ------------------------------------------------------------------------ */
+
+/* For every Gaussian: 1 - prod_p (1 - v_p[g]) with v_p from Alg. 2 over all
+ * Gaussians of the scene (virtual particles carry opacity 0, so they are
+ * measured but never occlude).  allow[g] (optional) bounds the change a
+ * near-tie decision can cause: |d(1 - prod)| <= sum_p |d v_p|. */
+int ora_multiview_visibility(int64_t n, const double *means, const double *scales, const double *quats,
+                             const double *opac, int32_t n_views, const double *camR, const double *camT,
+                             const double *camK, const int32_t *camWH, double eps_T, double znear, double lowpass,
+                             double cut, int32_t gather_mode, double *vis, double *allow)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    oproj *P = (oproj *)malloc(sizeof(oproj) * nn);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    double *pert = (double *)malloc(sizeof(double) * nn);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * nn);
+    double *prod = (double *)malloc(sizeof(double) * nn);
+    int rc = 0;
+    if (!P || !v || !pert || !cnt || !prod) { rc = -1; goto done; }
+    for (int64_t g = 0; g < n; ++g) { prod[g] = 1.0; if (allow) allow[g] = 0.0; }
+    for (int32_t p = 0; p < n_views; ++p) {
+        ocam c;
+        load_cam(&c, &camR[9 * p], &camT[3 * p], &camK[4 * p], &camWH[2 * p]);
+#pragma omp parallel for schedule(static)
+        for (int64_t g = 0; g < n; ++g)
+            project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
+        if (single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v, cnt, pert, NULL, NULL)) {
+            rc = -1;
+            goto done;
+        }
+        for (int64_t g = 0; g < n; ++g) {
+            prod[g] *= (1.0 - v[g]);
+            if (allow) allow[g] += pert[g];
+        }
+    }
+    for (int64_t g = 0; g < n; ++g) vis[g] = 1.0 - prod[g];
+done:
+    free(P); free(v); free(pert); free(cnt); free(prod);
+    return rc;
+}

@@ -22,7 +22,8 @@ EXPORTS = (
     "gv_create", "gv_destroy", "gv_last_error", "gv_default_vf_params", "gv_default_uq_params",
     "vf_build_workspace_size", "vf_build", "vf_query_workspace_size", "vf_query_views",
     "gv_workspace_check", "gv_workspace_bytes", "select_next_view",
-    "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name",
+    "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name", "vf_multiview_visibility",
+    "gv_set_tuning", "gv_get_tuning",
 )
 GV_PROFILE_STAGES = 9
 
@@ -56,6 +57,10 @@ class gv_uq_params(ctypes.Structure):
                 ("half_logdet_Qc", ctypes.c_float), ("eps_T", ctypes.c_float), ("znear", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("cut", ctypes.c_float), ("write_maps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("count_pairs", ctypes.c_int32)]
+
+
+class gv_tuning(ctypes.Structure):
+    _fields_ = [("vis_batch", ctypes.c_int32), ("uq_batch", ctypes.c_int32)]
 
 
 class gv_workspace(ctypes.Structure):
@@ -94,6 +99,9 @@ def load(path: str = LIB_PATH):
     L.vf_build.argtypes = [vp, P(gv_gaussians), P(gv_camera), i32, P(gv_vf_params), vp, ctypes.c_int,
                            P(gv_workspace), vp, vp]
     L.vf_build.restype = st
+    L.vf_multiview_visibility.argtypes = [vp, P(gv_gaussians), P(gv_camera), i32, P(gv_vf_params), vp,
+                                          P(gv_workspace), vp, vp]
+    L.vf_multiview_visibility.restype = st
     L.vf_query_workspace_size.argtypes = [vp, P(gv_gaussians), P(gv_camera), i32, P(gv_uq_params), i32,
                                           P(gv_workspace), vp]
     L.vf_query_workspace_size.restype = st
@@ -106,6 +114,10 @@ def load(path: str = LIB_PATH):
     L.gv_workspace_bytes.restype = ctypes.c_size_t
     L.select_next_view.argtypes = [vp, vp, i32, P(i32), vp]
     L.select_next_view.restype = st
+    L.gv_set_tuning.argtypes = [vp, P(gv_tuning)]
+    L.gv_set_tuning.restype = st
+    L.gv_get_tuning.argtypes = [vp, P(gv_tuning)]
+    L.gv_get_tuning.restype = st
     L.gv_profile_enable.argtypes = [vp, i32]
     L.gv_profile_enable.restype = st
     L.gv_profile_read.argtypes = [vp, P(ctypes.c_double), P(i64), vp]

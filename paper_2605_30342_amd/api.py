@@ -176,11 +176,35 @@ class Context:
                                     ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
         return scores, maps
 
+    def multiview_visibility(self, dsc: DeviceScene, cams, params: Optional[_lib.gv_vf_params] = None,
+                             ws: Optional[Workspace] = None, out: Optional[torch.Tensor] = None,
+                             stream=None) -> torch.Tensor:
+        """1 - prod_p (1 - v_p[g]) over the views (Alg. 5), float [n]."""
+        if params is None:
+            params = _lib.default_vf_params()
+        if ws is None:
+            ws = self.build_workspace(dsc, cams, params, stream)
+        if out is None:
+            out = torch.empty(dsc.n, dtype=torch.float32, device=f"cuda:{self.device}")
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_multiview_visibility(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params),
+                                             _ptr(out), ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
+        return out
+
     def check_workspace(self, ws: Workspace, stream=None):
         """(status, (records, instances, overflow flags, pairs composited))."""
         out = (ctypes.c_int64 * 4)()
         st = self.L.gv_workspace_check(self.h, ctypes.byref(ws.plan), _ptr(ws.buf), out, _stream(stream))
         return st, (int(out[0]), int(out[1]), int(out[2]), int(out[3]))
+
+    def set_tuning(self, vis_batch: int = 128, uq_batch: int = 128):
+        t = _lib.gv_tuning(vis_batch, uq_batch)
+        check(self.L.gv_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = _lib.gv_tuning()
+        check(self.L.gv_get_tuning(self.h, ctypes.byref(t)))
+        return {"vis_batch": t.vis_batch, "uq_batch": t.uq_batch}
 
     def profile(self, on: bool = True):
         check(self.L.gv_profile_enable(self.h, 1 if on else 0))
@@ -197,6 +221,58 @@ class Context:
         check(self.L.select_next_view(self.h, _ptr(scores), int(scores.numel()), ctypes.byref(best),
                                       _stream(stream)))
         return int(best.value)
+
+
+# ---------------------------------------------------------------- density control (Alg. 5)
+
+def virtual_particle_count(extent, rho: float = 100.0) -> int:
+    """N_virt = floor(rho * scene volume)."""
+    vol = float(np.prod([hi - lo for lo, hi in extent]))
+    return int(np.floor(rho * vol))
+
+
+def virtual_particle_scale(rho: float = 100.0, eta: float = 0.5) -> float:
+    """Isotropic scale s with (4/3) pi s^3 rho = 1 + eta."""
+    return float((3.0 * (1.0 + eta) / (4.0 * np.pi * rho)) ** (1.0 / 3.0))
+
+
+def virtual_particles(extent, u: np.ndarray, rho: float = 100.0, eta: float = 0.5):
+    """Virtual particles at lo + u (hi - lo) (u: uniform draws in [0, 1)^3,
+    at least N_virt rows), identity rotation, scale s, opacity 0."""
+    from .scenes import Scene
+    n = virtual_particle_count(extent, rho)
+    lo = np.array([e[0] for e in extent], dtype=np.float64)
+    hi = np.array([e[1] for e in extent], dtype=np.float64)
+    means = lo + np.asarray(u[:n], dtype=np.float64) * (hi - lo)
+    sc = virtual_particle_scale(rho, eta)
+    return Scene(means.astype(np.float32), np.full((n, 3), sc, np.float32),
+                 np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), np.zeros(n, np.float32), 0, tuple(extent))
+
+
+def append_virtual(real, virt, keep=None):
+    """Scene made of the real Gaussians followed by the (kept) virtual ones,
+    marked as the n_virtual tail."""
+    from .scenes import Scene
+    idx = np.arange(virt.n) if keep is None else np.asarray(keep)
+    return Scene(np.concatenate([real.means, virt.means[idx]]), np.concatenate([real.scales, virt.scales[idx]]),
+                 np.concatenate([real.quats, virt.quats[idx]]), np.concatenate([real.opacity, virt.opacity[idx]]),
+                 int(len(idx)), real.extent)
+
+
+def density_control(ctx: "Context", scene, train, u: np.ndarray, rho: float = 100.0, eta: float = 0.5,
+                    eps_v: float = 0.95, params=None):
+    """Alg. 5: sample virtual particles, measure their multi-view visibility
+    against the scene (transparent, on the GPU), keep those with visibility
+    <= eps_v.  Returns (augmented scene with the kept particles as its
+    n_virtual tail, visibility of every candidate particle)."""
+    virt = virtual_particles(scene.extent, u, rho, eta)
+    allp = append_virtual(scene, virt)
+    dsc = DeviceScene(allp)
+    vis = ctx.multiview_visibility(dsc, train, params)
+    torch.cuda.synchronize()
+    v = vis[scene.n:].cpu().numpy()
+    keep = np.nonzero(v <= eps_v)[0]
+    return append_virtual(scene, virt, keep), v
 
 
 def split_maps(maps: torch.Tensor, cams):

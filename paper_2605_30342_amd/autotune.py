@@ -1,0 +1,110 @@
+"""Autotuner for the blend launch schedule.
+
+The blends stage a tile's depth-ordered records through LDS in batches of
+64, 128 or 256 (`gv_tuning`): larger batches need fewer workgroup barriers,
+smaller ones leave room for more resident workgroups per CU.  Which wins
+depends on the workload (list lengths per tile, image sizes, Gaussian
+footprints), so the tuner times each candidate on the caller's actual
+workload, checks that the outputs are identical, and caches the winner per
+workload class in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Optional
+
+import torch
+
+CANDIDATES = (64, 128, 256)
+
+
+def workload_class(mode: str, n_gaussians: int, cams) -> str:
+    """Coarse key: operation, log2 of the Gaussian count, of the mean pixels
+    per view and of the view count."""
+    def b(x):
+        return int(round(math.log2(max(x, 1))))
+    return f"{mode}:n{b(n_gaussians)}:px{b(cams.pixels() / max(cams.n, 1))}:v{b(cams.n)}"
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+class Autotuner:
+    def __init__(self, ctx, cache_path: Optional[str] = None):
+        self.ctx = ctx
+        self.path = cache_path
+        self.table: Dict[str, dict] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.table = json.load(f)
+
+    def save(self) -> None:
+        if self.path:
+            with open(self.path, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+
+    def tune_query(self, dsc, gamma, sh_degree: int, n_train: int, cams, params, ws, reps: int = 3) -> dict:
+        key = workload_class("query", dsc.n, cams)
+        if key in self.table:
+            return self.table[key]
+        base = self.ctx.get_tuning()
+        times, ref = {}, None
+        scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        for bsz in CANDIDATES:
+            self.ctx.set_tuning(base["vis_batch"], bsz)
+            times[bsz] = _time(lambda: self.ctx.vf_query_views(dsc, gamma, sh_degree, n_train, cams, params, ws,
+                                                               scores=scores), reps)
+            out = scores.clone()
+            if ref is None:
+                ref = out
+            elif not torch.equal(out, ref):
+                raise RuntimeError(f"query results differ between batch sizes ({bsz})")
+        best = min(times, key=times.get)
+        self.ctx.set_tuning(base["vis_batch"], best)
+        self.table[key] = {"uq_batch": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        return self.table[key]
+
+    def tune_build(self, dsc, cams, params, ws, gamma, reps: int = 2) -> dict:
+        key = workload_class("build", dsc.n, cams)
+        if key in self.table:
+            return self.table[key]
+        base = self.ctx.get_tuning()
+        times, ref = {}, None
+        for bsz in CANDIDATES:
+            self.ctx.set_tuning(bsz, base["uq_batch"])
+            times[bsz] = _time(lambda: self.ctx.vf_build(dsc, cams, params.sh_degree, params, ws, gamma), reps)
+            out = gamma.clone()
+            if ref is None:
+                ref = out
+            else:
+                # float atomics may add in another order: compare to FP32 rounding
+                scale = ref.abs().amax(dim=0, keepdim=True) + 1e-30
+                if ((out - ref).abs() > 1e-5 * scale).any():
+                    raise RuntimeError(f"build results differ between batch sizes ({bsz})")
+        best = min(times, key=times.get)
+        self.ctx.set_tuning(best, base["uq_batch"])
+        self.table[key] = {"vis_batch": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        return self.table[key]
+
+    def apply(self, mode: str, n_gaussians: int, cams) -> bool:
+        e = self.table.get(workload_class(mode, n_gaussians, cams))
+        if not e:
+            return False
+        t = self.ctx.get_tuning()
+        if mode == "query":
+            t["uq_batch"] = e["uq_batch"]
+        else:
+            t["vis_batch"] = e["vis_batch"]
+        self.ctx.set_tuning(t["vis_batch"], t["uq_batch"])
+        return True

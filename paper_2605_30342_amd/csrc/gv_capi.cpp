@@ -188,6 +188,7 @@ struct gv_context {
     };
     std::vector<Graph> graphs;
     bool capturing = false;
+    gv_tuning tuning = {128, 128};
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     // stage timing
     bool prof_on = false;
@@ -608,7 +609,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              &st->measure[0], s);
+                              &st->measure[0], ctx->tuning.vis_batch, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -628,6 +629,68 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         acc = true;
     }
     if (half_out) launch_convert(gam32, 0, gamma, (int)gamma_dtype, (uint64_t)g->n * K, s);
+    GV_HIP(hipGetLastError());
+    return GV_OK;
+}
+
+gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                                  const gv_vf_params *prm, float *visibility, const gv_workspace *plan,
+                                  void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_train < 0 || (n_train > 0 && !train)) return fail(GV_ERR_INVALID_ARG, "bad training views");
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    if (g->n > 0 && !visibility) return fail(GV_ERR_INVALID_ARG, "visibility is NULL");
+    if (!plan || !workspace) return fail(GV_ERR_INVALID_ARG, "NULL workspace or plan");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (g->n == 0) return GV_OK;
+    if (n_train == 0) {
+        launch_fill_u32(reinterpret_cast<uint32_t *>(visibility), (uint64_t)g->n, 0u, s);
+        GV_HIP(hipGetLastError());
+        return GV_OK;
+    }
+    const int32_t vp = prm->views_per_pass > 0 ? std::min(prm->views_per_pass, n_train) : n_train;
+    const Layout Lay = make_layout(*plan);
+    const GaussArgs a = gargs(g);
+    const GeomArgs geo{prm->znear, prm->lowpass, prm->cut};
+    const float qcut = (float)(0.5 * prm->cut / std::log(2.0));
+    bool acc = false;
+    for (int32_t v0 = 0; v0 < n_train; v0 += vp) {
+        const int32_t nv = std::min(vp, n_train - v0);
+        std::vector<ViewDev> &views = ctx->host_views;
+        int64_t tiles, pixels;
+        GV_TRY(make_views(train + v0, nv, views, tiles, pixels));
+        GV_TRY(plan_check(plan, workspace, 0, g->n, nv, tiles, pixels));
+        GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
+                              hipMemcpyHostToDevice, s));
+        Binned bz;
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, false, 0, nullptr, 0, 0.f, s, bz));
+        Status *st = at<Status>(workspace, Lay.status);
+        float *accT = at<float>(workspace, Lay.accT);
+        uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
+        launch_fill_dev_u32(reinterpret_cast<uint32_t *>(accT), &st->R_eff, 1, 0u, s);
+        launch_fill_dev_u32(accC, &st->R_eff, 1, 0u, s);
+        {
+            StageScope sc(ctx, ST_RASTER_VIS, s);
+            launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
+                              bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
+                              &st->measure[0], ctx->tuning.vis_batch, s);
+        }
+        {
+            StageScope sc(ctx, ST_ACCUM, s);
+            launch_vis_logsum(g->n, at<uint32_t>(workspace, Lay.offs), accT, accC, st, visibility, acc, s);
+        }
+        GV_HIP(hipGetLastError());
+        if (v0 + vp < n_train) {
+            Status h;
+            GV_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+            GV_HIP(hipStreamSynchronize(s));
+            if (h.overflow) return fail(GV_ERR_CAPACITY, "workspace too small for views %d..%d", v0, v0 + nv - 1);
+        }
+        acc = true;
+    }
+    launch_vis_finish(g->n, visibility, s);
     GV_HIP(hipGetLastError());
     return GV_OK;
 }
@@ -683,7 +746,7 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
                              bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, mp,
-                             prm->count_pairs ? &st->measure[0] : nullptr, s);
+                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
         return GV_OK;
@@ -699,7 +762,7 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     struct Key {
         const void *ws, *gamma, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
         int64_t n, n_virtual, n_train, rcap, mcap, tiles, nbytes;
-        int32_t n_cand, sh, gdt, dtype, anchor_block, count;
+        int32_t n_cand, sh, gdt, dtype, anchor_block, count, uq_batch;
         float f[8];
     } key;
     std::memset(&key, 0, sizeof(key));
@@ -708,7 +771,7 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     key.n = g->n; key.n_virtual = g->n_virtual; key.n_train = n_train; key.rcap = plan->max_records;
     key.mcap = plan->max_instances; key.tiles = tiles; key.nbytes = (int64_t)plan->bytes;
     key.n_cand = n_cand; key.sh = sh_degree; key.gdt = (int)gamma_dtype; key.dtype = (int)g->dtype;
-    key.anchor_block = g->anchor_block; key.count = prm->count_pairs;
+    key.anchor_block = g->anchor_block; key.count = prm->count_pairs; key.uq_batch = ctx->tuning.uq_batch;
     const float fv[8] = {prm->beta, prm->o0, prm->half_logdet_Q0, prm->half_logdet_Qc, prm->eps_T, prm->znear,
                          prm->lowpass, prm->cut};
     std::memcpy(key.f, fv, sizeof(fv));
@@ -795,6 +858,20 @@ gv_status gv_profile_read(gv_context *ctx, double *ms, int64_t *calls, void *hip
         ctx->prof_pool.push_back(e.b);
     }
     ctx->prof_pending.clear();
+    return GV_OK;
+}
+
+gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t) {
+    if (!ctx || !t) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
+    if (!ok(t->vis_batch) || !ok(t->uq_batch)) return fail(GV_ERR_INVALID_ARG, "batch sizes must be 64, 128 or 256");
+    ctx->tuning = *t;
+    return GV_OK;
+}
+
+gv_status gv_get_tuning(const gv_context *ctx, gv_tuning *t) {
+    if (!ctx || !t) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    *t = ctx->tuning;
     return GV_OK;
 }
 

@@ -118,11 +118,10 @@ __device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, f
     return m;
 }
 
-// Records staged per batch, and the capacity of a per-quadrant list (the
-// lists are padded with never-hit entries up to a multiple of LGROUP).
-constexpr int RB = 128;
+// Records staged per batch (RB, a launch-time choice: 64, 128 or 256) and the
+// padding granule of a per-quadrant list (lists are padded with never-hit
+// entries up to a multiple of LGROUP).
 constexpr int LGROUP = 16;
-constexpr int LCAP = RB + LGROUP;
 
 // Positions of this thread's record in the four per-quadrant lists, each in
 // batch (= depth) order; -1 where the record does not touch the quadrant.
@@ -167,12 +166,14 @@ __device__ __forceinline__ int pad_slot(const int *slen, int &q) {
 // Contributions of LGROUP consecutive list entries are kept per lane (acc[])
 // and summed over the wave's 64 pixels with one transpose through LDS,
 // instead of a cross-lane reduction per Gaussian.
+template <int RB>
 __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
                                                    const uint2 *__restrict__ ranges,
                                                    const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
                                                    uint32_t *__restrict__ acc_c,
                                                    unsigned long long *__restrict__ pairs) {
+    constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
     __shared__ uint16_t wS[WAVES][LCAP];   // batch slot of the entry
@@ -294,12 +295,13 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
 
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
 
-template <bool MAPS, bool COUNT>
+template <int RB, bool MAPS, bool COUNT>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   unsigned long long *__restrict__ pairs) {
+    constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21
     __shared__ float4 wB[WAVES][LCAP];     // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
     __shared__ int scnt[WAVES * WAVES];
@@ -507,6 +509,46 @@ __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__r
     for (int k = 0; k < K; ++k) store_f(gamma, (int64_t)k * a.n + g, acc[k]);
 }
 
+// ---------------------------------------------------------------- multi-view visibility (Alg. 5)
+
+// out[g] += sum over this pass's views of log(1 - v_p[g]), v_p = sum T / count
+// (a view that reaches no pixel of g contributes log 1 = 0).
+__global__ __launch_bounds__(WG) void k_vis_logsum(int64_t n, const uint32_t *__restrict__ offs,
+                                                   const float *__restrict__ acc_T,
+                                                   const uint32_t *__restrict__ acc_c, const Status *__restrict__ st,
+                                                   float *__restrict__ out, bool accumulate) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= n) return;
+    if (st->overflow) return;
+    float s = accumulate ? out[g] : 0.0f;
+    const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t c = acc_c[r];
+        if (c == 0) continue;
+        const float v = fminf(acc_T[r] / (float)c, 1.0f);
+        s += log1pf(-v);
+    }
+    out[g] = s;
+}
+
+// out[g] = 1 - exp(out[g]) = 1 - prod_p (1 - v_p[g]).
+__global__ __launch_bounds__(WG) void k_vis_finish(int64_t n, float *__restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (g < n) out[g] = 1.0f - expf(out[g]);
+}
+
+void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
+                       float *out, bool accumulate, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_vis_logsum, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, n, offs, acc_T, acc_c, st,
+                       out, accumulate);
+}
+
+void launch_vis_finish(int64_t n, float *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_vis_finish, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, n, out);
+}
+
 // ---------------------------------------------------------------- dtype conversion
 
 template <typename TS, typename TD>
@@ -536,27 +578,49 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 
 // ---------------------------------------------------------------- launchers
 
+template <int RB>
+static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                          const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
+                          unsigned long long *pairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
+                       acc_T, acc_c, pairs);
+}
+
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                       unsigned long long *pairs, hipStream_t s) {
+                       unsigned long long *pairs, int batch, hipStream_t s) {
     if (total_tiles <= 0) return;
-    hipLaunchKernelGGL(k_raster_vis, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
-                       acc_T, acc_c, pairs);
+    switch (batch) {
+    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
+    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
+    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
+    }
+}
+
+template <int RB>
+static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                         const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
+                         hipStream_t s) {
+    const dim3 g(total_tiles), b(WG);
+    if (maps && pairs)
+        hipLaunchKernelGGL((k_raster_uq<RB, true, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    else if (maps)
+        hipLaunchKernelGGL((k_raster_uq<RB, true, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    else if (pairs)
+        hipLaunchKernelGGL((k_raster_uq<RB, false, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    else
+        hipLaunchKernelGGL((k_raster_uq<RB, false, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
-                      hipStream_t s) {
+                      int batch, hipStream_t s) {
     if (total_tiles <= 0) return;
-    const dim3 g(total_tiles), b(WG);
-    if (maps && pairs)
-        hipLaunchKernelGGL((k_raster_uq<true, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
-    else if (maps)
-        hipLaunchKernelGGL((k_raster_uq<true, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
-    else if (pairs)
-        hipLaunchKernelGGL((k_raster_uq<false, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
-    else
-        hipLaunchKernelGGL((k_raster_uq<false, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+    switch (batch) {
+    case 64: raster_uq_rb<64>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
+    case 256: raster_uq_rb<256>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
+    default: raster_uq_rb<128>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
+    }
 }
 
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,

@@ -259,6 +259,12 @@ def morton_order(scene: Scene, bits: int = 10) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
+def uniform_draws(n: int, seed: int) -> np.ndarray:
+    """n seeded samples of U[0, 1)^3 (the random positions density control
+    draws are passed in from here)."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, size=(n, 3))
+
+
 def subset_scene(scene: Scene, idx) -> Scene:
     idx = np.asarray(idx)
     return Scene(scene.means[idx].copy(), scene.scales[idx].copy(), scene.quats[idx].copy(),

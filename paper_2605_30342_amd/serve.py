@@ -154,11 +154,12 @@ class Server:
         t = self.be.now()
         off = 0
         for r in b.reqs:
-            r.t_done = t
-            r.status = status
-            r.error = msg
-            if scores is not None:
-                r.scores = np.asarray(scores[off:off + r.n_views])
+            if r.status == RUNNING:          # requests already failed by a time-out stay failed
+                r.t_done = t
+                r.status = status
+                r.error = msg
+                if scores is not None:
+                    r.scores = np.asarray(scores[off:off + r.n_views])
             off += r.n_views
         self.in_use -= b.nbytes
         self.free_slots.append(b.slot)
@@ -221,6 +222,27 @@ class Server:
                 "batches": self.batches_launched, "merged_requests": self.merged_requests,
                 "failed": sum(r.status == FAILED for r in self.requests.values()),
                 "rejected": sum(r.status == REJECTED for r in self.requests.values())}
+
+
+def replay(server: Server, arrivals, timeout: float = 120.0) -> dict:
+    """Submits (t_offset, scene_id, cams) requests at their arrival times
+    (relative to the start, on the backend's clock), stepping the server in
+    between, and returns its statistics once everything has drained."""
+    be = server.be
+    t0 = be.now()
+    queue = sorted(arrivals, key=lambda a: a[0])
+    i = 0
+    while i < len(queue) or not server.idle():
+        now = be.now() - t0
+        while i < len(queue) and queue[i][0] <= now:
+            server.submit(queue[i][1], queue[i][2], t_arrival=t0 + queue[i][0])
+            i += 1
+        server.step()
+        if be.now() - t0 > timeout:
+            raise TimeoutError("replay did not drain")
+        if i < len(queue) and server.idle():
+            be.wait(min(queue[i][0] - (be.now() - t0), 1e-3))
+    return server.stats()
 
 
 # ==================================================================== GPU backend

@@ -427,3 +427,38 @@ def test_argmax_lowest_index_on_ties():
     assert oracle.argmax([1.0, 3.0, 3.0, 2.0]) == 1
     assert oracle.argmax([float("nan"), -1.0]) == 1
     assert oracle.argmax([-5.0]) == 0
+
+
+# ---------------------------------------------------------------- density control (Alg. 5)
+
+def test_virtual_particle_constants():
+    """N_virt = floor(rho Vol) and (4/3) pi s^3 rho = 1 + eta (rho = 100, eta = 0.5)."""
+    from paper_2605_30342_amd.api import virtual_particle_count, virtual_particle_scale
+    assert virtual_particle_count(((0, 6), (0, 4), (0, 3)), 100.0) == 7200
+    s = virtual_particle_scale(100.0, 0.5)
+    assert 4.0 / 3.0 * math.pi * s ** 3 * 100.0 == pytest.approx(1.5, rel=1e-12)
+    assert s == pytest.approx(0.152992, abs=1e-6)
+
+
+def test_multiview_visibility_special_cases():
+    """A transparent (opacity 0) particle alone in view has v = 1 (T = 1 on
+    every reached pixel), so its multi-view visibility is 1 and it is pruned;
+    behind a 50 % occluder on a single pixel it has v = 1/2 per view, so two
+    identical views give 1 - (1/2)^2 = 3/4; behind three opaque occluders it
+    is never reached (0, kept).  A particle of opacity 0 never occludes."""
+    cam1 = axis_camera(1, 1, 50.0)
+    from paper_2605_30342_amd.scenes import Cameras
+    cam2 = Cameras(np.repeat(cam1.R, 2, 0), np.repeat(cam1.t, 2, 0), np.repeat(cam1.K, 2, 0), np.repeat(cam1.wh, 2, 0))
+    sc = stack_scene([2.0], [0.0], scale=0.01)
+    vis, _ = oracle.multiview_visibility(sc, cam2)
+    assert vis[0] == 1.0
+    sc = stack_scene([1.0, 2.0], [0.5, 0.0], scale=0.01)       # occluder alpha = 1/2 at the pixel centre
+    vis, _ = oracle.multiview_visibility(sc, cam2)
+    assert vis[1] == pytest.approx(0.75, rel=1e-12)
+    sc = stack_scene([1.0, 1.1, 1.2, 2.0], [0.99, 0.99, 0.99, 0.0], scale=0.01)
+    vis, _ = oracle.multiview_visibility(sc, cam2)
+    assert vis[3] == 0.0
+    assert list(oracle.density_control_keep(vis, 3)) == [3]
+    sc = stack_scene([1.0, 2.0], [0.0, 0.7], scale=0.01)       # transparent in front of a real one
+    v, c, _ = oracle.single_view(sc, cam1, 0)
+    assert v[1] == 1.0
