@@ -15,6 +15,8 @@
 // Workgroup = one 16x16 tile, 256 threads, one pixel per lane.  The tile's
 // list is staged through LDS in batches of 256 records; a batch loop stops
 // as soon as every pixel of the tile has terminated.
+#include <type_traits>
+
 #include "gv_device.hpp"
 #include "gv_launch.hpp"
 
@@ -59,34 +61,44 @@ __device__ __forceinline__ void local_centre(const Rec &R, int ox, int oy, float
     uy = (float)(ay - oy) + R.fy;
 }
 
-// Lane `lane` of v takes the uniform value x (v_writelane_b32 ignores EXEC;
-// the lane select must be an inline constant, so the switch below folds to a
-// single instruction once the caller's loop is unrolled).
 template <int J>
 __device__ __forceinline__ uint32_t write_lane_c(uint32_t v, uint32_t x) {
     asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "i"(J));
     return v;
 }
 
-__device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t x, int lane) {
-    switch (lane) {
-    case 0: return write_lane_c<0>(v, x);
-    case 1: return write_lane_c<1>(v, x);
-    case 2: return write_lane_c<2>(v, x);
-    case 3: return write_lane_c<3>(v, x);
-    case 4: return write_lane_c<4>(v, x);
-    case 5: return write_lane_c<5>(v, x);
-    case 6: return write_lane_c<6>(v, x);
-    case 7: return write_lane_c<7>(v, x);
-    case 8: return write_lane_c<8>(v, x);
-    case 9: return write_lane_c<9>(v, x);
-    case 10: return write_lane_c<10>(v, x);
-    case 11: return write_lane_c<11>(v, x);
-    case 12: return write_lane_c<12>(v, x);
-    case 13: return write_lane_c<13>(v, x);
-    case 14: return write_lane_c<14>(v, x);
-    default: return write_lane_c<15>(v, x);
+// Compile-time loop: f(std::integral_constant<int, J>{}) for J = I .. N-1.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
     }
+}
+
+// x as held by lane J of this lane's row of 16 (DPP row broadcast).  Used as
+// the first operand of a VALU instruction, the compiler folds the broadcast
+// into that instruction, so a value staged once per row costs no extra move.
+template <int J>
+__device__ __forceinline__ float row_bcast(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + J, 0xF, 0xF, true));
+}
+
+// c + a_J b, where a_J is a in lane J of this lane's row of 16 (the compiler
+// does not fold a broadcast into v_fmac, so it is written out; the s_nop
+// provides the two wait states a DPP read needs after a VALU write of a).
+template <int J>
+__device__ __forceinline__ float fmac_row_bcast(float c, float a, float b) {
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(c)
+        : "v"(a), "v"(b), "i"(J));
+    return c;
+}
+
+// x from the lane of this lane's quad that the DPP quad_perm control CTRL selects.
+template <int CTRL>
+__device__ __forceinline__ float quad_perm_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
 // ---------------------------------------------------------------- batch staging
@@ -105,9 +117,10 @@ __device__ __forceinline__ void quadrant_pixel(int t, int &qx, int &qy) {
 // (L L^T)^-1, so sigma_xx = (b^2 + c^2) / (a c)^2 and sigma_yy = 1 / c^2, and
 // the box is sqrt(qcut sigma) wide (widened slightly to stay conservative).
 __device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, float b, float c, float qcut) {
-    const float ic = 1.0f / c;
-    const float rx = sqrtf(qcut * fmaf(b, b, c * c)) * ic / a * 1.001f + 0.01f;
-    const float ry = sqrtf(qcut) * ic * 1.001f + 0.01f;
+    // hardware reciprocal and square root (about 1 ulp): the 0.1% widening covers them
+    const float ic = __builtin_amdgcn_rcpf(c);
+    const float rx = __builtin_amdgcn_sqrtf(qcut * fmaf(b, b, c * c)) * ic * __builtin_amdgcn_rcpf(a) * 1.001f + 0.01f;
+    const float ry = __builtin_amdgcn_sqrtf(qcut) * ic * 1.001f + 0.01f;
     uint32_t m = 0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
@@ -122,6 +135,10 @@ __device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, f
 // padding granule of a per-quadrant list (lists are padded with never-hit
 // entries up to a multiple of LGROUP).
 constexpr int LGROUP = 16;
+// Row stride (floats) of the per-wave transpose buffer: a multiple of 4 so that
+// 16-byte reads stay aligned, and 4 mod 64 banks so that the four quads'
+// reads of one pass fall in different banks.
+constexpr int SCR_STRIDE = 68;
 
 // Positions of this thread's record in the four per-quadrant lists, each in
 // batch (= depth) order; -1 where the record does not touch the quadrant.
@@ -182,7 +199,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     __shared__ int slen[WAVES];
     __shared__ float part[RB];
     __shared__ uint32_t cpart[RB];
-    __shared__ float scr[WAVES][LGROUP][65];
+    __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
 
     const int gt = blockIdx.x;
     const int vi = find_view(views, nv, gt);
@@ -236,45 +253,47 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
         }
         __syncthreads();
         const int len = __builtin_amdgcn_readfirstlane(slen[w]);
+        const int jl = lane & (LGROUP - 1);
         for (int i0 = 0; i0 < len; i0 += LGROUP) {
             if (__builtin_amdgcn_ballot_w64(T >= eps_T) == 0) break;
+            // lane j of every row loads entry i0 + j; entry jj then reaches all
+            // 64 pixels by row broadcast, so LDS is read once per 16 entries
+            const float4 A = wA[w][i0 + jl];
+            const float2 B = wB[w][i0 + jl];
             float acc[LGROUP];
+            // hit counts of the group, 8 bits per entry (at most 64 hits)
             uint32_t cv = 0;
-#pragma unroll
-            for (int jj = 0; jj < LGROUP; ++jj) {
-                const float4 A = wA[w][i0 + jj];
-                const float2 B = wB[w][i0 + jj];
-                const float dx = px - A.x, dy = py - A.y;
-                const float w1 = fmaf(A.z, dx, A.w * dy);
-                const float w2 = B.x * dy;
+            static_for<0, LGROUP>([&](auto jc) {
+                constexpr int jj = decltype(jc)::value;
+                // centre minus pixel: the sign flip leaves the quadratic form unchanged
+                const float ex = row_bcast<jj>(A.x) - px, ey = row_bcast<jj>(A.y) - py;
+                const float w1 = fmac_row_bcast<jj>(row_bcast<jj>(A.z) * ex, A.w, ey);
+                const float w2 = row_bcast<jj>(B.x) * ey;
                 const float p = fmaf(w1, w1, w2 * w2);
-                const bool ov = p <= qcut;
-                const bool hit = ov && (T >= eps_T);
-                acc[jj] = hit ? T : 0.0f;
-                const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
-                if (bal) {
-                    // alpha = 0 outside the ellipse, so T updates only where it overlaps
-                    const float alpha = B.y * fast_exp2(ov ? -p : -256.0f);
-                    T = fmaf(-T, alpha, T);
-                    cv = write_lane(cv, (uint32_t)__popcll(bal), jj);
-                }
-            }
-            // transpose: lane l sums pixels (l >> 4) * 16 .. + 15 of entry l & 15
+                const bool ov = p <= qcut, live = T >= eps_T;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(ov) & __builtin_amdgcn_ballot_w64(live);
+                const float a = (ov && live) ? T : 0.0f;
+                acc[jj] = a;
+                // T (1 - alpha), alpha = o 2^-p; a = 0 leaves T unchanged where there is no hit
+                T = fmaf(-a, row_bcast<jj>(B.y) * fast_exp2(-p), T);
+                cv = write_lane_c<4 * jj>(cv, (uint32_t)__popcll(bal));
+            });
 #pragma unroll
             for (int jj = 0; jj < LGROUP; ++jj) scr[w][jj][lane] = acc[jj];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int gi = lane & (LGROUP - 1), qq = lane >> 4;
-            float sum = 0.0f;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sum += scr[w][gi][qq * 16 + q];
-            sum += __shfl_xor(sum, 16);
-            sum += __shfl_xor(sum, 32);
+            const int ge = lane >> 2, gc = lane & 3;
+            const float4 *row = reinterpret_cast<const float4 *>(&scr[w][ge][gc * 16]);
+            const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
+            float sum = ((r0.x + r0.y) + (r0.z + r0.w)) + ((r1.x + r1.y) + (r1.z + r1.w)) +
+                        (((r2.x + r2.y) + (r2.z + r2.w)) + ((r3.x + r3.y) + (r3.z + r3.w)));
+            sum += quad_perm_f<0xB1>(sum);
+            sum += quad_perm_f<0x4E>(sum);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (lane < LGROUP && cv > 0u) {
-                const int slot = wS[w][i0 + lane];
+            if (gc == 0 && cv > 0u) {
+                const int slot = wS[w][i0 + ge];
                 atomicAdd(&part[slot], sum);
                 atomicAdd(&cpart[slot], cv);
             }
@@ -318,7 +337,9 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     quadrant_pixel(t, qx, qy);
     const float px = (float)qx + 0.5f, py = (float)qy + 0.5f;
     const bool inside = (ox + qx < V.w) && (oy + qy < V.h);
-    float T = inside ? 1.0f : 0.0f, H = 0.0f, w0 = 0.0f;
+    // per pixel: sx = sum w* v, sxl = sum w* v log2(w* v), sw = sum w*; the
+    // entropy bound is formed from them after the last Gaussian
+    float T = inside ? 1.0f : 0.0f, sx = 0.0f, sxl = 0.0f, sw = 0.0f;
     uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
@@ -356,33 +377,40 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         }
         __syncthreads();
         const int len = __builtin_amdgcn_readfirstlane(slen[w]);
-        for (int i0 = 0; i0 < len; i0 += 4) {
+        const int jl = lane & (LGROUP - 1);
+        for (int i0 = 0; i0 < len; i0 += LGROUP) {
             if (__builtin_amdgcn_ballot_w64(T >= u.eps_T) == 0) break;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float4 A = wA[w][i0 + k];
-                const float4 B = wB[w][i0 + k];
-                const float dx = px - A.x, dy = py - A.y;
-                const float w1 = fmaf(A.z, dx, A.w * dy);
-                const float w2 = B.x * dy;
+            const float4 A = wA[w][i0 + jl];
+            const float4 B = wB[w][i0 + jl];
+            static_for<0, LGROUP>([&](auto jc) {
+                // products and sums are rounded separately, so that every
+                // broadcast operand folds into its instruction
+#pragma clang fp contract(off)
+                constexpr int jj = decltype(jc)::value;
+                const float ex = row_bcast<jj>(A.x) - px, ey = row_bcast<jj>(A.y) - py;
+                const float w1 = fmac_row_bcast<jj>(row_bcast<jj>(A.z) * ex, A.w, ey);
+                const float w2 = row_bcast<jj>(B.x) * ey;
                 const float p = fmaf(w1, w1, w2 * w2);
-                const bool hit = (p <= u.qcut) && (T >= u.eps_T);
-                if (__builtin_amdgcn_ballot_w64(hit)) {
-                    if (hit) {
-                        const float as = fmaf(B.y, fast_exp2(-p), B.z);    // alpha*
-                        const float wt = as * T;                           // w*
-                        const float x = wt * B.w;                          // w* v
-                        const float lg = fast_log2(fmaxf(x, 1e-30f));
-                        H = fmaf(x, fmaf(-LN2, lg, u.cQc), H);
-                        w0 += wt - x;                                      // w* (1 - v)
-                        T -= wt;                                           // T (1 - alpha*)
-                        if (COUNT) ++npairs;
-                    }
+                const bool ov = p <= u.qcut, live = T >= u.eps_T;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(ov) & __builtin_amdgcn_ballot_w64(live);
+                if (bal) {
+                    const bool hit = ov && live;
+                    const float as = row_bcast<jj>(B.z) + row_bcast<jj>(B.y) * fast_exp2(-p);      // alpha*
+                    const float wt = hit ? as * T : 0.0f;                                            // w*
+                    const float x = row_bcast<jj>(B.w) * wt;                                         // w* v
+                    sxl = fmaf(x, fast_log2(fmaxf(x, 1e-30f)), sxl);
+                    sx += x;
+                    sw += wt;
+                    T -= wt;                                                                         // T (1 - alpha*)
+                    if (COUNT) npairs += hit ? 1u : 0u;
                 }
-            }
+            });
         }
         __syncthreads();
     }
+    // H = sum_hits x (cQc - ln x) + w0 (cQ0 - ln w0), w0 = sum w* (1 - v) = sw - sx >= 0
+    float H = fmaf(u.cQc, sx, -LN2 * sxl);
+    const float w0 = sw - sx;
     if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
     if (!inside) H = 0.0f;
     if (MAPS && inside) maps[V.pix_base + (int64_t)(oy + qy) * V.w + (ox + qx)] = H;

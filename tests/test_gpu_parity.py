@@ -422,9 +422,17 @@ def test_half_gamma_output_of_build(ctx, tiny):
     dsc = _dsc(tiny.scene)
     g32 = gpu_build(ctx, dsc, tiny.train, 2)
     for dt, tt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
-        gh = gpu_build(ctx, dsc, tiny.train, 2, gamma_dtype=dt)
+        gh = gpu_build(ctx, dsc, tiny.train, 2, gamma_dtype=dt).astype(np.float32)
         ref = torch.from_numpy(g32.astype(np.float32)).to(tt).float().numpy()
-        assert np.array_equal(gh.astype(np.float32), ref), dt
+        # the two builds add float atomics in different orders, so an FP32
+        # value next to a rounding boundary of the half format may round to
+        # the neighbouring half value; everything else must match exactly
+        mant, emin = (10, -14) if dt == "f16" else (7, -126)
+        e = np.floor(np.log2(np.maximum(np.abs(ref), 2.0 ** emin)))
+        ulp = np.exp2(e - mant)
+        diff = np.abs(gh - ref)
+        assert np.all(diff <= ulp), dt
+        assert np.mean(diff == 0) >= 0.99, (dt, np.mean(diff == 0))
 
 
 # ---------------------------------------------------------------- serving
