@@ -431,8 +431,10 @@ __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ i
 // scanned digit-major; block b then walks its chunk tile by tile.  In a tile,
 // wave w owns pairs [w * 512, (w + 1) * 512) and loads all eight of its keys
 // per lane up front; it ranks equal digits with ballot matching, sub-round by
-// sub-round, against wave-private LDS counters (no barrier), and one
-// block-wide step turns the four waves' counts into output offsets.
+// sub-round, against wave-private LDS counters (no barrier).  One block-wide
+// step turns the four waves' counts into slots of the tile sorted by digit;
+// the tile is staged in LDS in that order and written out so that
+// consecutive lanes store consecutive positions of each digit's run.
 constexpr int RITEMS = 8;
 constexpr int RTILE = WG * RITEMS;
 constexpr int RWAVE = 64 * RITEMS;
@@ -501,28 +503,39 @@ __global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, 
     if (threadIdx.x == WG - 1) dtot[blockIdx.x] = buf[WG - 1];
 }
 
+// Exclusive prefix sum over the block's 256 threads (one value each).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wtot[w] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) base += ww < w ? wtot[ww] : 0u;
+    return base + inc - x;
+}
+
 __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                       const uint32_t *n_dev, int shift, int nbits,
                                                       const uint32_t *__restrict__ hist,
                                                       const uint32_t *__restrict__ dtot) {
-    __shared__ uint32_t run[RADIX];
-    __shared__ uint32_t wcnt[WAVES][RADIX];
-    __shared__ uint32_t scan[RADIX];
+    __shared__ uint32_t run[RADIX];          // output position of this block's next pair of each digit
+    __shared__ uint32_t wcnt[WAVES][RADIX];  // wave counts, then wave offsets inside the digit
+    __shared__ uint32_t lbase[RADIX];        // first slot of each digit in the staged tile
+    __shared__ uint32_t goff[RADIX];         // output position minus staged slot, per digit
+    __shared__ uint32_t wtot[WAVES];
+    __shared__ uint32_t sk[RTILE], sv[RTILE];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     {   // digit bases: exclusive scan of the digit totals plus this block's offset
         const uint32_t d = dtot[t];
-        scan[t] = d;
-        __syncthreads();
-        for (int off = 1; off < RADIX; off <<= 1) {
-            const uint32_t y = t >= off ? scan[t - off] : 0u;
-            __syncthreads();
-            scan[t] += y;
-            __syncthreads();
-        }
-        run[t] = scan[t] - d + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
+        run[t] = block_excl_scan(d, wtot) + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
     }
-    __syncthreads();
     uint64_t start, end;
     radix_chunk(*n_dev, start, end);
     const uint32_t mask = (1u << nbits) - 1u;
@@ -562,28 +575,41 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         __syncthreads();
-        {   // digit t: offsets of the four waves, then advance the running base
-            uint32_t acc = run[t];
+        {   // digit t: wave offsets inside the digit, the digit's staged slot and output base
+            uint32_t c[WAVES], tot = 0;
 #pragma unroll
             for (int ww = 0; ww < WAVES; ++ww) {
-                const uint32_t c = wcnt[ww][t];
-                wcnt[ww][t] = acc;
-                acc += c;
+                c[ww] = wcnt[ww][t];
+                wcnt[ww][t] = tot;
+                tot += c[ww];
             }
-            run[t] = acc;
+            const uint32_t lb = block_excl_scan(tot, wtot);
+            lbase[t] = lb;
+            goff[t] = run[t] - lb;
+            run[t] += tot;
         }
         __syncthreads();
+        // stage the tile in digit order ...
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
             if (base + (uint64_t)i * 64 < end) {
                 const uint32_t d = (k[i] >> shift) & mask;
-                const uint32_t o = wcnt[w][d] + pos[i];
-                kout[o] = k[i];
-                vout[o] = v[i];
+                const uint32_t slot = lbase[d] + wcnt[w][d] + pos[i];
+                sk[slot] = k[i];
+                sv[slot] = v[i];
             }
         }
-        // no barrier here: until the next tile's first barrier a wave only
-        // touches its own counter row, which no other wave reads meanwhile
+        __syncthreads();
+        // ... and write it out: consecutive lanes write consecutive positions of a digit run
+        const uint32_t cnt = (uint32_t)min((uint64_t)RTILE, end - s);
+        for (uint32_t j = t; j < cnt; j += WG) {
+            const uint32_t key = sk[j];
+            const uint32_t o = goff[(key >> shift) & mask] + j;
+            kout[o] = key;
+            vout[o] = sv[j];
+        }
+        // no barrier here: the next tile writes sk / sv / goff only after its
+        // first block-wide barrier, which every thread reaches after this loop
     }
 }
 
@@ -788,8 +814,11 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s) {
     int cur = 0;
     const uint32_t *vin = iota ? nullptr : v0;
-    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
-        const int nb = bits - shift < RADIX_BITS ? bits - shift : RADIX_BITS;
+    // digits of equal width (at most RADIX_BITS): a narrow last digit would
+    // pile the whole histogram onto a few counters
+    const int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+    for (int p = 0, shift = 0; p < passes; ++p) {
+        const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
         uint32_t *ki = cur ? k1 : k0, *ko = cur ? k0 : k1;
         uint32_t *vo = cur ? v0 : v1;
         hipLaunchKernelGGL(k_radix_hist, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, n_dev, shift, nb, hist);
@@ -797,6 +826,7 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         hipLaunchKernelGGL(k_radix_scatter, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, hist, dtot);
         cur ^= 1;
         vin = cur ? v1 : v0;
+        shift += nb;
     }
     return cur;
 }
