@@ -626,14 +626,19 @@ __global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict
 // One (global tile id, record) instance per tile of every record, written in
 // depth order so that a stable sort by tile id keeps depth order in a tile.
 // Each wave takes 64 consecutive records and writes their instances as one
-// contiguous range, lane j writing output j, j + 64, ...; the record that
-// owns an output is found by binary search over the wave's offsets in LDS.
+// contiguous range in chunks of 64 outputs, lane j writing output J + j.
+// The record owning an output is found without a search: records starting
+// inside the chunk mark their first output in LDS, a ballot over the marks
+// gives every lane the number of records started up to its output, and the
+// compacted list of records that own tiles turns that count into a lane.
 __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
                                              const uint32_t *__restrict__ ioff, const ViewDev *__restrict__ views,
                                              const Status *__restrict__ st, uint32_t *__restrict__ ikey,
                                              uint32_t *__restrict__ ival) {
-    __shared__ uint32_t soff[WAVES][65];
-    __shared__ uint32_t sa[WAVES][64], sb[WAVES][64], sr[WAVES][64], stb[WAVES][64], stx[WAVES][64];
+    __shared__ uint4 srec[WAVES][64];      // x0y0, x1y1, tile base, tiles_x of each record
+    __shared__ uint2 sid[WAVES][64];       // record index, first output (relative)
+    __shared__ uint8_t cl[WAVES][64];      // lanes of the records that own at least one tile, in order
+    __shared__ uint8_t mk[WAVES][64];      // 1 where a record starts at that output of the chunk
     if (st->overflow) return;
     const uint64_t n = st->R_eff;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -656,35 +661,48 @@ __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, 
             }
         }
         const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
-        // exclusive offsets inside the wave's range; invalid lanes sit at the end
-        uint32_t rel = valid ? o - o0 : 0xFFFFFFFFu;
-        soff[w][lane] = rel;
-        sa[w][lane] = a0;
-        sb[w][lane] = a1;
-        sr[w][lane] = r;
-        stb[w][lane] = tb;
-        stx[w][lane] = tx;
-        // total = largest (rel + nt) over valid lanes
-        uint32_t endv = valid ? rel + nt : 0u;
-        for (int off = 32; off > 0; off >>= 1) endv = max(endv, (uint32_t)__shfl_xor((int)endv, off));
-        if (lane == 0) soff[w][64] = 0xFFFFFFFFu;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t j = lane; j < endv; j += 64) {
-            // last q with soff[q] <= j (soff is nondecreasing over valid lanes)
-            int lo = 0, hi = 63;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (soff[w][mid] <= j) lo = mid;
-                else hi = mid - 1;
+        const uint32_t rel = o - o0;
+        const bool owns = valid && nt > 0;
+        const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
+        if (owns) cl[w][lanes_below(own)] = (uint8_t)lane;
+        srec[w][lane] = make_uint4(a0, a1, tb, tx);
+        sid[w][lane] = make_uint2(r, rel);
+        // total outputs of the wave = end of the last record that owns tiles
+        uint32_t total = 0;
+        if (own) {
+            const int last = 63 - __builtin_clzll(own);
+            total = __shfl(rel + nt, last);
+        }
+        uint32_t started = 0;   // records (owning tiles) that start before the chunk
+        for (uint32_t J = 0; J < total; J += 64) {
+            mk[w][lane] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (owns && rel >= J && rel < J + 64) mk[w][rel - J] = 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const unsigned long long P = __builtin_amdgcn_ballot_w64(mk[w][lane] != 0);
+            const uint32_t upto = started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull);
+            const uint32_t j = J + lane;
+            if (j < total) {
+                const int q = cl[w][upto - 1];
+                const uint4 R = srec[w][q];
+                const uint2 id = sid[w][q];
+                const uint32_t k = j - id.y;
+                const uint32_t x0 = R.x & 0xFFFF, y0 = R.x >> 16, wx = (R.y & 0xFFFF) - x0;
+                // k / wx in floating point (k < 2^24), corrected to the exact quotient
+                uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)wx));
+                int32_t rem = (int32_t)(k - ty * wx);
+                if (rem < 0) { --ty; rem += (int32_t)wx; }
+                else if (rem >= (int32_t)wx) { ++ty; rem -= (int32_t)wx; }
+                ikey[o0 + j] = R.z + (y0 + ty) * R.w + x0 + (uint32_t)rem;
+                ival[o0 + j] = id.x;
             }
-            const uint32_t k = j - soff[w][lo];
-            const uint32_t x0 = sa[w][lo] & 0xFFFF, y0 = sa[w][lo] >> 16, x1 = sb[w][lo] & 0xFFFF;
-            const uint32_t wx = x1 - x0;
-            const uint32_t ty = k / wx, txx = k - ty * wx;
-            ikey[o0 + j] = stb[w][lo] + (y0 + ty) * stx[w][lo] + x0 + txx;
-            ival[o0 + j] = sr[w][lo];
+            started += (uint32_t)__popcll(P);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
