@@ -609,13 +609,13 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              &st->measure[0], ctx->tuning.vis_batch, s);
+                              ctx->tuning.vis_batch, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
             launch_vf_accum(a, at<ViewDev>(workspace, Lay.views), at<uint32_t>(workspace, Lay.offs),
                             at<Bin>(workspace, Lay.bin), accT, accC, st, L, al, acc_target,
-                            half_out ? 0 : (int)gamma_dtype, acc, s);
+                            half_out ? 0 : (int)gamma_dtype, acc, &st->measure[0], s);
         }
         GV_HIP(hipGetLastError());
         if (v0 + vp < n_train) {
@@ -675,11 +675,12 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              &st->measure[0], ctx->tuning.vis_batch, s);
+                              ctx->tuning.vis_batch, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
-            launch_vis_logsum(g->n, at<uint32_t>(workspace, Lay.offs), accT, accC, st, visibility, acc, s);
+            launch_vis_logsum(g->n, at<uint32_t>(workspace, Lay.offs), accT, accC, st, visibility, acc,
+                              &st->measure[0], s);
         }
         GV_HIP(hipGetLastError());
         if (v0 + vp < n_train) {

@@ -6,7 +6,8 @@
 //                 receives the pixel's transmittance and a count.  The 64
 //                 contributions of a wave are summed with DPP and the four
 //                 waves' sums combined in LDS, so each (tile, Gaussian) pair
-//                 costs one pair of global atomics.
+//                 costs one pair of global atomics (the pair count of the
+//                 blend is the sum of the counts, taken by k_vf_accum).
 //   k_raster_uq   uncertainty rasterisation (Alg. 6): compensated opacity
 //                 (eq. alpha_comp), per-pixel entropy bound (eq. huber) and
 //                 per-tile partial sums of the score.
@@ -188,17 +189,17 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
                                                    const uint2 *__restrict__ ranges,
                                                    const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
-                                                   uint32_t *__restrict__ acc_c,
-                                                   unsigned long long *__restrict__ pairs) {
+                                                   uint32_t *__restrict__ acc_c) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
     __shared__ uint16_t wS[WAVES][LCAP];   // batch slot of the entry
-    __shared__ uint32_t sR[RB];            // record index of each batch slot
+    // per batch slot (two batches: a batch is flushed while the next one blends)
+    __shared__ uint32_t sR[2 * RB];        // record index
     __shared__ int scnt[WAVES * WAVES];
     __shared__ int slen[WAVES];
-    __shared__ float part[RB];
-    __shared__ uint32_t cpart[RB];
+    __shared__ float part[2 * RB];         // sum of T over the tile's hit pixels
+    __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
     __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
 
     const int gt = blockIdx.x;
@@ -213,24 +214,50 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     // transmittance; pixels outside the image start inactive (T = 0 < eps_T)
     float T = (ox + qx < V.w && oy + qy < V.h) ? 1.0f : 0.0f;
     const uint2 rg = ranges[gt];
-    uint32_t npairs = 0;
 
+    // records are prefetched: while batch k is blended, the records of batch
+    // k + 1 and the record indices of batch k + 2 are in flight
+    const bool loader = t < RB;
+    uint32_t r1 = 0, r2 = 0;
+    Rec R1 = {};
+    if (loader && rg.x + t < rg.y) r1 = ival[rg.x + t];
+    if (loader && rg.x + RB + t < rg.y) r2 = ival[rg.x + RB + t];
+    if (loader && rg.x + t < rg.y) R1 = rec[r1];
+
+    // Adds a finished batch's per-slot sums to the per-record accumulators.
+    // Done one batch late, in the middle of the next batch, so that the
+    // atomics are long complete when the next record prefetch is waited for.
+    auto flush = [&](int buf, uint32_t bstart) {
+        const int cnt = (int)min((uint32_t)RB, rg.y - bstart);
+        if (t < cnt) {
+            const int sl = buf * RB + t;
+            const uint32_t c = cpart[sl];
+            if (c) {
+                atomicAdd(&acc_T[sR[sl]], part[sl]);
+                atomicAdd(&acc_c[sR[sl]], c);
+            }
+        }
+    };
+    int cur = 0;
+    uint32_t blast = rg.y;   // start of the last blended batch (none yet)
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
         if (__syncthreads_count(T >= eps_T) == 0) break;
-        const uint32_t idx = b + t;
+        const bool have = loader && b + t < rg.y;
+        const Rec R = R1;
+        const uint32_t r = r1;
+        r1 = r2;
+        if (loader && b + RB + t < rg.y) R1 = rec[r1];
+        if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
         uint32_t mask = 0;
-        Rec R;
         float ux = 0.f, uy = 0.f;
-        if (t < RB && idx < rg.y) {
-            const uint32_t r = ival[idx];
-            R = rec[r];
+        if (have) {
             local_centre(R, ox, oy, ux, uy);
-            sR[t] = r;
+            sR[cur * RB + t] = r;
             mask = quadrant_mask(ux, uy, R.l11, R.l21, R.l22, qcut);
         }
         if (t < RB) {
-            part[t] = 0.0f;
-            cpart[t] = 0u;
+            part[cur * RB + t] = 0.0f;
+            cpart[cur * RB + t] = 0u;
         }
         int pos[WAVES];
         list_positions(mask, pos, scnt, slen);
@@ -239,7 +266,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             if (pos[q] >= 0) {
                 wA[q][pos[q]] = make_float4(ux, uy, R.l11, R.l21);
                 wB[q][pos[q]] = make_float2(R.l22, R.o);
-                wS[q][pos[q]] = (uint16_t)t;
+                wS[q][pos[q]] = (uint16_t)(cur * RB + t);
             }
         }
         {
@@ -252,6 +279,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             }
         }
         __syncthreads();
+        if (blast != rg.y) flush(cur ^ 1, blast);
         const int len = __builtin_amdgcn_readfirstlane(slen[w]);
         const int jl = lane & (LGROUP - 1);
         for (int i0 = 0; i0 < len; i0 += LGROUP) {
@@ -298,18 +326,11 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
                 atomicAdd(&cpart[slot], cv);
             }
         }
-        __syncthreads();
-        const int cnt = (int)min((uint32_t)RB, rg.y - b);
-        if (t < cnt) {
-            const uint32_t c = cpart[t];
-            if (c) {
-                atomicAdd(&acc_T[sR[t]], part[t]);
-                atomicAdd(&acc_c[sR[t]], c);
-                npairs += c;
-            }
-        }
+        blast = b;
+        cur ^= 1;
     }
-    block_count(npairs, pairs);
+    __syncthreads();
+    if (blast != rg.y) flush(cur ^ 1, blast);
 }
 
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
@@ -344,13 +365,24 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
 
+    // records are prefetched as in the VF CONST blend
+    const bool loader = t < RB;
+    uint32_t r1 = 0, r2 = 0;
+    Rec R1 = {};
+    if (loader && rg.x + t < rg.y) r1 = ival[rg.x + t];
+    if (loader && rg.x + RB + t < rg.y) r2 = ival[rg.x + RB + t];
+    if (loader && rg.x + t < rg.y) R1 = rec[r1];
+
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
         if (__syncthreads_count(T >= u.eps_T) == 0) break;
-        const uint32_t idx = b + t;
+        const bool have = loader && b + t < rg.y;
+        const Rec R = R1;
+        r1 = r2;
+        if (loader && b + RB + t < rg.y) R1 = rec[r1];
+        if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
         uint32_t mask = 0;
         float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
-        if (t < RB && idx < rg.y) {
-            const Rec R = rec[ival[idx]];
+        if (have) {
             float ux, uy;
             local_centre(R, ox, oy, ux, uy);
             const float v = R.v;
@@ -493,48 +525,52 @@ __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__r
                                                  const uint32_t *__restrict__ offs, const Bin *__restrict__ bin,
                                                  const float *__restrict__ acc_T, const uint32_t *__restrict__ acc_c,
                                                  const Status *__restrict__ st, ALs al, TGam *__restrict__ gamma,
-                                                 bool accumulate) {
+                                                 bool accumulate, unsigned long long *__restrict__ pairs) {
     constexpr int K = (L + 1) * (L + 1);
     const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (g >= a.n) return;
     if (st->overflow) return;
-    float m[3];
-    {
-        const TG *mp = (const TG *)a.means;
-        if constexpr (sizeof(TG) == 4) {
-            m[0] = load_f(mp, 3 * g); m[1] = load_f(mp, 3 * g + 1); m[2] = load_f(mp, 3 * g + 2);
-        } else {
-            const int64_t blk = g / (a.anchor_block > 0 ? a.anchor_block : 1);
-            m[0] = a.anchors[3 * blk] + load_f(mp, 3 * g);
-            m[1] = a.anchors[3 * blk + 1] + load_f(mp, 3 * g + 1);
-            m[2] = a.anchors[3 * blk + 2] + load_f(mp, 3 * g + 2);
+    uint32_t npairs = 0;   // pixels composited over this Gaussian's records
+    if (g < a.n) {
+        float m[3];
+        {
+            const TG *mp = (const TG *)a.means;
+            if constexpr (sizeof(TG) == 4) {
+                m[0] = load_f(mp, 3 * g); m[1] = load_f(mp, 3 * g + 1); m[2] = load_f(mp, 3 * g + 2);
+            } else {
+                const int64_t blk = g / (a.anchor_block > 0 ? a.anchor_block : 1);
+                m[0] = a.anchors[3 * blk] + load_f(mp, 3 * g);
+                m[1] = a.anchors[3 * blk + 1] + load_f(mp, 3 * g + 1);
+                m[2] = a.anchors[3 * blk + 2] + load_f(mp, 3 * g + 2);
+            }
         }
-    }
-    float acc[K];
+        float acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = accumulate ? load_f((const TGam *)gamma, (int64_t)k * a.n + g) : 0.0f;
-    const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
-    for (uint32_t r = r0; r < r1; ++r) {
-        const uint32_t c = acc_c[r];
-        if (c == 0) continue;
-        const float v = acc_T[r] / (float)c;
-        const ViewDev &V = views[bin[r].view];
-        float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
-        const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
-        if (!(nrm > 0.0f)) continue;
-        const float inv = 1.0f / nrm;
-        dx *= inv; dy *= inv; dz *= inv;
-        float Y[K];
-        sh_eval<L>(dx, dy, dz, Y);
+        for (int k = 0; k < K; ++k) acc[k] = accumulate ? load_f((const TGam *)gamma, (int64_t)k * a.n + g) : 0.0f;
+        const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
+        for (uint32_t r = r0; r < r1; ++r) {
+            const uint32_t c = acc_c[r];
+            if (c == 0) continue;
+            npairs += c;
+            const float v = acc_T[r] / (float)c;
+            const ViewDev &V = views[bin[r].view];
+            float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+            const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+            if (!(nrm > 0.0f)) continue;
+            const float inv = 1.0f / nrm;
+            dx *= inv; dy *= inv; dz *= inv;
+            float Y[K];
+            sh_eval<L>(dx, dy, dz, Y);
 #pragma unroll
-        for (int l = 0; l <= L; ++l) {
-            const float va = v * al.a[l];
+            for (int l = 0; l <= L; ++l) {
+                const float va = v * al.a[l];
 #pragma unroll
-            for (int k = l * l; k < (l + 1) * (l + 1); ++k) acc[k] = fmaf(va, Y[k], acc[k]);
+                for (int k = l * l; k < (l + 1) * (l + 1); ++k) acc[k] = fmaf(va, Y[k], acc[k]);
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < K; ++k) store_f(gamma, (int64_t)k * a.n + g, acc[k]);
+        for (int k = 0; k < K; ++k) store_f(gamma, (int64_t)k * a.n + g, acc[k]);
+    }
+    block_count(npairs, pairs);
 }
 
 // ---------------------------------------------------------------- multi-view visibility (Alg. 5)
@@ -544,19 +580,24 @@ __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__r
 __global__ __launch_bounds__(WG) void k_vis_logsum(int64_t n, const uint32_t *__restrict__ offs,
                                                    const float *__restrict__ acc_T,
                                                    const uint32_t *__restrict__ acc_c, const Status *__restrict__ st,
-                                                   float *__restrict__ out, bool accumulate) {
+                                                   float *__restrict__ out, bool accumulate,
+                                                   unsigned long long *__restrict__ pairs) {
     const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (g >= n) return;
     if (st->overflow) return;
-    float s = accumulate ? out[g] : 0.0f;
-    const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
-    for (uint32_t r = r0; r < r1; ++r) {
-        const uint32_t c = acc_c[r];
-        if (c == 0) continue;
-        const float v = fminf(acc_T[r] / (float)c, 1.0f);
-        s += log1pf(-v);
+    uint32_t npairs = 0;
+    if (g < n) {
+        float s = accumulate ? out[g] : 0.0f;
+        const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
+        for (uint32_t r = r0; r < r1; ++r) {
+            const uint32_t c = acc_c[r];
+            if (c == 0) continue;
+            npairs += c;
+            const float v = fminf(acc_T[r] / (float)c, 1.0f);
+            s += log1pf(-v);
+        }
+        out[g] = s;
     }
-    out[g] = s;
+    block_count(npairs, pairs);
 }
 
 // out[g] = 1 - exp(out[g]) = 1 - prod_p (1 - v_p[g]).
@@ -566,10 +607,10 @@ __global__ __launch_bounds__(WG) void k_vis_finish(int64_t n, float *__restrict_
 }
 
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
-                       float *out, bool accumulate, hipStream_t s) {
+                       float *out, bool accumulate, unsigned long long *pairs, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_vis_logsum, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, n, offs, acc_T, acc_c, st,
-                       out, accumulate);
+                       out, accumulate, pairs);
 }
 
 void launch_vis_finish(int64_t n, float *out, hipStream_t s) {
@@ -608,20 +649,19 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 
 template <int RB>
 static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                          const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                          unsigned long long *pairs, hipStream_t s) {
+                          const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
     hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
-                       acc_T, acc_c, pairs);
+                       acc_T, acc_c);
 }
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                       unsigned long long *pairs, int batch, hipStream_t s) {
+                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
+                       hipStream_t s) {
     if (total_tiles <= 0) return;
     switch (batch) {
-    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
-    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
-    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, pairs, s); break;
+    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
     }
 }
 
@@ -664,38 +704,38 @@ void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s) {
 template <typename TG, typename TGam>
 static void accum_L(int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
                     const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
-                    bool accumulate, hipStream_t s) {
+                    bool accumulate, unsigned long long *pairs, hipStream_t s) {
     const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
     TGam *gm = (TGam *)gamma;
     switch (L) {
-    case 0: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 0>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
-    case 1: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 1>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
-    case 2: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 2>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
-    default: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 3>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate); break;
+    case 0: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 0>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    case 1: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 1>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    case 2: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 2>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    default: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 3>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
     }
 }
 
 template <typename TG>
 static void accum_gam(int gdt, int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
                       const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
-                      bool accumulate, hipStream_t s) {
+                      bool accumulate, unsigned long long *pairs, hipStream_t s) {
     switch (gdt) {
-    case 0: accum_L<TG, float>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
-    case 1: accum_L<TG, _Float16>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
-    default: accum_L<TG, uint16_t>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    case 0: accum_L<TG, float>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 1: accum_L<TG, _Float16>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    default: accum_L<TG, uint16_t>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
     }
 }
 
 void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
                      const float *acc_T, const uint32_t *acc_c, const Status *st, int L, const float *al_in,
-                     void *gamma, int gamma_dtype, bool accumulate, hipStream_t s) {
+                     void *gamma, int gamma_dtype, bool accumulate, unsigned long long *pairs, hipStream_t s) {
     if (a.n == 0) return;
     ALs al;
     for (int l = 0; l < 4; ++l) al.a[l] = l <= L ? al_in[l] : 0.0f;
     switch (a.dtype) {
-    case 0: accum_gam<float>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
-    case 1: accum_gam<_Float16>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
-    default: accum_gam<uint16_t>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, s); break;
+    case 0: accum_gam<float>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 1: accum_gam<_Float16>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    default: accum_gam<uint16_t>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
     }
 }
 
