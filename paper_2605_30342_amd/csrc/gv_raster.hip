@@ -112,23 +112,52 @@ __device__ __forceinline__ void quadrant_pixel(int t, int &qx, int &qy) {
     qy = ((w >> 1) << 3) + (l >> 3);
 }
 
-// Bit w set when the record's ellipse bounding box (m <= cut) can reach a
-// pixel centre of quadrant w.  The box half-widths follow from the scaled
-// Cholesky factor L = [[a, 0], [b, c]] of the conic: the covariance is
-// (L L^T)^-1, so sigma_xx = (b^2 + c^2) / (a c)^2 and sigma_yy = 1 / c^2, and
-// the box is sqrt(qcut sigma) wide (widened slightly to stay conservative).
+// Bit q set when the ellipse p <= qcut can reach the rectangle spanned by the
+// pixel centres of quadrant q.  With the scaled Cholesky factor
+// L = [[a, 0], [b, c]] of the conic, p = (a ex + b ey)^2 + (c ey)^2 for the
+// offset (ex, ey) from the centre.  The minimum of this convex form over a
+// rectangle is 0 when the centre lies inside, else it lies on an edge, where
+// it is a clamped one-dimensional minimum: on a line x = X the minimising
+// y is uy + (a b / (b^2 + c^2)) (ux - X), on a line y = Y the minimising x
+// is ux + (b / a) (uy - Y).  The threshold is widened so that rounding never
+// drops a quadrant with a pixel the blend would composite; about a third of
+// the quadrants an axis-aligned box admits are rejected.
 __device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, float b, float c, float qcut) {
-    // hardware reciprocal and square root (about 1 ulp): the 0.1% widening covers them
-    const float ic = __builtin_amdgcn_rcpf(c);
-    const float rx = __builtin_amdgcn_sqrtf(qcut * fmaf(b, b, c * c)) * ic * __builtin_amdgcn_rcpf(a) * 1.001f + 0.01f;
-    const float ry = __builtin_amdgcn_sqrtf(qcut) * ic * 1.001f + 0.01f;
+    const float thr = fmaf(qcut, 1.001f, 0.01f);
+    const float kx = b * __builtin_amdgcn_rcpf(a);
+    const float ky = a * b * __builtin_amdgcn_rcpf(fmaf(b, b, c * c));
+    constexpr float LO[2] = {0.5f, 8.5f}, HI[2] = {7.5f, 15.5f};
+    float pm[WAVES];
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) {
+        const int col = q & 1, row = q >> 1;
+        const bool inside = ux >= LO[col] && ux <= HI[col] && uy >= LO[row] && uy <= HI[row];
+        pm[q] = inside ? 0.0f : 3.0e38f;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int col = i >> 1;
+        const float X = (i & 1) ? HI[col] : LO[col];
+        // vertical edge x = X of the quadrants in column col
+        const float ex = ux - X, ys = fmaf(ky, ex, uy);
+#pragma unroll
+        for (int row = 0; row < 2; ++row) {
+            const float ey = uy - __builtin_amdgcn_fmed3f(ys, LO[row], HI[row]);
+            const float w1 = fmaf(a, ex, b * ey), w2 = c * ey;
+            pm[row * 2 + col] = fminf(pm[row * 2 + col], fmaf(w1, w1, w2 * w2));
+        }
+        // horizontal edge y = X of the quadrants in row col
+        const float ey = uy - X, xs = fmaf(kx, ey, ux);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const float ex2 = ux - __builtin_amdgcn_fmed3f(xs, LO[cc], HI[cc]);
+            const float w1 = fmaf(a, ex2, b * ey), w2 = c * ey;
+            pm[col * 2 + cc] = fminf(pm[col * 2 + cc], fmaf(w1, w1, w2 * w2));
+        }
+    }
     uint32_t m = 0;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-        const float x0 = ((w & 1) << 3) + 0.5f, y0 = ((w >> 1) << 3) + 0.5f;
-        const bool in = (ux + rx >= x0) && (ux - rx <= x0 + 7.0f) && (uy + ry >= y0) && (uy - ry <= y0 + 7.0f);
-        m |= in ? (1u << w) : 0u;
-    }
+    for (int q = 0; q < WAVES; ++q) m |= pm[q] <= thr ? (1u << q) : 0u;
     return m;
 }
 
