@@ -178,14 +178,19 @@ def main():
     st, cnt_q = ctx.check_workspace(ws_q)
     assert st == 0, "query workspace overflow"
 
-    # timed region (stage events recorded on the same stream)
-    ctx.profile(True)
+    # timed region: whole steps, no per-stage events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         best = step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-stage launch times: the same steps again with HIP events around every
+    # stage, recorded on the stream the kernels run on
+    ctx.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     stages = ctx.profile_read()
     ctx.profile(False)
     build_ms = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)]

@@ -9,6 +9,8 @@
 // 16x16 tile, and the instances are stably sorted by global tile id: every
 // tile's list is then in increasing (depth, Gaussian) order, the front-to-back
 // order that Alg. 2 and Alg. 6 composite in.
+#include <algorithm>
+
 #include "gv_device.hpp"
 #include "gv_launch.hpp"
 
@@ -181,7 +183,8 @@ __device__ __forceinline__ void project_exact(const float m[3], const double S[6
 
 template <typename TG>
 __global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
-                                              float znear, float lowpass, float cut, uint32_t *__restrict__ cnt) {
+                                              float znear, float lowpass, float cut, uint32_t *__restrict__ cnt,
+                                              uint32_t *__restrict__ vmask, int mw) {
     const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
     const int64_t g = e / PROJ_SPLIT;
     if (g >= G.n) return;
@@ -190,8 +193,20 @@ __global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__re
     G.mean(g, m);
     G.scale(g, s);
     const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
-    uint32_t c = 0;
-    for (int v = sub; v < nv; v += PROJ_SPLIT) c += cons_visible(m, smax, views[v], znear, lowpass, cut) ? 1u : 0u;
+    // bit i % 32 of word i / 32 set when view sub + PROJ_SPLIT i passes the test
+    uint32_t c = 0, word = 0;
+    int i = 0;
+    for (int v = sub; v < nv; v += PROJ_SPLIT, ++i) {
+        if (cons_visible(m, smax, views[v], znear, lowpass, cut)) {
+            ++c;
+            word |= 1u << (i & 31);
+        }
+        if ((i & 31) == 31) {
+            vmask[e * mw + (i >> 5)] = word;
+            word = 0;
+        }
+    }
+    if (i & 31) vmask[e * mw + (i >> 5)] = word;
     cnt[e] = c;
 }
 
@@ -231,95 +246,158 @@ __global__ __launch_bounds__(WG) void k_measure(GaussIn<TG> G, const ViewDev *__
     }
 }
 
-// Projection of every surviving (Gaussian, view) pair into its record slot.
+// Index of the k-th (from 0) set bit of x; x has more than k set bits.
+__device__ __forceinline__ int kth_set_bit(uint32_t x, uint32_t k) {
+    int pos = 0;
+#pragma unroll
+    for (int sh = 16; sh >= 1; sh >>= 1) {
+        const uint32_t low = (uint32_t)__popc(x & ((1u << sh) - 1u));
+        if (k >= low) {
+            k -= low;
+            x >>= sh;
+            pos += sh;
+        }
+    }
+    return pos;
+}
+
+// Projection of every surviving (Gaussian, view) pair into its record slot,
+// one record per lane.  A wave takes 64 consecutive (Gaussian, view subset)
+// entries and enumerates their records in chunks of 64: the entry owning a
+// record is found from start marks and a ballot (as in the instance
+// emission), the view from the entry's visibility mask.  Lanes therefore stay
+// busy however few views of a Gaussian survive the cull.
 // QUERY: also evaluates the visibility field in the direction camera ->
 // Gaussian (Alg. 4): V~ = sum_k gamma_k Y_k(d), clamped to [0, |P|], then
 // V = 1 - (1 - V~/|P|)^|P| computed as 1 - exp(|P| log1p(-V~/|P|)).
 template <typename TG, typename TGam, bool QUERY, int L>
 __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                                 float znear, float lowpass, float cut,
-                                                const uint32_t *__restrict__ offs, const Status *__restrict__ st,
-                                                uint32_t rcap, const TGam *__restrict__ gamma, float n_train,
+                                                const uint32_t *__restrict__ offs, const uint32_t *__restrict__ vmask,
+                                                int mw, const Status *__restrict__ st, uint32_t rcap,
+                                                const TGam *__restrict__ gamma, float n_train,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                 Bin *__restrict__ bin) {
     constexpr int K = (L + 1) * (L + 1);
-    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const int64_t g = e / PROJ_SPLIT;
-    if (g >= G.n) return;
-    const int sub = (int)(e % PROJ_SPLIT);
+    __shared__ uint32_t srel[WAVES][64];   // first record of each entry (relative)
+    __shared__ uint8_t cl[WAVES][64];      // lanes of the entries that own records, in order
+    __shared__ uint8_t mk[WAVES][64];      // 1 where an entry starts at that record of the chunk
     if (st->overflow & 1u) return;
-    float m[3], s[3], q[4];
-    G.mean(g, m);
-    G.scale(g, s);
-    G.quat(g, q);
-    const float o = G.opacity(g);
-    const float smax = fmaxf(fmaxf(s[0], s[1]), s[2]);
-    double S[6];
-    cov3d(s, q, S);
-    float gam[K > 0 ? K : 1];
-    const bool virt = g >= G.n - G.n_virtual;
-    if constexpr (QUERY) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) gam[k] = load_f(gamma, (int64_t)k * G.n + g);
-    }
-    uint32_t r = offs[e];
-    const uint32_t rend = offs[e + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t ne = (uint64_t)G.n * PROJ_SPLIT;
+    const uint64_t nwaves = (uint64_t)gridDim.x * WAVES;
     const double sc = 0.8493218002880191;   // sqrt(log2(e) / 2)
-    for (int v = sub; v < nv; v += PROJ_SPLIT) {
-        const ViewDev &V = views[v];
-        if (!cons_visible(m, smax, V, znear, lowpass, cut)) continue;
-        if (r >= rend || r >= rcap) break;
-        Proj P;
-        project_exact(m, S, V, znear, lowpass, cut, P);
-        Bin b;
-        b.view = v;
-        if (!P.ok) {
-            b.x0y0 = b.x1y1 = b.ntiles = 0;
-            bin[r] = b;
-            key[r] = DEAD_KEY;
-            rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            ++r;
-            continue;
+    for (uint64_t c = (uint64_t)blockIdx.x * WAVES + w; c * 64 < ne; c += nwaves) {
+        const uint64_t e = c * 64 + lane;
+        const bool valid = e < ne;
+        uint32_t o = 0, cnt = 0;
+        if (valid) {
+            o = offs[e];
+            cnt = offs[e + 1] - o;
         }
-        b.x0y0 = (uint32_t)P.x0 | ((uint32_t)P.y0 << 16);
-        b.x1y1 = (uint32_t)P.x1 | ((uint32_t)P.y1 << 16);
-        b.ntiles = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
-        const double ax = fmin(fmax(rint(P.ux), -32768.0), 32767.0);
-        const double ay = fmin(fmax(rint(P.uy), -32768.0), 32767.0);
-        Rec R;
-        R.uv = (int32_t)(((uint32_t)(int)ax & 0xFFFFu) | ((uint32_t)(int)ay << 16));
-        R.fx = (float)(P.ux - ax);
-        R.fy = (float)(P.uy - ay);
-        const double l11 = sqrt(P.ca);
-        const double l21 = P.cb / l11;
-        const double l22 = sqrt(fmax(P.cc - l21 * l21, 0.0));
-        R.l11 = (float)(sc * l11);
-        R.l21 = (float)(sc * l21);
-        R.l22 = (float)(sc * l22);
-        R.o = o;
-        float vis = 0.0f;
-        if constexpr (QUERY) {
-            if (!virt && n_train > 0.0f) {
-                float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
-                const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
-                if (nrm > 0.0f) {
-                    const float inv = 1.0f / nrm;
-                    dx *= inv; dy *= inv; dz *= inv;
-                    float Y[K];
-                    sh_eval<L>(dx, dy, dz, Y);
-                    float vt = 0.0f;
+        const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
+        const uint32_t rel = o - o0;
+        const bool owns = valid && cnt > 0;
+        const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
+        if (owns) cl[w][lanes_below(own)] = (uint8_t)lane;
+        srel[w][lane] = rel;
+        uint32_t total = 0;
+        if (own) {
+            const int last = 63 - __builtin_clzll(own);
+            total = __shfl(rel + cnt, last);
+        }
+        uint32_t started = 0;
+        for (uint32_t J = 0; J < total; J += 64) {
+            mk[w][lane] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (owns && rel >= J && rel < J + 64) mk[w][rel - J] = 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const unsigned long long P = __builtin_amdgcn_ballot_w64(mk[w][lane] != 0);
+            const uint32_t upto = started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull);
+            const uint32_t j = J + lane;
+            const uint32_t r = o0 + j;
+            if (j < total && r < rcap) {
+                const int q = cl[w][upto - 1];
+                uint32_t k = j - srel[w][q];
+                const uint64_t eq = c * 64 + (uint64_t)q;
+                const int64_t g = (int64_t)(eq / PROJ_SPLIT);
+                const int sub = (int)(eq % PROJ_SPLIT);
+                // the k-th view of the entry that passed the cull
+                int wi = 0;
+                uint32_t word = vmask[eq * mw];
+                for (uint32_t pc = (uint32_t)__popc(word); k >= pc; pc = (uint32_t)__popc(word)) {
+                    k -= pc;
+                    word = vmask[eq * mw + ++wi];
+                }
+                const int v = sub + PROJ_SPLIT * (32 * wi + kth_set_bit(word, k));
+                const ViewDev &V = views[v];
+                float m[3], s[3], qt[4];
+                G.mean(g, m);
+                G.scale(g, s);
+                G.quat(g, qt);
+                double S[6];
+                cov3d(s, qt, S);
+                Proj Pj;
+                project_exact(m, S, V, znear, lowpass, cut, Pj);
+                Bin b;
+                b.view = v;
+                if (!Pj.ok) {
+                    b.x0y0 = b.x1y1 = b.ntiles = 0;
+                    bin[r] = b;
+                    key[r] = DEAD_KEY;
+                    rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                } else {
+                    b.x0y0 = (uint32_t)Pj.x0 | ((uint32_t)Pj.y0 << 16);
+                    b.x1y1 = (uint32_t)Pj.x1 | ((uint32_t)Pj.y1 << 16);
+                    b.ntiles = (uint32_t)((Pj.x1 - Pj.x0) * (Pj.y1 - Pj.y0));
+                    const double ax = fmin(fmax(rint(Pj.ux), -32768.0), 32767.0);
+                    const double ay = fmin(fmax(rint(Pj.uy), -32768.0), 32767.0);
+                    Rec R;
+                    R.uv = (int32_t)(((uint32_t)(int)ax & 0xFFFFu) | ((uint32_t)(int)ay << 16));
+                    R.fx = (float)(Pj.ux - ax);
+                    R.fy = (float)(Pj.uy - ay);
+                    const double l11 = sqrt(Pj.ca);
+                    const double l21 = Pj.cb / l11;
+                    const double l22 = sqrt(fmax(Pj.cc - l21 * l21, 0.0));
+                    R.l11 = (float)(sc * l11);
+                    R.l21 = (float)(sc * l21);
+                    R.l22 = (float)(sc * l22);
+                    R.o = G.opacity(g);
+                    float vis = 0.0f;
+                    if constexpr (QUERY) {
+                        const bool virt = g >= G.n - G.n_virtual;
+                        if (!virt && n_train > 0.0f) {
+                            float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+                            const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+                            if (nrm > 0.0f) {
+                                const float inv = 1.0f / nrm;
+                                dx *= inv; dy *= inv; dz *= inv;
+                                float Y[K];
+                                sh_eval<L>(dx, dy, dz, Y);
+                                float vt = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < K; ++k) vt = fmaf(gam[k], Y[k], vt);
-                    vt = fminf(fmaxf(vt, 0.0f), n_train);
-                    vis = (vt >= n_train) ? 1.0f : 1.0f - expf(n_train * log1pf(-vt / n_train));
+                                for (int kk = 0; kk < K; ++kk) vt = fmaf(load_f(gamma, (int64_t)kk * G.n + g), Y[kk], vt);
+                                vt = fminf(fmaxf(vt, 0.0f), n_train);
+                                vis = (vt >= n_train) ? 1.0f : 1.0f - expf(n_train * log1pf(-vt / n_train));
+                            }
+                        }
+                    }
+                    R.v = vis;
+                    rec[r] = R;
+                    key[r] = __float_as_uint((float)Pj.z);
+                    bin[r] = b;
                 }
             }
+            started += (uint32_t)__popcll(P);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        R.v = vis;
-        rec[r] = R;
-        key[r] = __float_as_uint((float)P.z);
-        bin[r] = b;
-        ++r;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -753,13 +831,20 @@ static GaussIn<TG> gin(const GaussArgs &a) {
     return G;
 }
 
-void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, hipStream_t s) {
+int mask_words(int nv) {
+    const int per = (nv + PROJ_SPLIT - 1) / PROJ_SPLIT;
+    return per > 32 ? (per + 31) / 32 : 1;
+}
+
+void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt,
+                  uint32_t *vmask, hipStream_t s) {
     const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
     if (grid == 0) return;
+    const int mw = mask_words(nv);
     switch (a.dtype) {
-    case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
-    case 1: hipLaunchKernelGGL(k_count<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
-    default: hipLaunchKernelGGL(k_count<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, cnt); break;
+    case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
+    case 1: hipLaunchKernelGGL(k_count<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
+    default: hipLaunchKernelGGL(k_count<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
     }
 }
 
@@ -776,41 +861,44 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
 
 template <typename TG, typename TGam, bool QUERY>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
-                               const uint32_t *offs, const Status *st, uint32_t rcap, const void *gamma,
-                               float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
+                               const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
+                               const void *gamma, float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+    const uint64_t chunks = ((uint64_t)a.n * PROJ_SPLIT + 63) / 64;
+    const unsigned grid = (unsigned)std::min<uint64_t>((chunks + WAVES - 1) / WAVES, 4096);
+    const int mw = mask_words(nv);
     const TGam *gm = (const TGam *)gamma;
     switch (L) {
-    case 0: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 0>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
-    case 1: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 1>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
-    case 2: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 2>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
-    default: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 3>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, st, rcap, gm, n_train, rec, key, bin); break;
+    case 0: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 0>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
+    case 1: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 1>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
+    case 2: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 2>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
+    default: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 3>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
     }
 }
 
 template <typename TG>
 static void project_dispatch_gam(int gdt, bool query, int L, const GaussArgs &a, const ViewDev *views, int nv,
-                                 const GeomArgs &p, const uint32_t *offs, const Status *st, uint32_t rcap,
+                                 const GeomArgs &p, const uint32_t *offs, const uint32_t *vmask, const Status *st,
+                                 uint32_t rcap,
                                  const void *gamma, float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
     if (!query) {
-        project_dispatch_L<TG, float, false>(0, a, views, nv, p, offs, st, rcap, nullptr, 0.f, rec, key, bin, s);
+        project_dispatch_L<TG, float, false>(0, a, views, nv, p, offs, vmask, st, rcap, nullptr, 0.f, rec, key, bin, s);
         return;
     }
     switch (gdt) {
-    case 0: project_dispatch_L<TG, float, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    case 1: project_dispatch_L<TG, _Float16, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    default: project_dispatch_L<TG, uint16_t, true>(L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 0: project_dispatch_L<TG, float, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 1: project_dispatch_L<TG, _Float16, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    default: project_dispatch_L<TG, uint16_t, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
     }
 }
 
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
-                    const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
+                    const uint32_t *vmask, const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
                     float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
     if (a.n == 0) return;
     switch (a.dtype) {
-    case 0: project_dispatch_gam<float>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    case 1: project_dispatch_gam<_Float16>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    default: project_dispatch_gam<uint16_t>(gamma_dtype, query, L, a, views, nv, p, offs, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 0: project_dispatch_gam<float>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 1: project_dispatch_gam<_Float16>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    default: project_dispatch_gam<uint16_t>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
     }
 }
 

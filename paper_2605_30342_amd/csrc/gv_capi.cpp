@@ -103,7 +103,7 @@ bool finite_cam(const gv_camera &c) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t status, views, cnt, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
+    size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
     size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, total;
 };
 
@@ -121,6 +121,7 @@ Layout make_layout(const gv_workspace &p) {
     L.status = take(sizeof(Status));
     L.views = take(V * sizeof(ViewDev));
     L.cnt = take(N * PROJ_SPLIT * 4);
+    L.vmask = take(N * PROJ_SPLIT * (uint64_t)mask_words((int)V) * 4);
     L.offs = take((N * PROJ_SPLIT + 1) * 4);
     L.blk = take(scan_blk_count(std::max(N * PROJ_SPLIT, R)) * 8);
     L.rec = take(R * sizeof(Rec));
@@ -351,7 +352,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
                              float n_train, hipStream_t s, Binned &out) {
     Status *st = at<Status>(ws, L.status);
     ViewDev *views = at<ViewDev>(ws, L.views);
-    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs);
+    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs), *vmask = at<uint32_t>(ws, L.vmask);
     unsigned long long *blk = at<unsigned long long>(ws, L.blk);
     Rec *rec = at<Rec>(ws, L.rec);
     Bin *bin = at<Bin>(ws, L.bin);
@@ -367,13 +368,13 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     {
         StageScope sc(ctx, ST_CULL, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
-        launch_count(a, views, nv, geo, cnt, s);
+        launch_count(a, views, nv, geo, cnt, vmask, s);
         const uint64_t ne = (uint64_t)a.n * PROJ_SPLIT;
         launch_scan(cnt, offs, nullptr, ne, ne, blk, &st->R_total, &st->R_eff, R, &st->overflow, 1u, s);
     }
     {
         StageScope sc(ctx, ST_PROJECT, s);
-        launch_project(a, views, nv, geo, offs, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
+        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
     }
     int dres;
     {

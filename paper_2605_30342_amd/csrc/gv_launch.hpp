@@ -34,11 +34,14 @@ struct UqArgs {
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s);
 
-void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, hipStream_t s);
+// Words of the per-(Gaussian, view subset) visibility mask for nv views.
+int mask_words(int nv);
+void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, uint32_t *vmask,
+                  hipStream_t s);
 void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
-                    const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
+                    const uint32_t *vmask, const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
                     float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s);
 
 size_t scan_blk_count(uint64_t n_cap);
