@@ -343,17 +343,12 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 cov3d(s, qt, S);
                 Proj Pj;
                 project_exact(m, S, V, znear, lowpass, cut, Pj);
-                Bin b;
-                b.view = v;
+                Bin b = {};
                 if (!Pj.ok) {
-                    b.x0y0 = b.x1y1 = b.ntiles = 0;
                     bin[r] = b;
                     key[r] = DEAD_KEY;
                     rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
-                    b.x0y0 = (uint32_t)Pj.x0 | ((uint32_t)Pj.y0 << 16);
-                    b.x1y1 = (uint32_t)Pj.x1 | ((uint32_t)Pj.y1 << 16);
-                    b.ntiles = (uint32_t)((Pj.x1 - Pj.x0) * (Pj.y1 - Pj.y0));
                     const double ax = fmin(fmax(rint(Pj.ux), -32768.0), 32767.0);
                     const double ay = fmin(fmax(rint(Pj.uy), -32768.0), 32767.0);
                     Rec R;
@@ -389,6 +384,19 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     R.v = vis;
                     rec[r] = R;
                     key[r] = __float_as_uint((float)Pj.z);
+                    b.tile0 = (uint32_t)(V.tile_base + Pj.y0 * V.tiles_x + Pj.x0);
+                    b.dims = (uint32_t)V.tiles_x | (uint32_t)(Pj.x1 - Pj.x0 - 1) << 11 |
+                             (uint32_t)(Pj.y1 - Pj.y0 - 1) << 21 | 1u << 31;
+                    // the anchor is at least one pixel left of / above the first
+                    // tile only when that tile is the first of the image row, so
+                    // the offsets fit int16
+                    b.uvr = (int32_t)(((uint32_t)((int)ax - TILE * Pj.x0) & 0xFFFFu) |
+                                      ((uint32_t)((int)ay - TILE * Pj.y0) << 16));
+                    b.fx = R.fx;
+                    b.fy = R.fy;
+                    b.l11 = R.l11;
+                    b.l21 = R.l21;
+                    b.l22 = R.l22;
                     bin[r] = b;
                 }
             }
@@ -698,11 +706,14 @@ __global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict
                                                       const uint32_t *n_dev, uint32_t *__restrict__ icnt) {
     const uint64_t n = *n_dev;
     for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
-        icnt[i] = bin[sval[i]].ntiles;
+        icnt[i] = bin_ntiles(bin[sval[i]].dims);
 }
 
 // One (global tile id, record) instance per tile of every record, written in
 // depth order so that a stable sort by tile id keeps depth order in a tile.
+// The key also carries the record's quadrant mask for the tile (which
+// quadrants of the tile its ellipse reaches); an instance whose ellipse
+// reaches none of them is given the tile id past the last tile.
 // Each wave takes 64 consecutive records and writes their instances as one
 // contiguous range in chunks of 64 outputs, lane j writing output J + j.
 // The record owning an output is found without a search: records starting
@@ -710,41 +721,43 @@ __global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict
 // gives every lane the number of records started up to its output, and the
 // compacted list of records that own tiles turns that count into a lane.
 __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
-                                             const uint32_t *__restrict__ ioff, const ViewDev *__restrict__ views,
-                                             const Status *__restrict__ st, uint32_t *__restrict__ ikey,
+                                             const uint32_t *__restrict__ ioff, const Status *__restrict__ st,
+                                             float qcut, uint32_t dead_tile, uint32_t *__restrict__ ikey,
                                              uint32_t *__restrict__ ival) {
-    __shared__ uint4 srec[WAVES][64];      // x0y0, x1y1, tile base, tiles_x of each record
     __shared__ uint2 sid[WAVES][64];       // record index, first output (relative)
+    __shared__ float4 sgA[WAVES][64];      // band-test constants of each record: fx, fy, kx, 1 / a
+    __shared__ float4 sgB[WAVES][64];      // c, ey of the rightmost point, half height, anchor (bits)
+    __shared__ uint2 sgC[WAVES][64];       // first tile, rectangle dims
     __shared__ uint8_t cl[WAVES][64];      // lanes of the records that own at least one tile, in order
     __shared__ uint8_t mk[WAVES][64];      // 1 where a record starts at that output of the chunk
     if (st->overflow) return;
     const uint64_t n = st->R_eff;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t nwaves = (uint64_t)gridDim.x * WAVES;
+    const float qc = band_threshold(qcut), sq = sqrtf(qc);
     for (uint64_t c = (uint64_t)blockIdx.x * WAVES + w; c * 64 < n; c += nwaves) {
         const uint64_t i = c * 64 + lane;
         const bool valid = i < n;
-        uint32_t r = 0, o = 0, nt = 0, a0 = 0, a1 = 0, tb = 0, tx = 1;
+        uint32_t r = 0, o = 0, nt = 0;
+        Bin B = {};
         if (valid) {
             r = sval[i];
-            const Bin B = bin[r];
+            B = bin[r];
             o = ioff[i];
-            nt = B.ntiles;
-            a0 = B.x0y0;
-            a1 = B.x1y1;
-            if (nt) {
-                const ViewDev &V = views[B.view];
-                tb = (uint32_t)V.tile_base;
-                tx = (uint32_t)V.tiles_x;
-            }
+            nt = bin_ntiles(B.dims);
         }
         const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
         const uint32_t rel = o - o0;
         const bool owns = valid && nt > 0;
         const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
         if (owns) cl[w][lanes_below(own)] = (uint8_t)lane;
-        srec[w][lane] = make_uint4(a0, a1, tb, tx);
         sid[w][lane] = make_uint2(r, rel);
+        if (owns) {
+            const EllipseBands E = ellipse_bands(B.l11, B.l21, B.l22, sq);
+            sgA[w][lane] = make_float4(B.fx, B.fy, E.kx, E.ia);
+            sgB[w][lane] = make_float4(B.l22, E.eyR, E.hy, __int_as_float(B.uvr));
+            sgC[w][lane] = make_uint2(B.tile0, B.dims);
+        }
         // total outputs of the wave = end of the last record that owns tiles
         uint32_t total = 0;
         if (own) {
@@ -766,16 +779,23 @@ __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, 
             const uint32_t j = J + lane;
             if (j < total) {
                 const int q = cl[w][upto - 1];
-                const uint4 R = srec[w][q];
                 const uint2 id = sid[w][q];
+                const uint2 C = sgC[w][q];
                 const uint32_t k = j - id.y;
-                const uint32_t x0 = R.x & 0xFFFF, y0 = R.x >> 16, wx = (R.y & 0xFFFF) - x0;
+                const uint32_t wx = bin_wx(C.y);
                 // k / wx in floating point (k < 2^24), corrected to the exact quotient
                 uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)wx));
                 int32_t rem = (int32_t)(k - ty * wx);
                 if (rem < 0) { --ty; rem += (int32_t)wx; }
                 else if (rem >= (int32_t)wx) { ++ty; rem -= (int32_t)wx; }
-                ikey[o0 + j] = R.z + (y0 + ty) * R.w + x0 + (uint32_t)rem;
+                // quadrants of the tile the ellipse reaches; none: the instance is dead
+                const float4 A = sgA[w][q], Bq = sgB[w][q];
+                const int uvr = __float_as_int(Bq.w);
+                const float ux = (float)((int)(int16_t)(uvr & 0xFFFF) - rem * TILE) + A.x;
+                const float uy = (float)((uvr >> 16) - (int)ty * TILE) + A.y;
+                const uint32_t qm = quadrant_mask_bands(ux, uy, A.z, A.w, Bq.x, Bq.y, Bq.z, qc);
+                const uint32_t tile = qm ? C.x + ty * bin_tiles_x(C.y) + (uint32_t)rem : dead_tile;
+                ikey[o0 + j] = tile | (qm << QMASK_SHIFT);
                 ival[o0 + j] = id.x;
             }
             started += (uint32_t)__popcll(P);
@@ -787,15 +807,17 @@ __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, 
     }
 }
 
-// [start, end) of every tile's run in the sorted instance list.
+// [start, end) of every tile's run in the sorted instance list (instances
+// past the last tile are dead and belong to no run).
 __global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key, const Status *__restrict__ st,
-                                               uint2 *__restrict__ ranges) {
+                                               uint32_t dead_tile, uint2 *__restrict__ ranges) {
     if (st->overflow) return;
     const uint64_t n = st->M_eff;
     for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
-        const uint32_t k = key[i];
-        if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
-        if (i + 1 == n || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+        const uint32_t k = key[i] & TILE_KEY_MASK;
+        if (k >= dead_tile) continue;
+        if (i == 0 || (key[i - 1] & TILE_KEY_MASK) != k) ranges[k].x = (uint32_t)i;
+        if (i + 1 == n || (key[i + 1] & TILE_KEY_MASK) != k) ranges[k].y = (uint32_t)(i + 1);
     }
 }
 
@@ -941,13 +963,13 @@ void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *
     hipLaunchKernelGGL(k_gather_ntiles, dim3(2048), dim3(WG), 0, s, sval, bin, n_dev, icnt);
 }
 
-void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const ViewDev *views, const Status *st,
-                 uint32_t *ikey, uint32_t *ival, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, views, st, ikey, ival);
+void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
+                 uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
 }
 
-void launch_ranges(const uint32_t *key, const Status *st, uint2 *ranges, hipStream_t s) {
-    hipLaunchKernelGGL(k_ranges, dim3(4096), dim3(WG), 0, s, key, st, ranges);
+void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s) {
+    hipLaunchKernelGGL(k_ranges, dim3(4096), dim3(WG), 0, s, key, st, dead_tile, ranges);
 }
 
 }  // namespace gv

@@ -334,6 +334,8 @@ static gv_status plan_check(const gv_workspace *plan, const void *ws, int kind, 
                                   (long long)plan->n, (long long)n);
     if (nv > plan->n_views || tiles > plan->total_tiles || pixels > plan->total_pixels)
         return fail(GV_ERR_CAPACITY, "workspace plan too small for these views");
+    if (tiles >= (int64_t)TILE_KEY_MASK)
+        return fail(GV_ERR_UNSUPPORTED, "%lld tiles in one pass; at most %u", (long long)tiles, TILE_KEY_MASK - 1u);
     if (plan->max_records < 0 || plan->max_instances < 0 || plan->max_records > 0x7fffffffLL ||
         plan->max_instances > 0x7fffffffLL)
         return fail(GV_ERR_INVALID_ARG, "workspace capacities out of range");
@@ -345,6 +347,7 @@ static gv_status plan_check(const gv_workspace *plan, const void *ws, int kind, 
 struct Binned {
     const uint32_t *sval;   // record ids in depth order
     const uint32_t *ival;   // record ids in (tile, depth) order
+    const uint32_t *ikey;   // their instance keys (tile id, quadrant mask)
 };
 
 static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
@@ -387,20 +390,22 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
         launch_gather_ntiles(sval, bin, &st->R_eff, icnt, s);
         launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
-        launch_emit(sval, bin, ioff, views, st, ik0, iv0, s);
+        launch_emit(sval, bin, ioff, st, (float)(0.5 * geo.cut / std::log(2.0)), (uint32_t)tiles, ik0, iv0, s);
     }
     int tres;
     {
         StageScope sc(ctx, ST_SORT_TILE, s);
-        tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s);
+        // tile ids 0..tiles, where tiles marks dead instances
+        tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles + 1), false, hist, dtot, s);
     }
     const uint32_t *skey = tres ? ik1 : ik0;
     {
         StageScope sc(ctx, ST_RANGES, s);
-        launch_ranges(skey, st, ranges, s);
+        launch_ranges(skey, st, (uint32_t)tiles, ranges, s);
     }
     out.sval = sval;
     out.ival = tres ? iv1 : iv0;
+    out.ikey = skey;
     return GV_OK;
 }
 
@@ -609,13 +614,13 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         {
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                              bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
+                              bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
                               ctx->tuning.vis_batch, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
             launch_vf_accum(a, at<ViewDev>(workspace, Lay.views), at<uint32_t>(workspace, Lay.offs),
-                            at<Bin>(workspace, Lay.bin), accT, accC, st, L, al, acc_target,
+                            at<uint32_t>(workspace, Lay.vmask), mask_words(nv), accT, accC, st, L, al, acc_target,
                             half_out ? 0 : (int)gamma_dtype, acc, &st->measure[0], s);
         }
         GV_HIP(hipGetLastError());
@@ -675,7 +680,7 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
         {
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                              bz.ival, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
+                              bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
                               ctx->tuning.vis_batch, s);
         }
         {
@@ -747,7 +752,7 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
             StageScope sc(ctx, ST_RASTER_UQ, s);
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                             bz.ival, at<Rec>(workspace, Lay.rec), u, tpart, mp,
+                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), u, tpart, mp,
                              prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);

@@ -62,13 +62,27 @@ struct Rec {
 };
 static_assert(sizeof(Rec) == 32, "Rec layout");
 
-// Tile rectangle [x0, x1) x [y0, y1) of a record and its tile count.
+// What the binning needs of a record, in one 32-byte line: its tile
+// rectangle (first global tile id, tiles per view row, rectangle width and
+// height) and its ellipse relative to the rectangle's first tile.
+//   tile0     global id of the rectangle's top-left tile
+//   dims      tiles_x | (wx - 1) << 11 | (wy - 1) << 21 | live << 31
+//   uvr       anchor pixel minus 16 x the rectangle's first tile column / row,
+//             int16 x | int16 y << 16
+//   fx, fy, l11, l21, l22   as in Rec
 struct Bin {
-    int32_t view;
-    uint32_t x0y0;
-    uint32_t x1y1;
-    uint32_t ntiles;
+    uint32_t tile0;
+    uint32_t dims;
+    int32_t uvr;
+    float fx, fy;
+    float l11, l21, l22;
 };
+static_assert(sizeof(Bin) == 32, "Bin layout");
+
+__device__ __forceinline__ uint32_t bin_tiles_x(uint32_t dims) { return dims & 0x7FFu; }
+__device__ __forceinline__ uint32_t bin_wx(uint32_t dims) { return ((dims >> 11) & 0x3FFu) + 1u; }
+__device__ __forceinline__ uint32_t bin_wy(uint32_t dims) { return ((dims >> 21) & 0x3FFu) + 1u; }
+__device__ __forceinline__ uint32_t bin_ntiles(uint32_t dims) { return (dims >> 31) ? bin_wx(dims) * bin_wy(dims) : 0u; }
 
 // Status words at the start of every workspace.
 struct Status {
@@ -82,6 +96,13 @@ struct Status {
 };
 
 constexpr uint32_t DEAD_KEY = 0xFFFFFFFFu;
+
+// Instance keys: global tile id in the low QMASK_SHIFT bits (sorted on), the
+// record's quadrant mask for that tile in the bits above (carried along).
+// Instances whose mask is empty get the tile id one past the last tile, so
+// they sort behind every tile and no tile range contains them.
+constexpr int QMASK_SHIFT = 28;
+constexpr uint32_t TILE_KEY_MASK = (1u << QMASK_SHIFT) - 1u;
 
 // ---------------------------------------------------------------- wave helpers
 
@@ -144,6 +165,71 @@ __device__ __forceinline__ float load_f(const float *p, int64_t i) { return p[i]
 __device__ __forceinline__ float load_f(const _Float16 *p, int64_t i) { return (float)p[i]; }
 __device__ __forceinline__ float load_f(const uint16_t *p, int64_t i) {   // bfloat16 bits
     return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+
+
+// ---------------------------------------------------------------- tile-local geometry
+
+// Record -> tile-local form: centre relative to the tile origin, computed from
+// the integer anchor and the FP32 fraction so that it keeps full precision.
+__device__ __forceinline__ void local_centre(const Rec &R, int ox, int oy, float &ux, float &uy) {
+    const int ax = (int)(int16_t)(R.uv & 0xFFFF);
+    const int ay = R.uv >> 16;
+    ux = (float)(ax - ox) + R.fx;
+    uy = (float)(ay - oy) + R.fy;
+}
+
+// Quadrant test of the binning.  Bit q of the mask is set when the ellipse
+// p <= qc reaches the rectangle spanned by the pixel centres of quadrant q of
+// the tile (q = 2 row + column, quadrants of 8 x 8 pixels).  With the scaled
+// Cholesky factor L = [[a, 0], [b, c]] of the conic, p = u^2 + w^2 with
+// u = a ex + b ey, w = c ey, for the offset (ex, ey) = centre - point.  The
+// points of the ellipse in a horizontal band of rows form a convex set whose
+// x-extent comes from the extreme points of the ellipse: at offset ey the
+// chord spans x = ux + (b ey +- s) / a, s = sqrt(qc - (c ey)^2); the
+// rightmost point of the whole ellipse lies at ey_R = sqrt(qc) (b / c) / (c n),
+// n = sqrt(1 + (b / c)^2), the leftmost at -ey_R, and over a band the extreme
+// x are taken at ey_R and -ey_R clamped into the band.  The threshold and the
+// x-extent are widened so that rounding never drops a quadrant holding a
+// pixel the blend composites.
+struct EllipseBands {
+    float kx;    // b / a
+    float ia;    // 1 / a
+    float eyR;   // offset ey of the rightmost point
+    float hy;    // half height sqrt(qc) / c
+};
+
+__device__ __forceinline__ float band_threshold(float qcut) { return fmaf(qcut, 1.001f, 0.01f); }
+
+__device__ __forceinline__ EllipseBands ellipse_bands(float a, float b, float c, float sq) {
+    EllipseBands E;
+    E.ia = 1.0f / a;
+    E.kx = b * E.ia;
+    const float ic = 1.0f / c, bc = b * ic;
+    E.eyR = sq * bc * ic / sqrtf(fmaf(bc, bc, 1.0f));
+    E.hy = sq * ic;
+    return E;
+}
+
+__device__ __forceinline__ uint32_t quadrant_mask_bands(float ux, float uy, float kx, float ia, float c, float eyR,
+                                                     float hy, float qc) {
+    const float mg = fmaf(1e-5f, fabsf(ux), 0.01f);
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float lo = fmaxf(uy - (8.0f * j + 7.5f), -hy), hi = fminf(uy - (8.0f * j + 0.5f), hy);
+        const float eR = __builtin_amdgcn_fmed3f(eyR, lo, hi), eL = __builtin_amdgcn_fmed3f(-eyR, lo, hi);
+        const float tR = c * eR, tL = c * eL;
+        const float sR = sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f)), sL = sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
+        const float xmax = fmaf(sR, ia, fmaf(kx, eR, ux)) + mg;
+        const float xmin = fmaf(-sL, ia, fmaf(kx, eL, ux)) - mg;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bool in = lo <= hi && xmax >= 8.0f * i + 0.5f && xmin <= 8.0f * i + 7.5f;
+            m |= in ? 1u << (2 * j + i) : 0u;
+        }
+    }
+    return m;
 }
 
 }  // namespace gv

@@ -55,20 +55,20 @@ void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, cons
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s);
 void launch_vis_finish(int64_t n, float *out, hipStream_t s);
 void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
-void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const ViewDev *views, const Status *st,
-                 uint32_t *ikey, uint32_t *ival, hipStream_t s);
-void launch_ranges(const uint32_t *key, const Status *st, uint2 *ranges, hipStream_t s);
+void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
+                 uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
+void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s);
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
-                       hipStream_t s);
+                       const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
+                       int batch, hipStream_t s);
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
-                      int batch, hipStream_t s);
+                      const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps,
+                      unsigned long long *pairs, int batch, hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);
-void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const uint32_t *vmask, int mw,
                      const float *acc_T, const uint32_t *acc_c, const Status *st, int L, const float *al,
                      void *gamma, int gamma_dtype, bool accumulate, unsigned long long *pairs, hipStream_t s);
 

@@ -53,21 +53,6 @@ __device__ __forceinline__ void block_count(uint32_t c, unsigned long long *out)
 }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
-// Record -> tile-local form: centre relative to the tile origin, computed from
-// the integer anchor and the FP32 fraction so that it keeps full precision.
-__device__ __forceinline__ void local_centre(const Rec &R, int ox, int oy, float &ux, float &uy) {
-    const int ax = (int)(int16_t)(R.uv & 0xFFFF);
-    const int ay = R.uv >> 16;
-    ux = (float)(ax - ox) + R.fx;
-    uy = (float)(ay - oy) + R.fy;
-}
-
-template <int J>
-__device__ __forceinline__ uint32_t write_lane_c(uint32_t v, uint32_t x) {
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "i"(J));
-    return v;
-}
-
 // Compile-time loop: f(std::integral_constant<int, J>{}) for J = I .. N-1.
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -110,55 +95,6 @@ __device__ __forceinline__ void quadrant_pixel(int t, int &qx, int &qy) {
     const int w = t >> 6, l = t & 63;
     qx = ((w & 1) << 3) + (l & 7);
     qy = ((w >> 1) << 3) + (l >> 3);
-}
-
-// Bit q set when the ellipse p <= qcut can reach the rectangle spanned by the
-// pixel centres of quadrant q.  With the scaled Cholesky factor
-// L = [[a, 0], [b, c]] of the conic, p = (a ex + b ey)^2 + (c ey)^2 for the
-// offset (ex, ey) from the centre.  The minimum of this convex form over a
-// rectangle is 0 when the centre lies inside, else it lies on an edge, where
-// it is a clamped one-dimensional minimum: on a line x = X the minimising
-// y is uy + (a b / (b^2 + c^2)) (ux - X), on a line y = Y the minimising x
-// is ux + (b / a) (uy - Y).  The threshold is widened so that rounding never
-// drops a quadrant with a pixel the blend would composite; about a third of
-// the quadrants an axis-aligned box admits are rejected.
-__device__ __forceinline__ uint32_t quadrant_mask(float ux, float uy, float a, float b, float c, float qcut) {
-    const float thr = fmaf(qcut, 1.001f, 0.01f);
-    const float kx = b * __builtin_amdgcn_rcpf(a);
-    const float ky = a * b * __builtin_amdgcn_rcpf(fmaf(b, b, c * c));
-    constexpr float LO[2] = {0.5f, 8.5f}, HI[2] = {7.5f, 15.5f};
-    float pm[WAVES];
-#pragma unroll
-    for (int q = 0; q < WAVES; ++q) {
-        const int col = q & 1, row = q >> 1;
-        const bool inside = ux >= LO[col] && ux <= HI[col] && uy >= LO[row] && uy <= HI[row];
-        pm[q] = inside ? 0.0f : 3.0e38f;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int col = i >> 1;
-        const float X = (i & 1) ? HI[col] : LO[col];
-        // vertical edge x = X of the quadrants in column col
-        const float ex = ux - X, ys = fmaf(ky, ex, uy);
-#pragma unroll
-        for (int row = 0; row < 2; ++row) {
-            const float ey = uy - __builtin_amdgcn_fmed3f(ys, LO[row], HI[row]);
-            const float w1 = fmaf(a, ex, b * ey), w2 = c * ey;
-            pm[row * 2 + col] = fminf(pm[row * 2 + col], fmaf(w1, w1, w2 * w2));
-        }
-        // horizontal edge y = X of the quadrants in row col
-        const float ey = uy - X, xs = fmaf(kx, ey, ux);
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const float ex2 = ux - __builtin_amdgcn_fmed3f(xs, LO[cc], HI[cc]);
-            const float w1 = fmaf(a, ex2, b * ey), w2 = c * ey;
-            pm[col * 2 + cc] = fminf(pm[col * 2 + cc], fmaf(w1, w1, w2 * w2));
-        }
-    }
-    uint32_t m = 0;
-#pragma unroll
-    for (int q = 0; q < WAVES; ++q) m |= pm[q] <= thr ? (1u << q) : 0u;
-    return m;
 }
 
 // Records staged per batch (RB, a launch-time choice: 64, 128 or 256) and the
@@ -216,7 +152,8 @@ __device__ __forceinline__ int pad_slot(const int *slen, int &q) {
 template <int RB>
 __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
                                                    const uint2 *__restrict__ ranges,
-                                                   const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
+                                                   const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
+                                                   const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
                                                    uint32_t *__restrict__ acc_c) {
     constexpr int LCAP = RB + LGROUP;
@@ -247,10 +184,16 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     // records are prefetched: while batch k is blended, the records of batch
     // k + 1 and the record indices of batch k + 2 are in flight
     const bool loader = t < RB;
-    uint32_t r1 = 0, r2 = 0;
+    uint32_t r1 = 0, r2 = 0, k1 = 0, k2 = 0;   // record indices and instance keys
     Rec R1 = {};
-    if (loader && rg.x + t < rg.y) r1 = ival[rg.x + t];
-    if (loader && rg.x + RB + t < rg.y) r2 = ival[rg.x + RB + t];
+    if (loader && rg.x + t < rg.y) {
+        r1 = ival[rg.x + t];
+        k1 = ikey[rg.x + t];
+    }
+    if (loader && rg.x + RB + t < rg.y) {
+        r2 = ival[rg.x + RB + t];
+        k2 = ikey[rg.x + RB + t];
+    }
     if (loader && rg.x + t < rg.y) R1 = rec[r1];
 
     // Adds a finished batch's per-slot sums to the per-record accumulators.
@@ -273,16 +216,20 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
         if (__syncthreads_count(T >= eps_T) == 0) break;
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
-        const uint32_t r = r1;
+        const uint32_t r = r1, kq = k1;
         r1 = r2;
+        k1 = k2;
         if (loader && b + RB + t < rg.y) R1 = rec[r1];
-        if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
-        uint32_t mask = 0;
+        if (loader && b + 2 * RB + t < rg.y) {
+            r2 = ival[b + 2 * RB + t];
+            k2 = ikey[b + 2 * RB + t];
+        }
+        // quadrants of this tile the record's ellipse reaches (from the binning)
+        const uint32_t mask = have ? kq >> QMASK_SHIFT : 0u;
         float ux = 0.f, uy = 0.f;
         if (have) {
             local_centre(R, ox, oy, ux, uy);
             sR[cur * RB + t] = r;
-            mask = quadrant_mask(ux, uy, R.l11, R.l21, R.l22, qcut);
         }
         if (t < RB) {
             part[cur * RB + t] = 0.0f;
@@ -319,7 +266,8 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             const float2 B = wB[w][i0 + jl];
             float acc[LGROUP];
             // hit counts of the group, 8 bits per entry (at most 64 hits)
-            uint32_t cv = 0;
+            // hit counts of the group's entries, one byte each (at most 64 hits)
+            unsigned long long cnt8[2] = {0ull, 0ull};
             static_for<0, LGROUP>([&](auto jc) {
                 constexpr int jj = decltype(jc)::value;
                 // centre minus pixel: the sign flip leaves the quadratic form unchanged
@@ -333,7 +281,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
                 acc[jj] = a;
                 // T (1 - alpha), alpha = o 2^-p; a = 0 leaves T unchanged where there is no hit
                 T = fmaf(-a, row_bcast<jj>(B.y) * fast_exp2(-p), T);
-                cv = write_lane_c<4 * jj>(cv, (uint32_t)__popcll(bal));
+                cnt8[jj / 8] |= (unsigned long long)__popcll(bal) << (8 * (jj % 8));
             });
 #pragma unroll
             for (int jj = 0; jj < LGROUP; ++jj) scr[w][jj][lane] = acc[jj];
@@ -349,6 +297,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             sum += quad_perm_f<0x4E>(sum);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            const uint32_t cv = (uint32_t)(((ge < 8 ? cnt8[0] : cnt8[1]) >> (8 * (ge & 7))) & 0xFFull);
             if (gc == 0 && cv > 0u) {
                 const int slot = wS[w][i0 + ge];
                 atomicAdd(&part[slot], sum);
@@ -367,7 +316,8 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
 template <int RB, bool MAPS, bool COUNT>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ ival, const Rec *__restrict__ rec,
+                                                  const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
+                                                  const Rec *__restrict__ rec,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   unsigned long long *__restrict__ pairs) {
     constexpr int LCAP = RB + LGROUP;
@@ -396,20 +346,31 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
 
     // records are prefetched as in the VF CONST blend
     const bool loader = t < RB;
-    uint32_t r1 = 0, r2 = 0;
+    uint32_t r1 = 0, r2 = 0, k1 = 0, k2 = 0;   // record indices and instance keys
     Rec R1 = {};
-    if (loader && rg.x + t < rg.y) r1 = ival[rg.x + t];
-    if (loader && rg.x + RB + t < rg.y) r2 = ival[rg.x + RB + t];
+    if (loader && rg.x + t < rg.y) {
+        r1 = ival[rg.x + t];
+        k1 = ikey[rg.x + t];
+    }
+    if (loader && rg.x + RB + t < rg.y) {
+        r2 = ival[rg.x + RB + t];
+        k2 = ikey[rg.x + RB + t];
+    }
     if (loader && rg.x + t < rg.y) R1 = rec[r1];
 
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
         if (__syncthreads_count(T >= u.eps_T) == 0) break;
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
+        const uint32_t kq = k1;
         r1 = r2;
+        k1 = k2;
         if (loader && b + RB + t < rg.y) R1 = rec[r1];
-        if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
-        uint32_t mask = 0;
+        if (loader && b + 2 * RB + t < rg.y) {
+            r2 = ival[b + 2 * RB + t];
+            k2 = ikey[b + 2 * RB + t];
+        }
+        const uint32_t mask = have ? kq >> QMASK_SHIFT : 0u;
         float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
         if (have) {
             float ux, uy;
@@ -417,7 +378,6 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             const float v = R.v;
             a4 = make_float4(ux, uy, R.l11, R.l21);
             b4 = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
-            mask = quadrant_mask(ux, uy, R.l11, R.l21, R.l22, u.qcut);
         }
         int pos[WAVES];
         list_positions(mask, pos, scnt, slen);
@@ -551,7 +511,8 @@ __device__ __forceinline__ void store_f(uint16_t *p, int64_t i, float v) {   // 
 
 template <typename TG, typename TGam, int L>
 __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__restrict__ views,
-                                                 const uint32_t *__restrict__ offs, const Bin *__restrict__ bin,
+                                                 const uint32_t *__restrict__ offs, const uint32_t *__restrict__ vmask,
+                                                 int mw,
                                                  const float *__restrict__ acc_T, const uint32_t *__restrict__ acc_c,
                                                  const Status *__restrict__ st, ALs al, TGam *__restrict__ gamma,
                                                  bool accumulate, unsigned long long *__restrict__ pairs) {
@@ -575,25 +536,38 @@ __global__ __launch_bounds__(WG) void k_vf_accum(GaussArgs a, const ViewDev *__r
         float acc[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] = accumulate ? load_f((const TGam *)gamma, (int64_t)k * a.n + g) : 0.0f;
-        const uint32_t r0 = offs[g * PROJ_SPLIT], r1 = min(offs[(g + 1) * PROJ_SPLIT], st->R_eff);
-        for (uint32_t r = r0; r < r1; ++r) {
-            const uint32_t c = acc_c[r];
-            if (c == 0) continue;
-            npairs += c;
-            const float v = acc_T[r] / (float)c;
-            const ViewDev &V = views[bin[r].view];
-            float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
-            const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
-            if (!(nrm > 0.0f)) continue;
-            const float inv = 1.0f / nrm;
-            dx *= inv; dy *= inv; dz *= inv;
-            float Y[K];
-            sh_eval<L>(dx, dy, dz, Y);
+        // records of g in order: per view subset, the views whose bit is set in
+        // the cull's mask, ascending
+        const uint32_t rlim = st->R_eff;
+        for (int sub = 0; sub < PROJ_SPLIT; ++sub) {
+            const int64_t e = g * PROJ_SPLIT + sub;
+            uint32_t r = offs[e];
+            const uint32_t rend = min(offs[e + 1], rlim);
+            for (int wi = 0; wi < mw && r < rend; ++wi) {
+                uint32_t x = vmask[e * mw + wi];
+                while (x != 0u && r < rend) {
+                    const int vw = sub + PROJ_SPLIT * (32 * wi + __builtin_ctz(x));
+                    x &= x - 1u;
+                    const uint32_t c = acc_c[r];
+                    if (c == 0) { ++r; continue; }
+                    npairs += c;
+                    const float v = acc_T[r] / (float)c;
+                    const ViewDev &V = views[vw];
+                    float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+                    const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+                    if (!(nrm > 0.0f)) { ++r; continue; }
+                    const float inv = 1.0f / nrm;
+                    dx *= inv; dy *= inv; dz *= inv;
+                    float Y[K];
+                    sh_eval<L>(dx, dy, dz, Y);
 #pragma unroll
-            for (int l = 0; l <= L; ++l) {
-                const float va = v * al.a[l];
+                    for (int l = 0; l <= L; ++l) {
+                        const float va = v * al.a[l];
 #pragma unroll
-                for (int k = l * l; k < (l + 1) * (l + 1); ++k) acc[k] = fmaf(va, Y[k], acc[k]);
+                        for (int k = l * l; k < (l + 1) * (l + 1); ++k) acc[k] = fmaf(va, Y[k], acc[k]);
+                    }
+                    ++r;
+                }
             }
         }
 #pragma unroll
@@ -678,45 +652,45 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 
 template <int RB>
 static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                          const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
-    hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, rec, eps_T, qcut,
+                          const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
+    hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, ikey, rec, eps_T, qcut,
                        acc_T, acc_c);
 }
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                       const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
+                       const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
                        hipStream_t s) {
     if (total_tiles <= 0) return;
     switch (batch) {
-    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
-    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
-    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
     }
 }
 
 template <int RB>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                         const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
+                         const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
                          hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
     if (maps && pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, true, true>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
     else if (maps)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, true, false>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
     else if (pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, false, true>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, false, true>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
     else
-        hipLaunchKernelGGL((k_raster_uq<RB, false, false>), g, b, 0, s, views, nv, ranges, ival, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, false, false>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
+                      const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
                       int batch, hipStream_t s) {
     if (total_tiles <= 0) return;
     switch (batch) {
-    case 64: raster_uq_rb<64>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
-    case 256: raster_uq_rb<256>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
-    default: raster_uq_rb<128>(views, nv, total_tiles, ranges, ival, rec, u, tile_part, maps, pairs, s); break;
+    case 64: raster_uq_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
+    case 256: raster_uq_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
+    default: raster_uq_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
     }
 }
 
@@ -731,40 +705,40 @@ void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s) {
 }
 
 template <typename TG, typename TGam>
-static void accum_L(int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+static void accum_L(int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const uint32_t *vmask, int mw,
                     const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
                     bool accumulate, unsigned long long *pairs, hipStream_t s) {
     const unsigned grid = (unsigned)((a.n + WG - 1) / WG);
     TGam *gm = (TGam *)gamma;
     switch (L) {
-    case 0: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 0>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
-    case 1: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 1>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
-    case 2: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 2>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
-    default: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 3>), dim3(grid), dim3(WG), 0, s, a, views, offs, bin, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    case 0: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 0>), dim3(grid), dim3(WG), 0, s, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    case 1: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 1>), dim3(grid), dim3(WG), 0, s, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    case 2: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 2>), dim3(grid), dim3(WG), 0, s, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
+    default: hipLaunchKernelGGL((k_vf_accum<TG, TGam, 3>), dim3(grid), dim3(WG), 0, s, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gm, accumulate, pairs); break;
     }
 }
 
 template <typename TG>
-static void accum_gam(int gdt, int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+static void accum_gam(int gdt, int L, const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const uint32_t *vmask, int mw,
                       const float *acc_T, const uint32_t *acc_c, const Status *st, const ALs &al, void *gamma,
                       bool accumulate, unsigned long long *pairs, hipStream_t s) {
     switch (gdt) {
-    case 0: accum_L<TG, float>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
-    case 1: accum_L<TG, _Float16>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
-    default: accum_L<TG, uint16_t>(L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 0: accum_L<TG, float>(L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 1: accum_L<TG, _Float16>(L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    default: accum_L<TG, uint16_t>(L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
     }
 }
 
-void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const Bin *bin,
+void launch_vf_accum(const GaussArgs &a, const ViewDev *views, const uint32_t *offs, const uint32_t *vmask, int mw,
                      const float *acc_T, const uint32_t *acc_c, const Status *st, int L, const float *al_in,
                      void *gamma, int gamma_dtype, bool accumulate, unsigned long long *pairs, hipStream_t s) {
     if (a.n == 0) return;
     ALs al;
     for (int l = 0; l < 4; ++l) al.a[l] = l <= L ? al_in[l] : 0.0f;
     switch (a.dtype) {
-    case 0: accum_gam<float>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
-    case 1: accum_gam<_Float16>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
-    default: accum_gam<uint16_t>(gamma_dtype, L, a, views, offs, bin, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 0: accum_gam<float>(gamma_dtype, L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    case 1: accum_gam<_Float16>(gamma_dtype, L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
+    default: accum_gam<uint16_t>(gamma_dtype, L, a, views, offs, vmask, mw, acc_T, acc_c, st, al, gamma, accumulate, pairs, s); break;
     }
 }
 
