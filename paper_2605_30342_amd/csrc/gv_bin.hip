@@ -182,13 +182,16 @@ __device__ __forceinline__ void project_exact(const float m[3], const double S[6
 }
 
 template <typename TG>
+// Wave w of a block takes view subset sub = w (views sub, sub + PROJ_SPLIT,
+// ...) for the block's 64 Gaussians, one per lane, so that the view read in
+// each step is the same for the whole wave (scalar loads).
 __global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                               float znear, float lowpass, float cut, uint32_t *__restrict__ cnt,
                                               uint32_t *__restrict__ vmask, int mw) {
-    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const int64_t g = e / PROJ_SPLIT;
+    const int sub = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int64_t g = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     if (g >= G.n) return;
-    const int sub = (int)(e % PROJ_SPLIT);
+    const int64_t e = g * PROJ_SPLIT + sub;
     float m[3], s[3];
     G.mean(g, m);
     G.scale(g, s);
@@ -860,7 +863,8 @@ int mask_words(int nv) {
 
 void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt,
                   uint32_t *vmask, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n * PROJ_SPLIT + WG - 1) / WG);
+    static_assert(PROJ_SPLIT == WAVES, "one view subset per wave");
+    const unsigned grid = (unsigned)((a.n + 63) / 64);
     if (grid == 0) return;
     const int mw = mask_words(nv);
     switch (a.dtype) {
