@@ -24,7 +24,15 @@ sys.path.insert(0, ROOT)
 
 # VALU lane-operation slots per composited (pixel, Gaussian) pair, counted on
 # the inner loops of the two blend kernels (a transcendental counts 4 slots).
-VALU_SLOTS_PER_PAIR = {"raster_vis": 18.0, "raster_uq": 28.0}
+# Algorithmic VALU issue slots per composited (pixel, Gaussian) pair, with a
+# transcendental (exp2, log2) counted as 2 slots (half rate on gfx950, measured):
+#   VF CONST: offsets 2, first factor 2, second factor 1, quadratic form 2,
+#     overlap and termination tests 2, contribution select 1, alpha = o 2^-p 3,
+#     T update 1, sum of T 1                                          = 15
+#   VF QUERY: offsets to quadratic form 7, tests 2, alpha* = o' 2^-p + o0' 4,
+#     w* = alpha* T with select 2, x = v w* 1, log2 x with guard 3,
+#     sum x log x 1, sums of x and w* 2, T update 1                   = 23
+VALU_SLOTS_PER_PAIR = {"raster_vis": 15.0, "raster_uq": 23.0}
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: VALU lane-operation issue rate.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
