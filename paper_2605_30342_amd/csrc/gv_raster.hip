@@ -87,6 +87,11 @@ __device__ __forceinline__ float quad_perm_f(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
+// x from lane i - 4 of this lane's row (0 in lanes 0..3 of the row).
+__device__ __forceinline__ float row_shr4_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x114, 0xF, 0xF, true));
+}
+
 // ---------------------------------------------------------------- batch staging
 
 // A 16x16 tile is split into four 8x8 quadrants, one per wave.  Lane l of wave
@@ -133,15 +138,18 @@ __device__ __forceinline__ void list_positions(uint32_t mask, int pos[WAVES], in
     __syncthreads();
 }
 
-// Index of the first pad slot that thread t fills with a never-hit entry, or
-// -1 (threads 0..63 pad the four lists up to a multiple of LGROUP).
+// Lists are padded with never-hit entries to a multiple of LPAD; a list is
+// consumed in groups of LGROUP entries and, for its last 1..LPAD entries, one
+// group of LPAD.  Index of the pad slot thread t fills, or -1 (threads
+// 0 .. 4 LPAD - 1 pad the four lists).
+constexpr int LPAD = LGROUP / 2;
 __device__ __forceinline__ int pad_slot(const int *slen, int &q) {
     const int t = threadIdx.x;
-    q = t >> 4;
-    if (t >= WAVES * LGROUP) return -1;
+    q = t / LPAD;
+    if (t >= WAVES * LPAD) return -1;
     const int n = slen[q];
-    const int k = n + (t & (LGROUP - 1));
-    return k < ((n + LGROUP - 1) / LGROUP) * LGROUP ? k : -1;
+    const int k = n + (t % LPAD);
+    return k < ((n + LPAD - 1) / LPAD) * LPAD ? k : -1;
 }
 
 // ---------------------------------------------------------------- VF CONST raster (Alg. 2)
@@ -258,17 +266,17 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
         if (blast != rg.y) flush(cur ^ 1, blast);
         const int len = __builtin_amdgcn_readfirstlane(slen[w]);
         const int jl = lane & (LGROUP - 1);
-        for (int i0 = 0; i0 < len; i0 += LGROUP) {
-            if (__builtin_amdgcn_ballot_w64(T >= eps_T) == 0) break;
+        // one group of G entries (G = LGROUP, or LPAD for the last few)
+        auto group = [&](int i0, auto gs) {
+            constexpr int G = decltype(gs)::value;
             // lane j of every row loads entry i0 + j; entry jj then reaches all
-            // 64 pixels by row broadcast, so LDS is read once per 16 entries
+            // 64 pixels by row broadcast, so LDS is read once per group
             const float4 A = wA[w][i0 + jl];
             const float2 B = wB[w][i0 + jl];
-            float acc[LGROUP];
-            // hit counts of the group, 8 bits per entry (at most 64 hits)
+            float acc[G];
             // hit counts of the group's entries, one byte each (at most 64 hits)
             unsigned long long cnt8[2] = {0ull, 0ull};
-            static_for<0, LGROUP>([&](auto jc) {
+            static_for<0, G>([&](auto jc) {
                 constexpr int jj = decltype(jc)::value;
                 // centre minus pixel: the sign flip leaves the quadratic form unchanged
                 const float ex = row_bcast<jj>(A.x) - px, ey = row_bcast<jj>(A.y) - py;
@@ -283,26 +291,37 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
                 T = fmaf(-a, row_bcast<jj>(B.y) * fast_exp2(-p), T);
                 cnt8[jj / 8] |= (unsigned long long)__popcll(bal) << (8 * (jj % 8));
             });
+            // transpose: the 64 / G lanes of entry e = lane / (64 / G) each sum G
+            // pixels; their partial sums are combined by DPP within the row
+            constexpr int LPE = 64 / G;
 #pragma unroll
-            for (int jj = 0; jj < LGROUP; ++jj) scr[w][jj][lane] = acc[jj];
+            for (int jj = 0; jj < G; ++jj) scr[w][jj][lane] = acc[jj];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int ge = lane >> 2, gc = lane & 3;
-            const float4 *row = reinterpret_cast<const float4 *>(&scr[w][ge][gc * 16]);
-            const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
-            float sum = ((r0.x + r0.y) + (r0.z + r0.w)) + ((r1.x + r1.y) + (r1.z + r1.w)) +
-                        (((r2.x + r2.y) + (r2.z + r2.w)) + ((r3.x + r3.y) + (r3.z + r3.w)));
-            sum += quad_perm_f<0xB1>(sum);
-            sum += quad_perm_f<0x4E>(sum);
+            const int ge = lane / LPE, gc = lane % LPE;
+            const float4 *row = reinterpret_cast<const float4 *>(&scr[w][ge][gc * G]);
+            float sum = 0.0f;
+            static_for<0, G / 4>([&](auto rc) {
+                const float4 r = row[decltype(rc)::value];
+                sum += (r.x + r.y) + (r.z + r.w);
+            });
+            sum += quad_perm_f<0xB1>(sum);   // lanes (0 1 2 3) <- (1 0 3 2)
+            sum += quad_perm_f<0x4E>(sum);   // lanes (0 1 2 3) <- (2 3 0 1)
+            if constexpr (LPE == 8) sum += row_shr4_f(sum);   // lanes 4..7 <- 0..3 of the 8
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const uint32_t cv = (uint32_t)(((ge < 8 ? cnt8[0] : cnt8[1]) >> (8 * (ge & 7))) & 0xFFull);
-            if (gc == 0 && cv > 0u) {
+            if (gc == (LPE == 8 ? 4 : 0) && cv > 0u) {
                 const int slot = wS[w][i0 + ge];
                 atomicAdd(&part[slot], sum);
                 atomicAdd(&cpart[slot], cv);
             }
+        };
+        for (int i0 = 0; i0 < len; i0 += LGROUP) {
+            if (__builtin_amdgcn_ballot_w64(T >= eps_T) == 0) break;
+            if (len - i0 > LPAD) group(i0, std::integral_constant<int, LGROUP>{});
+            else group(i0, std::integral_constant<int, LPAD>{});
         }
         blast = b;
         cur ^= 1;
@@ -399,11 +418,12 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         __syncthreads();
         const int len = __builtin_amdgcn_readfirstlane(slen[w]);
         const int jl = lane & (LGROUP - 1);
-        for (int i0 = 0; i0 < len; i0 += LGROUP) {
-            if (__builtin_amdgcn_ballot_w64(T >= u.eps_T) == 0) break;
+        // one group of G entries (G = LGROUP, or LPAD for the last few)
+        auto group = [&](int i0, auto gs) {
+            constexpr int G = decltype(gs)::value;
             const float4 A = wA[w][i0 + jl];
             const float4 B = wB[w][i0 + jl];
-            static_for<0, LGROUP>([&](auto jc) {
+            static_for<0, G>([&](auto jc) {
                 // products and sums are rounded separately, so that every
                 // broadcast operand folds into its instruction
 #pragma clang fp contract(off)
@@ -426,6 +446,11 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                     if (COUNT) npairs += hit ? 1u : 0u;
                 }
             });
+        };
+        for (int i0 = 0; i0 < len; i0 += LGROUP) {
+            if (__builtin_amdgcn_ballot_w64(T >= u.eps_T) == 0) break;
+            if (len - i0 > LPAD) group(i0, std::integral_constant<int, LGROUP>{});
+            else group(i0, std::integral_constant<int, LPAD>{});
         }
         __syncthreads();
     }
