@@ -150,13 +150,22 @@ def default_uq_params(**kw) -> gv_uq_params:
     return p
 
 
+_CAMERA_DTYPE = None
+
+
 def cameras_to_c(cams) -> ctypes.Array:
-    """Host gv_camera[] from a scenes.Cameras."""
+    """Host gv_camera[] from a scenes.Cameras (filled column-wise with numpy)."""
+    global _CAMERA_DTYPE
+    if _CAMERA_DTYPE is None:
+        import numpy as np
+        _CAMERA_DTYPE = np.dtype([("R", np.float32, 9), ("t", np.float32, 3), ("K", np.float32, 4),
+                                  ("wh", np.int32, 2)])
+        assert _CAMERA_DTYPE.itemsize == ctypes.sizeof(gv_camera)
+    import numpy as np
     arr = (gv_camera * cams.n)()
-    for i in range(cams.n):
-        c = arr[i]
-        c.R[:] = [float(x) for x in cams.R[i].reshape(9)]
-        c.t[:] = [float(x) for x in cams.t[i]]
-        c.fx, c.fy, c.cx, c.cy = (float(x) for x in cams.K[i])
-        c.width, c.height = int(cams.wh[i, 0]), int(cams.wh[i, 1])
+    view = np.frombuffer(arr, dtype=_CAMERA_DTYPE, count=cams.n)
+    view["R"] = np.asarray(cams.R, dtype=np.float32).reshape(cams.n, 9)
+    view["t"] = np.asarray(cams.t, dtype=np.float32).reshape(cams.n, 3)
+    view["K"] = np.asarray(cams.K, dtype=np.float32).reshape(cams.n, 4)
+    view["wh"] = np.asarray(cams.wh, dtype=np.int32).reshape(cams.n, 2)
     return arr
