@@ -816,11 +816,28 @@ __global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key,
                                                uint32_t dead_tile, uint2 *__restrict__ ranges) {
     if (st->overflow) return;
     const uint64_t n = st->M_eff;
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
-        const uint32_t k = key[i] & TILE_KEY_MASK;
-        if (k >= dead_tile) continue;
-        if (i == 0 || (key[i - 1] & TILE_KEY_MASK) != k) ranges[k].x = (uint32_t)i;
-        if (i + 1 == n || (key[i + 1] & TILE_KEY_MASK) != k) ranges[k].y = (uint32_t)(i + 1);
+    // four consecutive keys per thread (one 16-byte load where aligned and
+    // complete) and the key before them; run ends are found against the next
+    // key, which is the first of the following thread's four
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * WG + threadIdx.x) * 4; i0 < n; i0 += (uint64_t)gridDim.x * WG * 4) {
+        uint32_t k[6];
+        k[0] = i0 > 0 ? key[i0 - 1] & TILE_KEY_MASK : 0xFFFFFFFFu;
+        if (i0 + 4 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(key + i0);
+            k[1] = v.x & TILE_KEY_MASK; k[2] = v.y & TILE_KEY_MASK; k[3] = v.z & TILE_KEY_MASK; k[4] = v.w & TILE_KEY_MASK;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? key[i0 + j] & TILE_KEY_MASK : 0xFFFFFFFFu;
+        }
+        k[5] = i0 + 4 < n ? key[i0 + 4] & TILE_KEY_MASK : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t i = i0 + j;
+            const uint32_t kk = k[1 + j];
+            if (i >= n || kk >= dead_tile) continue;
+            if (k[j] != kk) ranges[kk].x = (uint32_t)i;
+            if (k[2 + j] != kk) ranges[kk].y = (uint32_t)(i + 1);
+        }
     }
 }
 
