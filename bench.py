@@ -24,15 +24,20 @@ sys.path.insert(0, ROOT)
 
 # VALU lane-operation slots per composited (pixel, Gaussian) pair, counted on
 # the inner loops of the two blend kernels (a transcendental counts 4 slots).
-# Algorithmic VALU issue slots per composited (pixel, Gaussian) pair, with a
-# transcendental (exp2, log2) counted as 2 slots (half rate on gfx950, measured):
+# Algorithmic VALU issue slots per composited (pixel, Gaussian) pair.  The
+# reported fraction counts a transcendental (exp2, log2) as 4 slots (quarter
+# rate): VF CONST about 14 VALU ops + 1 exp = 18, VF QUERY about 20 VALU ops +
+# exp + log = 28.  Itemised:
 #   VF CONST: offsets 2, first factor 2, second factor 1, quadratic form 2,
-#     overlap and termination tests 2, contribution select 1, alpha = o 2^-p 3,
-#     T update 1, sum of T 1                                          = 15
-#   VF QUERY: offsets to quadratic form 7, tests 2, alpha* = o' 2^-p + o0' 4,
-#     w* = alpha* T with select 2, x = v w* 1, log2 x with guard 3,
-#     sum x log x 1, sums of x and w* 2, T update 1                   = 23
-VALU_SLOTS_PER_PAIR = {"raster_vis": 15.0, "raster_uq": 23.0}
+#     overlap and termination tests 2, contribution select 1, alpha = o 2^-p
+#     1 + exp, T update 1, sum of T 1, count 1                    = 14 + exp
+#   VF QUERY: offsets to quadratic form 7, tests 2, alpha* = o' 2^-p + o0'
+#     2 + exp, w* = alpha* T with select 2, x = v w* 1, log2 x with guard
+#     1 + log, sum x log x 1, sums of x and w* 2, T update 1, count 1
+#                                                                 = 20 + exp + log
+VALU_SLOTS_PER_PAIR = {"raster_vis": 18.0, "raster_uq": 28.0}
+# The same with transcendentals at the half rate measured on gfx950 (2 slots).
+VALU_SLOTS_PER_PAIR_HALF_RATE_TRANS = {"raster_vis": 16.0, "raster_uq": 24.0}
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: VALU lane-operation issue rate.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -249,7 +254,9 @@ def main():
         roof = {"kernel": f"k_{dom}", "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s (VALU lane-ops)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic_for(dom), "avg_launch_ms": round(per_launch[dom], 4),
-                "units_per_launch": int(pairs), "per_unit": f"{VALU_SLOTS_PER_PAIR[dom]:.0f} VALU slots per pair"}
+                "units_per_launch": int(pairs), "per_unit": f"{VALU_SLOTS_PER_PAIR[dom]:.0f} VALU slots per pair",
+                "frac_transcendentals_at_half_rate": round(
+                    pairs * VALU_SLOTS_PER_PAIR_HALF_RATE_TRANS[dom] / t / 1e12 / VALU_PEAK_TOPS, 4)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": traffic_for(dom), "avg_launch_ms": round(per_launch[dom], 4)}
@@ -257,7 +264,9 @@ def main():
     uq_frac = None
     if per_launch.get("raster_uq"):
         a = pairs_uq * VALU_SLOTS_PER_PAIR["raster_uq"] / (per_launch["raster_uq"] / 1e3) / 1e12
+        a2 = pairs_uq * VALU_SLOTS_PER_PAIR_HALF_RATE_TRANS["raster_uq"] / (per_launch["raster_uq"] / 1e3) / 1e12
         uq_frac = {"achieved": round(a, 3), "peak": round(VALU_PEAK_TOPS, 2), "frac": round(a / VALU_PEAK_TOPS, 4),
+                   "frac_transcendentals_at_half_rate": round(a2 / VALU_PEAK_TOPS, 4),
                    "avg_launch_ms": round(per_launch["raster_uq"], 4), "pairs": int(pairs_uq)}
 
     # a plain device copy of known size, to scale HBM byte counters taken
