@@ -60,6 +60,11 @@ def lib():
         L.ora_vf_query.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
                                    d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
         L.ora_vf_query.restype = ctypes.c_int
+        L.ora_exact_visibility.argtypes = [i64, vp, i64, vp, d, vp, vp]
+        L.ora_exact_visibility.restype = d
+        L.ora_vf_query_exact.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, i64, d, i32, vp, vp, vp, vp,
+                                         d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
+        L.ora_vf_query_exact.restype = ctypes.c_int
         L.ora_multiview_visibility.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, d, d, d, d, i32, vp, vp]
         L.ora_multiview_visibility.restype = ctypes.c_int
         L.ora_argmax.argtypes = [vp, i32]
@@ -202,6 +207,55 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
                             prm.cut, gather_mode, _p(maps), _p(scores), _p(vq), _p(pflags), _p(stats))
     if rc:
         raise RuntimeError("oracle vf_query failed")
+    out_maps, out_flags, off = [], [], 0
+    for (w, h) in wh:
+        n = int(w) * int(h)
+        if maps is not None:
+            out_maps.append(maps[off:off + n].reshape(h, w))
+        out_flags.append(pflags[off:off + n].reshape(h, w).astype(bool))
+        off += n
+    return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
+            "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+
+
+def camera_centres(cams) -> np.ndarray:
+    """[V][3] camera centres C = -R^T t in FP64."""
+    R = np.asarray(cams.R, dtype=np.float64).reshape(-1, 3, 3)
+    t = np.asarray(cams.t, dtype=np.float64).reshape(-1, 3)
+    return -np.einsum("vji,vj->vi", R, t)
+
+
+def exact_visibility(vtrain_g, train_centres, kappa: float, x, C) -> float:
+    """Exact multi-view visibility of one Gaussian at x seen from C (eq. vis_all
+    with eq. vis_p): 1 - prod_p (1 - v_p exp(kappa (d.d_p - 1)))."""
+    v = _f64(vtrain_g)
+    tc = _f64(train_centres).reshape(-1, 3)
+    return float(lib().ora_exact_visibility(len(v), _p(v), 1, _p(tc), float(kappa), _p(_f64(x)), _p(_f64(C))))
+
+
+def vf_query_exact(scene, vtrain, train_cams, kappa: float, cams, prm: Params = Params(), gather_mode: int = 0,
+                   want_maps: bool = True, want_vq: bool = False):
+    """Alg. 6 for every view in `cams` with the exact multi-view visibility
+    (eq. vis_all) in place of the SH query: vtrain [n_train][n] holds v_p of
+    every Gaussian in every training view (as from vf_build(want_views=True)).
+    Same outputs as vf_query."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    vt = _f64(vtrain)
+    tc = camera_centres(train_cams)
+    npx = int(np.sum(wh[:, 0].astype(np.int64) * wh[:, 1]))
+    maps = np.zeros(npx) if want_maps else None
+    pflags = np.zeros(npx, dtype=np.uint8)
+    scores = np.zeros(cams.n)
+    stats = np.zeros(4, dtype=np.int64)
+    vq = np.zeros((cams.n, scene.n)) if want_vq else None
+    rc = lib().ora_vf_query_exact(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(vt), _p(tc),
+                                  int(train_cams.n), float(kappa), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta,
+                                  prm.o0, prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear,
+                                  prm.lowpass, prm.cut, gather_mode, _p(maps), _p(scores), _p(vq), _p(pflags),
+                                  _p(stats))
+    if rc:
+        raise RuntimeError("oracle vf_query_exact failed")
     out_maps, out_flags, off = [], [], 0
     for (w, h) in wh:
         n = int(w) * int(h)

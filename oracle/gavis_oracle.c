@@ -11,6 +11,8 @@
  *   - single-view particle visibility                      (Appendix, Alg. 2)
  *   - visibility-field construction                        (Alg. 3, eq. vis_gamma)
  *   - visibility-field query with the AM-GM bound          (Alg. 1 / Alg. 4, eq. vis_bound)
+ *   - exact multi-view visibility, the quantity the field  (eq. vis_all with eq. vis_p)
+ *     and the bound approximate (validation mode)
  *   - uncertainty-quantification rasterisation             (Alg. 6, eq. alpha_comp, eq. huber)
  *   - view score and next-best-view argmax                 (eq. i_gain, eq. id with f_corr = 0)
  *
@@ -668,6 +670,31 @@ double ora_query_visibility(const double *gamma_g, int32_t L, int64_t n_train, c
     return 1.0 - pow(1.0 - Vt / P, P);
 }
 
+/* Multi-view visibility in direction d = x_g - C, exactly (eq. vis_all with
+ * eq. vis_p): V = 1 - prod_p (1 - v_p nu(d; d_p)), nu = zeta exp(kappa d.d_p)
+ * with zeta = exp(-kappa), unit d and d_p = x_g - C_p.  v_p = Phi T of view p
+ * (the single-view visibility of Alg. 2), read as vtrain[p * stride].  A
+ * Gaussian at a camera centre has no direction and gets 0 from that view
+ * (and V = 0 when it sits at the querying centre). */
+double ora_exact_visibility(int64_t n_train, const double *vtrain, int64_t stride, const double *trainC,
+                            double kappa, const double *x, const double *C)
+{
+    double d[3] = {x[0] - C[0], x[1] - C[1], x[2] - C[2]};
+    double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(nd > 0.0)) return 0.0;
+    double prod = 1.0;
+    for (int64_t p = 0; p < n_train; ++p) {
+        double vp = vtrain[p * stride];
+        if (vp == 0.0) continue;
+        double e[3] = {x[0] - trainC[3 * p], x[1] - trainC[3 * p + 1], x[2] - trainC[3 * p + 2]};
+        double ne = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        if (!(ne > 0.0)) continue;
+        double cosang = (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]) / (nd * ne);
+        prod *= 1.0 - vp * exp(-kappa) * exp(kappa * cosang);
+    }
+    return 1.0 - prod;
+}
+
 /* -x log x, with its limit 0 at x = 0 */
 static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
 
@@ -685,12 +712,14 @@ static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
  * pflags (optional) likewise, 1 where a near-tie decision touches the pixel.
  * vq (optional) [n_views][n] receives the queried visibility.
  * stats [4]: pairs composited, list entries, flagged pixels, total pixels. */
-int ora_vf_query(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
-                 int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
-                 int32_t n_views, const double *camR, const double *camT, const double *camK, const int32_t *camWH,
-                 double beta, double o0, double half_logdet_Q0, double half_logdet_Qc,
-                 double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
-                 double *maps, double *scores, double *vq, uint8_t *pflags, int64_t *stats)
+static int vf_query_core(int64_t n, const double *means, const double *scales, const double *quats,
+                         const double *opac, int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
+                         const double *vtrain, const double *trainC, double kappa,
+                         int32_t n_views, const double *camR, const double *camT, const double *camK,
+                         const int32_t *camWH, double beta, double o0, double half_logdet_Q0,
+                         double half_logdet_Qc, double eps_T, double znear, double lowpass, double cut,
+                         int32_t gather_mode, double *maps, double *scores, double *vq, uint8_t *pflags,
+                         int64_t *stats)
 {
     if (n < 0 || n_views < 0 || L < 0 || L > ORA_LMAX || n_virtual < 0 || n_virtual > n) return -1;
     int K = (L + 1) * (L + 1);
@@ -708,7 +737,9 @@ int ora_vf_query(int64_t n, const double *means, const double *scales, const dou
         for (int64_t g = 0; g < n; ++g) {
             project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
             double d[3] = {means[3 * g] - c.C[0], means[3 * g + 1] - c.C[1], means[3 * g + 2] - c.C[2]};
-            v[g] = (g >= n - n_virtual) ? 0.0 : ora_query_visibility(&gamma[(size_t)g * K], L, n_train, d);
+            if (g >= n - n_virtual) v[g] = 0.0;
+            else if (vtrain) v[g] = ora_exact_visibility(n_train, &vtrain[g], n, trainC, kappa, &means[3 * g], c.C);
+            else v[g] = ora_query_visibility(&gamma[(size_t)g * K], L, n_train, d);
             if (vq) vq[(size_t)p * n + g] = v[g];
         }
         olists Ls = {0, 0};
@@ -765,6 +796,35 @@ int ora_vf_query(int64_t n, const double *means, const double *scales, const dou
     if (stats) { stats[0] = pairs; stats[1] = entries; stats[2] = nflag; stats[3] = npix_total; }
     free(P); free(v);
     return rc;
+}
+
+int ora_vf_query(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                 int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
+                 int32_t n_views, const double *camR, const double *camT, const double *camK, const int32_t *camWH,
+                 double beta, double o0, double half_logdet_Q0, double half_logdet_Qc,
+                 double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
+                 double *maps, double *scores, double *vq, uint8_t *pflags, int64_t *stats)
+{
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, n_views,
+                         camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
+                         lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
+}
+
+/* The same with the exact multi-view visibility in place of the SH query:
+ * vtrain [n_train][n] holds v_p of every Gaussian in every training view,
+ * trainC [n_train][3] the training camera centres. */
+int ora_vf_query_exact(int64_t n, const double *means, const double *scales, const double *quats,
+                       const double *opac, int64_t n_virtual, const double *vtrain, const double *trainC,
+                       int64_t n_train, double kappa, int32_t n_views, const double *camR, const double *camT,
+                       const double *camK, const int32_t *camWH, double beta, double o0, double half_logdet_Q0,
+                       double half_logdet_Qc, double eps_T, double znear, double lowpass, double cut,
+                       int32_t gather_mode, double *maps, double *scores, double *vq, uint8_t *pflags,
+                       int64_t *stats)
+{
+    if (n_train < 0 || (n_train > 0 && (!vtrain || !trainC))) return -1;
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, NULL, 0, n_train, vtrain, trainC, kappa,
+                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T,
+                         znear, lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
 }
 
 /* Next-best view (eq. i_gain): index of the largest score, lowest index on

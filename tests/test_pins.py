@@ -462,3 +462,127 @@ def test_multiview_visibility_special_cases():
     sc = stack_scene([1.0, 2.0], [0.0, 0.7], scale=0.01)       # transparent in front of a real one
     v, c, _ = oracle.single_view(sc, cam1, 0)
     assert v[1] == 1.0
+
+
+# ---------------------------------------------------------------- exact multi-view visibility (eq. vis_all)
+
+def _unit(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v)
+
+
+def test_exact_visibility_single_view_closed_forms():
+    """One training view: V = v_p nu(d; d_p) = v_p e^{kappa (cos theta - 1)}.
+    Gaussian at the origin, training camera on -z.  Queried from the same
+    centre theta = 0 and V = v_p; from +x (theta = 90 deg) V = v_p e^{-kappa};
+    from +z (theta = 180 deg) V = v_p e^{-2 kappa}.  v_p = 0.6, kappa = 1:
+    0.6, 0.2207277, 0.0812012."""
+    x = np.zeros(3)
+    Cp = np.array([[0.0, 0.0, -3.0]])
+    v = [0.6]
+    for C, expect in (((0.0, 0.0, -2.0), 0.6), ((5.0, 0.0, 0.0), 0.2207277), ((0.0, 0.0, 4.0), 0.0812012)):
+        got = oracle.exact_visibility(v, Cp, 1.0, x, C)
+        assert got == pytest.approx(expect, abs=5e-8)
+    # kappa = 0 is isotropic: V = v_p from every direction
+    assert oracle.exact_visibility(v, Cp, 0.0, x, (0.0, 4.0, 0.0)) == pytest.approx(0.6, rel=1e-15)
+    # a Gaussian at the querying centre has no direction: V = 0
+    assert oracle.exact_visibility(v, Cp, 1.0, x, (0.0, 0.0, 0.0)) == 0.0
+
+
+def test_exact_visibility_two_views_by_hand():
+    """Two training views on -z and +x of a Gaussian at the origin, v = (0.5,
+    0.3), queried from -z: view 1 is aligned (nu = 1), view 2 is at 90 deg
+    (nu = e^{-1}), so V = 1 - 0.5 (1 - 0.3/e) = 0.5551819 (kappa = 1)."""
+    Cp = np.array([[0.0, 0.0, -3.0], [2.0, 0.0, 0.0]])
+    got = oracle.exact_visibility([0.5, 0.3], Cp, 1.0, np.zeros(3), (0.0, 0.0, -1.0))
+    assert got == pytest.approx(0.5551819, abs=5e-8)
+    # a view with v_p = 0 changes nothing; a view with v_p nu = 1 makes V = 1
+    assert oracle.exact_visibility([0.5, 0.0], Cp, 1.0, np.zeros(3), (0.0, 0.0, -1.0)) == pytest.approx(0.5)
+    assert oracle.exact_visibility([1.0, 0.3], Cp, 1.0, np.zeros(3), (0.0, 0.0, -1.0)) == 1.0
+
+
+def test_sh_query_approaches_exact_for_identical_views():
+    """|P| copies of one training view: all v_p nu_p are equal, so the AM-GM
+    bound is tight (eq. vis_bound) and the SH query (Alg. 4) differs from the
+    exact product only by the truncated tail: |V_L - V_exact| <= |P| e^{-kappa}
+    sum_{l>L} (2l+1) i_l(kappa).  Ties the SH path (Bessel table, real SH,
+    addition theorem) to the direct product."""
+    from paper_2605_30342_amd.scenes import Cameras
+    cam1 = axis_camera(32, 32, 60.0, center=(0.0, 0.0, -3.0))
+    P = 4
+    camP = Cameras(np.repeat(cam1.R, P, 0), np.repeat(cam1.t, P, 0), np.repeat(cam1.K, P, 0),
+                   np.repeat(cam1.wh, P, 0))
+    sc = stack_scene([0.0, -0.5], [0.8, 0.4], scale=0.1)
+    Cp = oracle.camera_centres(camP)
+    np.testing.assert_allclose(Cp, np.tile([0.0, 0.0, -3.0], (P, 1)), atol=1e-7)
+    for L in (2, 3):
+        b = oracle.vf_build(sc, camP, L, want_views=True)
+        tail = math.exp(-1.0) * sum((2 * l + 1) * float(sp.spherical_in(l, 1.0)) for l in range(L + 1, 60))
+        for g in range(2):
+            x = sc.means[g].astype(np.float64)
+            for d in _rand_dirs(6):
+                C = x - 2.5 * _unit(d)                 # query camera seeing x along d
+                Vq = oracle.query_visibility(b["gamma"][g], L, P, d)
+                Ve = oracle.exact_visibility(b["vview"][:, g], Cp, 1.0, x, C)
+                assert abs(Vq - Ve) <= P * tail + 1e-12
+
+
+def test_exact_visibility_dominates_am_gm_of_exact_sum():
+    """For distinct training views the exact product is never below the AM-GM
+    bound of the same (untruncated) sum (eq. vis_bound): with S = sum_p v_p
+    nu_p, 1 - (1 - S/|P|)^|P| <= V_exact.  The SH query at L = 3 follows the
+    bound to within the truncation tail."""
+    from paper_2605_30342_amd import scenes
+    w = scenes.workload("tiny", scale=0.2)
+    L = 3
+    b = oracle.vf_build(w.scene, w.train, L, want_views=True)
+    Cp = oracle.camera_centres(w.train)
+    P = w.train.n
+    tail = math.exp(-1.0) * sum((2 * l + 1) * float(sp.spherical_in(l, 1.0)) for l in range(L + 1, 60))
+    checked = 0
+    for g in range(0, w.scene.n, 41):
+        x = w.scene.means[g].astype(np.float64)
+        for d in _rand_dirs(3):
+            C = x - 2.0 * _unit(d)
+            Ve = oracle.exact_visibility(b["vview"][:, g], Cp, 1.0, x, C)
+            Vq = oracle.query_visibility(b["gamma"][g], L, P, d)
+            assert Vq <= Ve + P * tail + 1e-12
+            checked += 1
+    assert checked > 10
+
+
+def test_vf_query_exact_single_pixel_closed_form():
+    """1x1 image, one Gaussian on the pixel centre, one training view equal to
+    the querying camera: V = v_p exactly, so the map matches the closed form of
+    eq. alpha_comp / eq. huber with that v (as for the SH query; sigma_c = 1
+    so that c_c = c_0)."""
+    sc = stack_scene([2.0], [0.6], scale=0.01)
+    cam = axis_camera(1, 1, 50.0)
+    alpha = float(np.float32(0.6))
+    c3 = 1.5 * math.log(2 * math.pi * math.e)
+
+    def xl(t):
+        return -t * math.log(t) if t > 0 else 0.0
+    for v in (0.0, 0.25, 1.0):
+        out = oracle.vf_query_exact(sc, np.array([[v]]), cam, 1.0, cam, Params(sigma_c=1.0), want_vq=True)
+        assert out["vq"][0, 0] == pytest.approx(v, rel=1e-15)
+        a = (v + 0.5 * (1 - v)) * alpha + 0.15 * 0.5 * (1 - v)
+        closed = xl(a * v) + a * v * c3 + xl(a * (1 - v)) + a * (1 - v) * c3
+        assert out["maps"][0][0, 0] == pytest.approx(closed, rel=1e-12)
+
+
+def test_vf_query_exact_virtual_particles_and_no_views():
+    """Virtual particles have V = 0 in the exact mode too, and with no training
+    view every V is 0: the maps equal those of the SH query with n_train = 0."""
+    from paper_2605_30342_amd import scenes
+    w = scenes.workload("tiny", scale=0.25)
+    nv = 40
+    sc = scenes.Scene(w.scene.means, w.scene.scales, w.scene.quats, w.scene.opacity, n_virtual=nv)
+    b = oracle.vf_build(sc, w.train, 2, want_views=True)
+    out = oracle.vf_query_exact(sc, b["vview"], w.train, 1.0, w.cand, want_vq=True)
+    assert np.all(out["vq"][:, sc.n - nv:] == 0.0) and np.any(out["vq"][:, :sc.n - nv] > 0.5)
+    assert np.all(out["vq"] >= 0.0) and np.all(out["vq"] <= 1.0)
+    empty = oracle.vf_query_exact(sc, np.zeros((0, sc.n)), scenes.Cameras(
+        w.train.R[:0], w.train.t[:0], w.train.K[:0], w.train.wh[:0]), 1.0, w.cand)
+    ref = oracle.vf_query(sc, np.zeros((sc.n, 9)), 2, 0, w.cand)
+    np.testing.assert_allclose(empty["scores"], ref["scores"], rtol=1e-13)
