@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=24, help="candidate views the CPU baseline runs")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-visibility validation mode")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default blend batch sizes instead of tuning them on this workload")
     ap.add_argument("--profile-only", action="store_true",
@@ -343,6 +344,29 @@ def main():
     del dm, gm, wsm
     log(f"precision {precision}")
 
+    # validation mode: the exact multi-view visibility (O(|P|) per record) in
+    # place of the field's AM-GM query, and the score gap between the two
+    exact = None
+    if not args.no_exact:
+        vis_v, centres = ctx.view_visibility(dsc, w.train, vprm, ws_b)
+        vv_ms = timed(lambda: ctx.view_visibility(dsc, w.train, vprm, ws_b), reps=3)
+        s_ex = torch.empty_like(scores)
+        ex_ms = timed(lambda: ctx.vf_query_views_exact(dsc, vis_v, centres, w.kappa, w.cand, uprm, ws_q,
+                                                       scores=s_ex), reps=3)
+        ctx.vf_query_views(dsc, gamma, L, w.train.n, w.cand, uprm, ws_q, scores=scores)
+        torch.cuda.synchronize()
+        se, sq = s_ex.double().cpu().numpy(), scores.double().cpu().numpy()
+        gap = np.abs(sq - se) / np.abs(se)
+        b_sh, b_ex = int(np.argmax(sq)), int(np.argmax(se))
+        exact = {"view_visibility_ms": round(vv_ms, 4), "exact_query_ms": round(ex_ms, 4),
+                 "max_rel_score_gap_sh_vs_exact": float(gap.max()),
+                 "median_rel_score_gap_sh_vs_exact": float(np.median(gap)),
+                 "best_view_sh": b_sh, "best_view_exact": b_ex,
+                 "exact_rank_of_sh_choice": int((se > se[b_sh]).sum()),
+                 "exact_score_ratio_of_sh_choice": float(se[b_sh] / se[b_ex])}
+        del vis_v, centres, s_ex
+        log(f"exact validation {exact}")
+
     serving = None
     if not args.no_serving:
         serving = serving_bench(ctx, w, dsc, gamma, L, log)
@@ -391,6 +415,7 @@ def main():
         "batching": batching,
         "precision": precision,
         "serving": serving,
+        "exact_validation": exact,
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -174,6 +174,19 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
                                   const gv_vf_params *params, float *visibility, const gv_workspace *plan,
                                   void *workspace, void *hip_stream);
 
+/* Per-view single-view visibility, the input of the exact validation mode:
+ * view_vis[p * n + g] = v_p[g] (device, float [n_train][n]), the visibility of
+ * Alg. 2 that vf_build weights each view's vMF lobe with (eq. vis_p without
+ * its directional factor); 0 where view p culls g or reaches none of its
+ * pixels.  train_centres (device, float [n_train][3], optional: NULL skips it)
+ * receives the camera centres C_p = -R_p^T t_p.  Uses the workspace plan of
+ * vf_build (same scene, views and params).  Enqueue only, except between
+ * passes when views_per_pass splits the views (then it synchronises to check
+ * capacity). */
+gv_status vf_view_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                             const gv_vf_params *params, float *view_vis, float *train_centres,
+                             const gv_workspace *plan, void *workspace, void *hip_stream);
+
 /* Workspace for vf_query_views over `n_cand` candidate views. */
 gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *cand,
                                   int32_t n_cand, const gv_uq_params *params, int32_t sh_degree,
@@ -192,6 +205,23 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
                          int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
                          const gv_uq_params *params, float *scores, float *maps,
                          const gv_workspace *plan, void *workspace, void *hip_stream);
+
+/* Validation mode of vf_query_views: the same Alg. 6 rasterisation and
+ * scores, with each Gaussian's visibility in direction d = camera -> Gaussian
+ * taken exactly from the per-view visibilities instead of from the field and
+ * its AM-GM bound: V = 1 - prod_p (1 - v_p exp(kappa (d . d_p - 1))) (eq.
+ * vis_all with eq. vis_p), d_p the unit direction from training camera p.
+ * The gap to vf_query_views measures the AM-GM and SH truncation error.
+ * view_vis: device float [n_train][n] and train_centres: device float
+ * [n_train][3], both as written by vf_view_visibility; kappa as in the
+ * field.  Costs O(n_train) per (Gaussian, candidate view) record.  Any query
+ * plan for these Gaussians and candidate views serves (its sh_degree is not
+ * used).  Virtual particles get V = 0; a training camera at a Gaussian's
+ * centre contributes nothing.  Enqueue only, as vf_query_views. */
+gv_status vf_query_views_exact(gv_context *ctx, const gv_gaussians *g, const float *view_vis,
+                               const float *train_centres, int32_t n_train, float kappa, const gv_camera *cand,
+                               int32_t n_cand, const gv_uq_params *params, float *scores, float *maps,
+                               const gv_workspace *plan, void *workspace, void *hip_stream);
 
 /* Synchronises hip_stream and reads the workspace's status words of the last
  * call (the last pass of a multi-pass build): out[0] records, out[1]

@@ -191,6 +191,53 @@ class Context:
                                              _ptr(out), ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
         return out
 
+    def view_visibility(self, dsc: DeviceScene, cams, params: Optional[_lib.gv_vf_params] = None,
+                        ws: Optional[Workspace] = None, stream=None):
+        """Per-view single-view visibility v_p[g] (Alg. 2), float [n_views][n],
+        and the camera centres, float [n_views][3]: the inputs of
+        vf_query_views_exact."""
+        if params is None:
+            params = _lib.default_vf_params()
+        if ws is None:
+            ws = self.build_workspace(dsc, cams, params, stream)
+        dev = f"cuda:{self.device}"
+        vis = torch.empty((cams.n, dsc.n), dtype=torch.float32, device=dev)
+        centres = torch.empty((cams.n, 3), dtype=torch.float32, device=dev)
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_view_visibility(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params), _ptr(vis),
+                                        _ptr(centres), ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
+        return vis, centres
+
+    def vf_query_views_exact(self, dsc: DeviceScene, view_vis: torch.Tensor, train_centres: torch.Tensor,
+                             kappa: float, cams, params: Optional[_lib.gv_uq_params] = None,
+                             ws: Optional[Workspace] = None, want_maps: bool = False,
+                             scores: Optional[torch.Tensor] = None, maps: Optional[torch.Tensor] = None,
+                             stream=None):
+        """Alg. 6 with the exact multi-view visibility (eq. vis_all) in place of
+        the field's AM-GM query; same outputs as vf_query_views."""
+        if params is None:
+            params = _lib.default_uq_params()
+        params.write_maps = 1 if want_maps else 0
+        if view_vis.dtype != torch.float32 or train_centres.dtype != torch.float32:
+            raise TypeError("view_vis and train_centres must be float32")
+        n_train = int(view_vis.shape[0])
+        if tuple(view_vis.shape) != (n_train, dsc.n) or tuple(train_centres.shape) != (n_train, 3):
+            raise ValueError("view_vis must be [n_train][n] and train_centres [n_train][3]")
+        view_vis, train_centres = view_vis.contiguous(), train_centres.contiguous()
+        if ws is None:
+            ws = self.query_workspace(dsc, cams, params, 0, stream)
+        dev = f"cuda:{self.device}"
+        if scores is None:
+            scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
+        if want_maps and maps is None:
+            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_query_views_exact(self.h, ctypes.byref(dsc.c), _ptr(view_vis), _ptr(train_centres),
+                                          n_train, float(kappa), cc, cams.n, ctypes.byref(params), _ptr(scores),
+                                          _ptr(maps) if want_maps else None, ctypes.byref(ws.plan), _ptr(ws.buf),
+                                          _stream(stream)))
+        return scores, maps
+
     def check_workspace(self, ws: Workspace, stream=None):
         """(status, (records, instances, overflow flags, pairs composited))."""
         out = (ctypes.c_int64 * 4)()

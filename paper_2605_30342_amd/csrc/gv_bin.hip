@@ -270,15 +270,23 @@ __device__ __forceinline__ int kth_set_bit(uint32_t x, uint32_t k) {
 // record is found from start marks and a ballot (as in the instance
 // emission), the view from the entry's visibility mask.  Lanes therefore stay
 // busy however few views of a Gaussian survive the cull.
-// QUERY: also evaluates the visibility field in the direction camera ->
-// Gaussian (Alg. 4): V~ = sum_k gamma_k Y_k(d), clamped to [0, |P|], then
-// V = 1 - (1 - V~/|P|)^|P| computed as 1 - exp(|P| log1p(-V~/|P|)).
-template <typename TG, typename TGam, bool QUERY, int L>
+// MODE 0 (build) leaves the record's visibility at 0.  The query modes store
+// the Gaussian's visibility in direction d = camera -> Gaussian:
+// MODE 1, the visibility field (Alg. 4): V~ = sum_k gamma_k Y_k(d), clamped to
+//   [0, |P|], then V = 1 - (1 - V~/|P|)^|P| as 1 - exp(|P| log1p(-V~/|P|));
+// MODE 2, the exact multi-view visibility (eq. vis_all with eq. vis_p):
+//   V = 1 - prod_p (1 - v_p nu_p), nu_p = exp(kappa (d . d_p - 1)), d_p the
+//   unit direction from training camera p, summed as logs and finished with
+//   expm1 so that small V keep their relative precision.  A training camera
+//   at the Gaussian's centre contributes nothing.
+template <typename TG, typename TGam, int MODE, int L>
 __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                                 float znear, float lowpass, float cut,
                                                 const uint32_t *__restrict__ offs, const uint32_t *__restrict__ vmask,
                                                 int mw, const Status *__restrict__ st, uint32_t rcap,
                                                 const TGam *__restrict__ gamma, float n_train,
+                                                const float *__restrict__ vtrain, const float *__restrict__ tc,
+                                                int ntv, float kappa_log2e,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                 Bin *__restrict__ bin) {
     constexpr int K = (L + 1) * (L + 1);
@@ -366,7 +374,27 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     R.l22 = (float)(sc * l22);
                     R.o = G.opacity(g);
                     float vis = 0.0f;
-                    if constexpr (QUERY) {
+                    if constexpr (MODE == 2) {
+                        const bool virt = g >= G.n - G.n_virtual;
+                        float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+                        const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+                        if (!virt && ntv > 0 && nrm > 0.0f) {
+                            const float inv = 1.0f / nrm;
+                            dx *= inv; dy *= inv; dz *= inv;
+                            float lsum = 0.0f;   // sum_p log(1 - v_p nu_p)
+                            for (int p = 0; p < ntv; ++p) {
+                                const float vp = vtrain[(int64_t)p * G.n + g];
+                                const float ex = m[0] - tc[3 * p], ey = m[1] - tc[3 * p + 1], ez = m[2] - tc[3 * p + 2];
+                                const float e2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                                const float cosang = fmaf(dx, ex, fmaf(dy, ey, dz * ez)) * rsqrtf(e2);
+                                const float nu = exp2f(kappa_log2e * (cosang - 1.0f));
+                                const float a = e2 > 0.0f ? fminf(vp * nu, 1.0f) : 0.0f;
+                                lsum += log1pf(-a);
+                            }
+                            vis = -expm1f(lsum);
+                        }
+                    }
+                    if constexpr (MODE == 1) {
                         const bool virt = g >= G.n - G.n_virtual;
                         if (!virt && n_train > 0.0f) {
                             float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
@@ -902,46 +930,59 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
     }
 }
 
-template <typename TG, typename TGam, bool QUERY>
+template <typename TG, typename TGam, int MODE>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
-                               const void *gamma, float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+                               const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
     const uint64_t chunks = ((uint64_t)a.n * PROJ_SPLIT + 63) / 64;
     const unsigned grid = (unsigned)std::min<uint64_t>((chunks + WAVES - 1) / WAVES, 4096);
     const int mw = mask_words(nv);
-    const TGam *gm = (const TGam *)gamma;
-    switch (L) {
-    case 0: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 0>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
-    case 1: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 1>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
-    case 2: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 2>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
-    default: hipLaunchKernelGGL((k_project<TG, TGam, QUERY, 3>), dim3(grid), dim3(WG), 0, s, gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, n_train, rec, key, bin); break;
+    const TGam *gm = (const TGam *)q.gamma;
+    const float kl = (float)(q.kappa * 1.4426950408889634);
+#define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
+        q.view_vis, q.train_centres, q.n_train_views, kl, rec, key, bin
+    if constexpr (MODE != 1) {   // no SH evaluation
+        hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
+    } else {
+        switch (L) {
+        case 0: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
+        case 1: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 1>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
+        case 2: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 2>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
+        default: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 3>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
+        }
     }
+#undef GV_PROJECT_ARGS
 }
 
 template <typename TG>
-static void project_dispatch_gam(int gdt, bool query, int L, const GaussArgs &a, const ViewDev *views, int nv,
-                                 const GeomArgs &p, const uint32_t *offs, const uint32_t *vmask, const Status *st,
-                                 uint32_t rcap,
-                                 const void *gamma, float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
-    if (!query) {
-        project_dispatch_L<TG, float, false>(0, a, views, nv, p, offs, vmask, st, rcap, nullptr, 0.f, rec, key, bin, s);
+static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
+                                 const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
+                                 const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+    if (!q) {
+        const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f};
+        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, s);
         return;
     }
-    switch (gdt) {
-    case 0: project_dispatch_L<TG, float, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    case 1: project_dispatch_L<TG, _Float16, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    default: project_dispatch_L<TG, uint16_t, true>(L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    if (q->mode == 2) {
+        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s);
+        return;
+    }
+    switch (q->gamma_dtype) {
+    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
+    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
+    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
     }
 }
 
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
-                    const uint32_t *vmask, const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
-                    float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+                    const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
+                    uint32_t *key, Bin *bin, hipStream_t s) {
     if (a.n == 0) return;
+    const int L = q ? q->sh_degree : 0;
     switch (a.dtype) {
-    case 0: project_dispatch_gam<float>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    case 1: project_dispatch_gam<_Float16>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
-    default: project_dispatch_gam<uint16_t>(gamma_dtype, query, L, a, views, nv, p, offs, vmask, st, rcap, gamma, n_train, rec, key, bin, s); break;
+    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
+    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
+    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
     }
 }
 

@@ -181,6 +181,7 @@ struct gv_context {
     ViewDev *dev_views = nullptr;                 // view table for sizing passes
     size_t dev_views_cap = 0;
     std::vector<ViewDev> host_views;
+    std::vector<float> host_centres;
     // captured query sequences, most recent last
     struct Graph {
         std::vector<unsigned char> key;
@@ -351,8 +352,7 @@ struct Binned {
 };
 
 static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
-                             int64_t tiles, const GeomArgs &geo, bool query, int sh, const void *gamma, int gdt,
-                             float n_train, hipStream_t s, Binned &out) {
+                             int64_t tiles, const GeomArgs &geo, const QueryArgs *query, hipStream_t s, Binned &out) {
     Status *st = at<Status>(ws, L.status);
     ViewDev *views = at<ViewDev>(ws, L.views);
     uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs), *vmask = at<uint32_t>(ws, L.vmask);
@@ -377,7 +377,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     }
     {
         StageScope sc(ctx, ST_PROJECT, s);
-        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, sh, gamma, gdt, n_train, rec, k0, bin, s);
+        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, s);
     }
     int dres;
     {
@@ -605,7 +605,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, false, L, nullptr, 0, 0.f, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
@@ -639,20 +639,25 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
     return GV_OK;
 }
 
-gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
-                                  const gv_vf_params *prm, float *visibility, const gv_workspace *plan,
-                                  void *workspace, void *hip_stream) {
+}  // extern "C"
+
+// Single-view visibility of every training view, pass by pass (Alg. 2).
+// multi = true: visibility[g] = 1 - prod_p (1 - v_p[g]) (Alg. 5);
+// multi = false: visibility[p * n + g] = v_p[g].
+static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                                 const gv_vf_params *prm, float *visibility, bool multi, const gv_workspace *plan,
+                                 void *workspace, void *hip_stream) {
     if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     GV_TRY(check_gauss(g));
     if (n_train < 0 || (n_train > 0 && !train)) return fail(GV_ERR_INVALID_ARG, "bad training views");
     GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
-    if (g->n > 0 && !visibility) return fail(GV_ERR_INVALID_ARG, "visibility is NULL");
+    if (g->n > 0 && (multi || n_train > 0) && !visibility) return fail(GV_ERR_INVALID_ARG, "visibility is NULL");
     if (!plan || !workspace) return fail(GV_ERR_INVALID_ARG, "NULL workspace or plan");
     DeviceGuard dg(ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
     if (g->n == 0) return GV_OK;
     if (n_train == 0) {
-        launch_fill_u32(reinterpret_cast<uint32_t *>(visibility), (uint64_t)g->n, 0u, s);
+        if (multi) launch_fill_u32(reinterpret_cast<uint32_t *>(visibility), (uint64_t)g->n, 0u, s);
         GV_HIP(hipGetLastError());
         return GV_OK;
     }
@@ -671,7 +676,7 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, false, 0, nullptr, 0, 0.f, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
@@ -685,8 +690,15 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
-            launch_vis_logsum(g->n, at<uint32_t>(workspace, Lay.offs), accT, accC, st, visibility, acc,
-                              &st->measure[0], s);
+            if (multi) {
+                launch_vis_logsum(g->n, at<uint32_t>(workspace, Lay.offs), accT, accC, st, visibility, acc,
+                                  &st->measure[0], s);
+            } else {
+                float *rows = visibility + (int64_t)v0 * g->n;
+                launch_fill_u32(reinterpret_cast<uint32_t *>(rows), (uint64_t)nv * (uint64_t)g->n, 0u, s);
+                launch_view_vis(a, at<uint32_t>(workspace, Lay.offs), at<uint32_t>(workspace, Lay.vmask),
+                                mask_words(nv), accT, accC, st, rows, &st->measure[0], s);
+            }
         }
         GV_HIP(hipGetLastError());
         if (v0 + vp < n_train) {
@@ -697,32 +709,54 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
         }
         acc = true;
     }
-    launch_vis_finish(g->n, visibility, s);
+    if (multi) launch_vis_finish(g->n, visibility, s);
     GV_HIP(hipGetLastError());
     return GV_OK;
 }
 
-gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
-                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
-                         const gv_uq_params *prm, float *scores, float *maps, const gv_workspace *plan,
-                         void *workspace, void *hip_stream) {
-    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
-    GV_TRY(check_gauss(g));
+extern "C" {
+
+gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                                  const gv_vf_params *prm, float *visibility, const gv_workspace *plan,
+                                  void *workspace, void *hip_stream) {
+    return view_visibility(ctx, g, train, n_train, prm, visibility, true, plan, workspace, hip_stream);
+}
+
+gv_status vf_view_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                             const gv_vf_params *prm, float *view_vis, float *train_centres,
+                             const gv_workspace *plan, void *workspace, void *hip_stream) {
+    GV_TRY(view_visibility(ctx, g, train, n_train, prm, view_vis, false, plan, workspace, hip_stream));
+    if (train_centres && n_train > 0) {
+        DeviceGuard dg(ctx->device);
+        std::vector<float> &hc = ctx->host_centres;
+        hc.resize((size_t)n_train * 3);
+        for (int32_t p = 0; p < n_train; ++p) {
+            const gv_camera &c = train[p];
+            for (int k = 0; k < 3; ++k)
+                hc[(size_t)p * 3 + k] = (float)(-((double)c.R[0 * 3 + k] * c.t[0] + (double)c.R[1 * 3 + k] * c.t[1] +
+                                                   (double)c.R[2 * 3 + k] * c.t[2]));
+        }
+        GV_HIP(hipMemcpyAsync(train_centres, hc.data(), hc.size() * sizeof(float), hipMemcpyHostToDevice,
+                              (hipStream_t)hip_stream));
+    }
+    return GV_OK;
+}
+
+}  // extern "C"
+
+// Alg. 6 over the candidate views with the visibility source `q` (the SH
+// field of Alg. 4 or the exact product of eq. vis_all).
+static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const QueryArgs &q, const gv_camera *cand,
+                             int32_t n_cand, const gv_uq_params *prm, float *scores, float *maps,
+                             const gv_workspace *plan, void *workspace, void *hip_stream) {
     if (n_cand < 1 || !cand) return fail(GV_ERR_INVALID_ARG, "need at least one candidate view");
     if (!scores) return fail(GV_ERR_INVALID_ARG, "scores is NULL");
-    if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
-        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", sh_degree, GV_MAX_SH_DEGREE);
-    if (n_train < 0) return fail(GV_ERR_INVALID_ARG, "n_train < 0");
-    if (n_train > 0 && g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
-    if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
-        return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
     GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
     if (!(prm->beta >= 0.f && prm->beta <= 1.f && prm->o0 >= 0.f && prm->o0 <= 1.f))
         return fail(GV_ERR_INVALID_ARG, "beta and o0 must lie in [0, 1]");
     if (!std::isfinite(prm->half_logdet_Q0) || !std::isfinite(prm->half_logdet_Qc))
         return fail(GV_ERR_INVALID_ARG, "non-finite covariance log-determinants");
     if (prm->write_maps && !maps) return fail(GV_ERR_INVALID_ARG, "write_maps set but maps is NULL");
-    if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
     DeviceGuard dg(ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<ViewDev> &views = ctx->host_views;
@@ -745,8 +779,7 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     float *mp = prm->write_maps ? maps : nullptr;
     auto enqueue = [&]() -> gv_status {
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, true, sh_degree, gamma,
-                           (int)gamma_dtype, (float)n_train, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &q, s, bz));
         float *tpart = at<float>(workspace, Lay.tpart);
         {
             StageScope sc(ctx, ST_RASTER_UQ, s);
@@ -767,20 +800,22 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     // the key below (the cameras themselves live in the view table, uploaded
     // above on the same stream before the replay).
     struct Key {
-        const void *ws, *gamma, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
-        int64_t n, n_virtual, n_train, rcap, mcap, tiles, nbytes;
-        int32_t n_cand, sh, gdt, dtype, anchor_block, count, uq_batch;
-        float f[8];
+        const void *ws, *gamma, *vtrain, *tc, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
+        int64_t n, n_virtual, rcap, mcap, tiles, nbytes;
+        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv;
+        float f[10];
     } key;
     std::memset(&key, 0, sizeof(key));
-    key.ws = workspace; key.gamma = gamma; key.scores = scores; key.maps = mp;
+    key.ws = workspace; key.gamma = q.gamma; key.vtrain = q.view_vis; key.tc = q.train_centres;
+    key.scores = scores; key.maps = mp;
     key.means = g->means; key.scales = g->scales; key.quats = g->quats; key.opac = g->opacity; key.anchors = g->anchors;
-    key.n = g->n; key.n_virtual = g->n_virtual; key.n_train = n_train; key.rcap = plan->max_records;
+    key.n = g->n; key.n_virtual = g->n_virtual; key.rcap = plan->max_records;
     key.mcap = plan->max_instances; key.tiles = tiles; key.nbytes = (int64_t)plan->bytes;
-    key.n_cand = n_cand; key.sh = sh_degree; key.gdt = (int)gamma_dtype; key.dtype = (int)g->dtype;
+    key.mode = q.mode; key.n_cand = n_cand; key.sh = q.sh_degree; key.gdt = q.gamma_dtype; key.dtype = (int)g->dtype;
     key.anchor_block = g->anchor_block; key.count = prm->count_pairs; key.uq_batch = ctx->tuning.uq_batch;
-    const float fv[8] = {prm->beta, prm->o0, prm->half_logdet_Q0, prm->half_logdet_Qc, prm->eps_T, prm->znear,
-                         prm->lowpass, prm->cut};
+    key.ntv = q.n_train_views;
+    const float fv[10] = {prm->beta, prm->o0, prm->half_logdet_Q0, prm->half_logdet_Qc, prm->eps_T, prm->znear,
+                          prm->lowpass, prm->cut, q.n_train, q.kappa};
     std::memcpy(key.f, fv, sizeof(fv));
     const unsigned char *kb = reinterpret_cast<const unsigned char *>(&key);
     std::vector<unsigned char> kv(kb, kb + sizeof(key));
@@ -819,6 +854,39 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     ctx->graphs.push_back(gr);
     GV_HIP(hipGraphLaunch(gr.exec, s));
     return GV_OK;
+}
+
+extern "C" {
+
+gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                         const gv_uq_params *prm, float *scores, float *maps, const gv_workspace *plan,
+                         void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", sh_degree, GV_MAX_SH_DEGREE);
+    if (n_train < 0) return fail(GV_ERR_INVALID_ARG, "n_train < 0");
+    if (n_train > 0 && g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
+    if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
+        return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
+    if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
+    QueryArgs q = {1, sh_degree, gamma, (int)gamma_dtype, (float)n_train, nullptr, nullptr, 0, 0.f};
+    return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, plan, workspace, hip_stream);
+}
+
+gv_status vf_query_views_exact(gv_context *ctx, const gv_gaussians *g, const float *view_vis,
+                               const float *train_centres, int32_t n_train, float kappa, const gv_camera *cand,
+                               int32_t n_cand, const gv_uq_params *prm, float *scores, float *maps,
+                               const gv_workspace *plan, void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (n_train < 0) return fail(GV_ERR_INVALID_ARG, "n_train < 0");
+    if (n_train > 0 && g->n > 0 && (!view_vis || !train_centres))
+        return fail(GV_ERR_INVALID_ARG, "view_vis or train_centres is NULL");
+    if (!(std::isfinite(kappa) && kappa >= 0.f)) return fail(GV_ERR_INVALID_ARG, "kappa must be >= 0");
+    QueryArgs q = {2, 0, nullptr, 0, (float)n_train, view_vis, train_centres, n_train, kappa};
+    return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, plan, workspace, hip_stream);
 }
 
 gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const void *workspace, int64_t out[4],

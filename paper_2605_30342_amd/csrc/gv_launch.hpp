@@ -31,6 +31,20 @@ struct UqArgs {
     float qcut;      // log2(e) cut / 2, the overlap threshold on the scaled quadratic form
 };
 
+// Where the query takes a Gaussian's visibility in a candidate view from.
+struct QueryArgs {
+    int mode;                     // 1: SH field with the AM-GM bound (Alg. 4)
+                                  // 2: exact product over the training views (eq. vis_all)
+    int sh_degree;                // mode 1
+    const void *gamma;            // mode 1: planar [K][n]
+    int gamma_dtype;              // mode 1
+    float n_train;                // |P|
+    const float *view_vis;        // mode 2: v_p of every Gaussian, [n_train][n]
+    const float *train_centres;   // mode 2: [n_train][3]
+    int32_t n_train_views;        // mode 2
+    float kappa;                  // mode 2
+};
+
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s);
 
@@ -41,8 +55,8 @@ void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomAr
 void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
-                    const uint32_t *vmask, const Status *st, uint32_t rcap, bool query, int L, const void *gamma, int gamma_dtype,
-                    float n_train, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s);
+                    const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
+                    uint32_t *key, Bin *bin, hipStream_t s);
 
 size_t scan_blk_count(uint64_t n_cap);
 void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
@@ -54,6 +68,8 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s);
 void launch_vis_finish(int64_t n, float *out, hipStream_t s);
+void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *vmask, int mw, const float *acc_T,
+                     const uint32_t *acc_c, const Status *st, float *out, unsigned long long *pairs, hipStream_t s);
 void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
 void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
                  uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);

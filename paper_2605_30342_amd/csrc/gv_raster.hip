@@ -634,6 +634,51 @@ __global__ __launch_bounds__(WG) void k_vis_finish(int64_t n, float *__restrict_
     if (g < n) out[g] = 1.0f - expf(out[g]);
 }
 
+// Per-view single-view visibility (Alg. 2): out[view * n + g] = v_p[g] =
+// sum T / count over the pixels the view composites for g, for every record
+// of g in this pass (the caller clears the pass's rows first, so a view that
+// culls g or reaches none of its pixels leaves 0).  Walks g's records in the
+// order of the projection: per view subset, the views of the cull's mask,
+// ascending.
+__global__ __launch_bounds__(WG) void k_view_vis(int64_t n, const uint32_t *__restrict__ offs,
+                                                 const uint32_t *__restrict__ vmask, int mw,
+                                                 const float *__restrict__ acc_T, const uint32_t *__restrict__ acc_c,
+                                                 const Status *__restrict__ st, float *__restrict__ out,
+                                                 unsigned long long *__restrict__ pairs) {
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (st->overflow) return;
+    uint32_t npairs = 0;
+    if (g < n) {
+        const uint32_t rlim = st->R_eff;
+        for (int sub = 0; sub < PROJ_SPLIT; ++sub) {
+            const int64_t e = g * PROJ_SPLIT + sub;
+            uint32_t r = offs[e];
+            const uint32_t rend = min(offs[e + 1], rlim);
+            for (int wi = 0; wi < mw && r < rend; ++wi) {
+                uint32_t x = vmask[e * mw + wi];
+                while (x != 0u && r < rend) {
+                    const int vw = sub + PROJ_SPLIT * (32 * wi + __builtin_ctz(x));
+                    x &= x - 1u;
+                    const uint32_t c = acc_c[r];
+                    if (c != 0) {
+                        npairs += c;
+                        out[(int64_t)vw * n + g] = acc_T[r] / (float)c;
+                    }
+                    ++r;
+                }
+            }
+        }
+    }
+    block_count(npairs, pairs);
+}
+
+void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *vmask, int mw, const float *acc_T,
+                     const uint32_t *acc_c, const Status *st, float *out, unsigned long long *pairs, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_view_vis, dim3((unsigned)((a.n + WG - 1) / WG)), dim3(WG), 0, s, a.n, offs, vmask, mw,
+                       acc_T, acc_c, st, out, pairs);
+}
+
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s) {
     if (n <= 0) return;
