@@ -65,6 +65,11 @@ def lib():
         L.ora_vf_query_exact.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, i64, d, i32, vp, vp, vp, vp,
                                          d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
         L.ora_vf_query_exact.restype = ctypes.c_int
+        L.ora_half_logdet_color.argtypes = [i32, vp, i64, vp]
+        L.ora_half_logdet_color.restype = d
+        L.ora_vf_query_color.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, vp, i32, i32, vp, vp, vp, vp,
+                                         d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
+        L.ora_vf_query_color.restype = ctypes.c_int
         L.ora_multiview_visibility.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, d, d, d, d, i32, vp, vp]
         L.ora_multiview_visibility.restype = ctypes.c_int
         L.ora_argmax.argtypes = [vp, i32]
@@ -256,6 +261,51 @@ def vf_query_exact(scene, vtrain, train_cams, kappa: float, cams, prm: Params = 
                                   _p(stats))
     if rc:
         raise RuntimeError("oracle vf_query_exact failed")
+    out_maps, out_flags, off = [], [], 0
+    for (w, h) in wh:
+        n = int(w) * int(h)
+        if maps is not None:
+            out_maps.append(maps[off:off + n].reshape(h, w))
+        out_flags.append(pflags[off:off + n].reshape(h, w).astype(bool))
+        off += n
+    return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
+            "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+
+
+def half_logdet_color(Lc: int, var_g, d) -> float:
+    """1/2 log|Q_c(d)| of one Gaussian from the variances of its colour SH
+    coefficients var_g [3][Kc] (Appendix, integration with FisherRF):
+    Q_k(d) = sum_j Y_j(d)^2 var_g[k][j]."""
+    v = _f64(var_g).reshape(3, -1)
+    if v.shape[1] != (Lc + 1) ** 2:
+        raise ValueError("var_g must be [3][(Lc+1)^2]")
+    flat = np.ascontiguousarray(v.reshape(-1))
+    return float(lib().ora_half_logdet_color(int(Lc), _p(flat), 1, _p(_f64(d))))
+
+
+def vf_query_color(scene, gamma, L: int, n_train: int, color_var, Lc: int, cams, prm: Params = Params(),
+                   gather_mode: int = 0, want_maps: bool = True, want_vq: bool = False):
+    """vf_query with the constant colour covariance replaced per Gaussian and
+    view by Q_c(d) from the colour SH-coefficient variances color_var
+    [3][Kc][n] (Kc = (Lc+1)^2).  prm.sigma_c is not used."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    g = _f64(gamma)
+    cv = _f64(color_var)
+    if cv.shape != (3, (Lc + 1) ** 2, scene.n):
+        raise ValueError("color_var must be [3][(Lc+1)^2][n]")
+    npx = int(np.sum(wh[:, 0].astype(np.int64) * wh[:, 1]))
+    maps = np.zeros(npx) if want_maps else None
+    pflags = np.zeros(npx, dtype=np.uint8)
+    scores = np.zeros(cams.n)
+    stats = np.zeros(4, dtype=np.int64)
+    vq = np.zeros((cams.n, scene.n)) if want_vq else None
+    rc = lib().ora_vf_query_color(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), L, n_train,
+                                  _p(cv), int(Lc), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
+                                  prm.half_logdet_Q0, prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode,
+                                  _p(maps), _p(scores), _p(vq), _p(pflags), _p(stats))
+    if rc:
+        raise RuntimeError("oracle vf_query_color failed")
     out_maps, out_flags, off = [], [], 0
     for (w, h) in wh:
         n = int(w) * int(h)

@@ -13,6 +13,8 @@
  *   - visibility-field query with the AM-GM bound          (Alg. 1 / Alg. 4, eq. vis_bound)
  *   - exact multi-view visibility, the quantity the field  (eq. vis_all with eq. vis_p)
  *     and the bound approximate (validation mode)
+ *   - per-Gaussian colour covariance from SH-coefficient   (Appendix, integration with FisherRF)
+ *     variances, in place of the constant Q_c
  *   - uncertainty-quantification rasterisation             (Alg. 6, eq. alpha_comp, eq. huber)
  *   - view score and next-best-view argmax                 (eq. i_gain, eq. id with f_corr = 0)
  *
@@ -695,6 +697,28 @@ double ora_exact_visibility(int64_t n_train, const double *vtrain, int64_t strid
     return 1.0 - prod;
 }
 
+/* Emitted-colour covariance of one Gaussian seen in direction d, from the
+ * diagonal variances of its colour SH coefficients (Appendix, integration
+ * with FisherRF): the colour is linear in the coefficients, so channel k has
+ * variance Q_k(d) = sum over l <= Lc, m of Y_lm(d)^2 S_lmk, and with
+ * independent channels |Q_c(d)| = prod_k Q_k.  S_lmk is read as
+ * var[(k Kc + l^2 + l + m) stride], Kc = (Lc + 1)^2, k = 0..2.  Returns
+ * 1/2 log|Q_c(d)|, each Q_k floored at 1e-30 (a zero variance would give
+ * -infinity); 0 for a Gaussian without direction (at the camera centre). */
+double ora_half_logdet_color(int32_t Lc, const double *var, int64_t stride, const double *d)
+{
+    double Y[(ORA_LMAX + 1) * (ORA_LMAX + 1)];
+    if (Lc < 0 || Lc > ORA_LMAX || ora_sh_real(Lc, d, Y)) return 0.0;
+    int Kc = (Lc + 1) * (Lc + 1);
+    double h = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double Q = 0.0;
+        for (int j = 0; j < Kc; ++j) Q += Y[j] * Y[j] * var[(int64_t)(k * Kc + j) * stride];
+        h += 0.5 * log(Q > 1e-30 ? Q : 1e-30);
+    }
+    return h;
+}
+
 /* -x log x, with its limit 0 at x = 0 */
 static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
 
@@ -708,6 +732,10 @@ static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
  * with c_c = half_logdet_Qc + 1.5 log(2 pi e), c_0 = half_logdet_Q0 + 1.5 log(2 pi e)
  * (D = 3 colour channels).  The last n_virtual Gaussians have V = 0.
  *
+ * With color_var (optional, [3][Kc][n], Kc = (Lc + 1)^2) the constant c_c is
+ * replaced per Gaussian and view by 1/2 log|Q_c(d)| + 1.5 log(2 pi e), Q_c(d)
+ * from the SH-coefficient variances (ora_half_logdet_color).
+ *
  * gamma is [n][K].  maps (optional) is packed view after view, row major;
  * pflags (optional) likewise, 1 where a near-tie decision touches the pixel.
  * vq (optional) [n_views][n] receives the queried visibility.
@@ -715,7 +743,7 @@ static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
 static int vf_query_core(int64_t n, const double *means, const double *scales, const double *quats,
                          const double *opac, int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
                          const double *vtrain, const double *trainC, double kappa,
-                         int32_t n_views, const double *camR, const double *camT, const double *camK,
+                         const double *color_var, int32_t Lc, int32_t n_views, const double *camR, const double *camT, const double *camK,
                          const int32_t *camWH, double beta, double o0, double half_logdet_Q0,
                          double half_logdet_Qc, double eps_T, double znear, double lowpass, double cut,
                          int32_t gather_mode, double *maps, double *scores, double *vq, uint8_t *pflags,
@@ -725,9 +753,11 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
     int K = (L + 1) * (L + 1);
     const double c3 = 1.5 * log(2.0 * M_PI * M_E);
     const double cQc = half_logdet_Qc + c3, cQ0 = half_logdet_Q0 + c3;
+    if (color_var && (Lc < 0 || Lc > ORA_LMAX)) return -1;
     oproj *P = (oproj *)malloc(sizeof(oproj) * (size_t)(n > 0 ? n : 1));
     double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    if (!P || !v) { free(P); free(v); return -1; }
+    double *cc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!P || !v || !cc) { free(P); free(v); free(cc); return -1; }
     int64_t pairs = 0, entries = 0, nflag = 0, npix_total = 0, pix_off = 0;
     int rc = 0;
     for (int32_t p = 0; p < n_views; ++p) {
@@ -741,6 +771,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
             else if (vtrain) v[g] = ora_exact_visibility(n_train, &vtrain[g], n, trainC, kappa, &means[3 * g], c.C);
             else v[g] = ora_query_visibility(&gamma[(size_t)g * K], L, n_train, d);
             if (vq) vq[(size_t)p * n + g] = v[g];
+            cc[g] = color_var ? ora_half_logdet_color(Lc, &color_var[g], n, d) + c3 : cQc;
         }
         olists Ls = {0, 0};
         if (gather(P, n, &c, cut, gather_mode, 1, &Ls)) { free_lists(&Ls); rc = -1; break; }
@@ -764,7 +795,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                 double astar = (vg + beta * (1.0 - vg)) * alpha + o0 * (1.0 - beta) * (1.0 - vg);
                 double w = astar * T;
                 double x = w * vg;
-                H += xlogx_neg(x) + x * cQc;
+                H += xlogx_neg(x) + x * cc[g];
                 w0 += w * (1.0 - vg);
                 T *= (1.0 - astar);
                 vpairs++;
@@ -794,7 +825,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
         pix_off += npix;
     }
     if (stats) { stats[0] = pairs; stats[1] = entries; stats[2] = nflag; stats[3] = npix_total; }
-    free(P); free(v);
+    free(P); free(v); free(cc);
     return rc;
 }
 
@@ -805,8 +836,23 @@ int ora_vf_query(int64_t n, const double *means, const double *scales, const dou
                  double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
                  double *maps, double *scores, double *vq, uint8_t *pflags, int64_t *stats)
 {
-    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, n_views,
-                         camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
+                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
+                         lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
+}
+
+/* The same with the per-Gaussian colour covariance: color_var [3][Kc][n]
+ * holds the variances of the colour SH coefficients of degree <= Lc. */
+int ora_vf_query_color(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                       int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train, const double *color_var,
+                       int32_t Lc, int32_t n_views, const double *camR, const double *camT, const double *camK,
+                       const int32_t *camWH, double beta, double o0, double half_logdet_Q0, double eps_T,
+                       double znear, double lowpass, double cut, int32_t gather_mode, double *maps, double *scores,
+                       double *vq, uint8_t *pflags, int64_t *stats)
+{
+    if (!color_var && n > 0) return -1;
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, color_var, Lc,
+                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, 0.0, eps_T, znear,
                          lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
 }
 
@@ -823,7 +869,7 @@ int ora_vf_query_exact(int64_t n, const double *means, const double *scales, con
 {
     if (n_train < 0 || (n_train > 0 && (!vtrain || !trainC))) return -1;
     return vf_query_core(n, means, scales, quats, opac, n_virtual, NULL, 0, n_train, vtrain, trainC, kappa,
-                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T,
+                         NULL, 0, n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T,
                          znear, lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
 }
 

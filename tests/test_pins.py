@@ -586,3 +586,65 @@ def test_vf_query_exact_virtual_particles_and_no_views():
         w.train.R[:0], w.train.t[:0], w.train.K[:0], w.train.wh[:0]), 1.0, w.cand)
     ref = oracle.vf_query(sc, np.zeros((sc.n, 9)), 2, 0, w.cand)
     np.testing.assert_allclose(empty["scores"], ref["scores"], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- colour covariance from SH variances (FisherRF hook)
+
+def test_color_covariance_unsold_isotropy():
+    """Equal variances s for every coefficient of degree <= Lc: by Unsold's
+    theorem sum_m Y_lm(d)^2 = (2l+1)/(4 pi), so Q_k = s (Lc+1)^2 / (4 pi) in
+    every direction; s = 0.05, Lc = 3: 1/2 log|Q_c| = -4.1312517."""
+    for Lc in (0, 1, 2, 3):
+        var = np.full((3, (Lc + 1) ** 2), 0.05)
+        expect = 1.5 * math.log(0.05 * (Lc + 1) ** 2 / (4 * math.pi))
+        for d in _rand_dirs(5):
+            assert oracle.half_logdet_color(Lc, var, d) == pytest.approx(expect, rel=1e-13, abs=1e-13)
+    assert oracle.half_logdet_color(3, np.full((3, 16), 0.05), (0.0, 0.0, 1.0)) == pytest.approx(-4.1312517, abs=1e-7)
+
+
+def test_color_covariance_direction_dependence():
+    """Variances on Y_00 (4 pi 0.01 c_k) and Y_10 (4 pi 0.02 c_k) only, channel
+    factors c = (1, 2, 3): Y_00^2 = 1/(4 pi) and Y_10^2 = 3 z^2/(4 pi), so
+    Q_k = c_k (0.01 + 0.06 z^2): 1/2 log|Q_c| = -3.0930103 along +-z and
+    -6.0118755 in the xy-plane."""
+    var = np.zeros((3, 4))
+    for k, c in enumerate((1.0, 2.0, 3.0)):
+        var[k, 0] = 4 * math.pi * 0.01 * c
+        var[k, 2] = 4 * math.pi * 0.02 * c
+    for d in ((0, 0, 1), (0, 0, -2)):
+        assert oracle.half_logdet_color(1, var, d) == pytest.approx(-3.0930103, abs=1e-7)
+    for d in ((1, 0, 0), (0.3, -0.7, 0)):
+        assert oracle.half_logdet_color(1, var, d) == pytest.approx(-6.0118755, abs=1e-7)
+
+
+def test_color_query_with_constant_variance_equals_constant_qc():
+    """Only Y_00 carries variance, 4 pi sigma_c^2 in every channel: Q_c = sigma_c^2 I
+    in every direction, so the query equals the constant-Q_c query."""
+    from paper_2605_30342_amd import scenes
+    w = scenes.workload("tiny", scale=0.25)
+    b = oracle.vf_build(w.scene, w.train, 2)
+    sig = 0.3
+    var = np.zeros((3, 4, w.scene.n))
+    var[:, 0, :] = 4 * math.pi * sig * sig
+    ref = oracle.vf_query(w.scene, b["gamma"], 2, w.train.n, w.cand, Params(sigma_c=sig))
+    got = oracle.vf_query_color(w.scene, b["gamma"], 2, w.train.n, var, 1, w.cand)
+    np.testing.assert_allclose(got["maps_flat"], ref["maps_flat"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(got["scores"], ref["scores"], rtol=1e-12)
+
+
+def test_color_query_single_pixel_closed_form():
+    """1x1 image looking along +z at one Gaussian (V = 1 from gamma_00, T = 1):
+    H = -x log x + x c_c with x = alpha* = alpha, c_c = 1/2 log|Q_c(+z)| +
+    1.5 log(2 pi e), Q_c from the direction-dependent variances above."""
+    sc = stack_scene([2.0], [0.6], scale=0.01)
+    cam = axis_camera(1, 1, 50.0)
+    g = np.zeros((1, 9))
+    g[0, 0] = 1.0 / (0.5 / math.sqrt(math.pi))
+    var = np.zeros((3, 4, 1))
+    for k, c in enumerate((1.0, 2.0, 3.0)):
+        var[k, 0, 0] = 4 * math.pi * 0.01 * c
+        var[k, 2, 0] = 4 * math.pi * 0.02 * c
+    out = oracle.vf_query_color(sc, g, 2, 1, var, 1, cam)
+    x = float(np.float32(0.6))
+    closed = -x * math.log(x) + x * (-3.0930103207851394 + 1.5 * math.log(2 * math.pi * math.e))
+    assert out["maps"][0][0, 0] == pytest.approx(closed, rel=1e-12)
