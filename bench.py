@@ -129,6 +129,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=24, help="candidate views the CPU baseline runs")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-visibility validation mode")
+    ap.add_argument("--no-color", action="store_true", help="skip the per-Gaussian colour covariance query")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default blend batch sizes instead of tuning them on this workload")
     ap.add_argument("--profile-only", action="store_true",
@@ -367,6 +368,21 @@ def main():
         del vis_v, centres, s_ex
         log(f"exact validation {exact}")
 
+    # per-Gaussian colour covariance from colour SH-coefficient variances
+    # (degree 3, the 3DGS colour degree) in place of the constant Q_c
+    color = None
+    if not args.no_color:
+        cvar = torch.from_numpy(scenes.color_sh_variances(w.scene.n, 3, 5001)).cuda()
+        s_c = torch.empty_like(scores)
+        c_ms = timed(lambda: ctx.vf_query_views_color(dsc, gamma, L, w.train.n, cvar, w.cand, uprm, ws_q,
+                                                      scores=s_c))
+        torch.cuda.synchronize()
+        color = {"query_ms": round(c_ms, 4), "mpix_s": round(px / (c_ms / 1e3) / 1e6, 3),
+                 "constant_covariance_query_ms": round(batched_ms, 4),
+                 "best_view": int(torch.argmax(s_c).item()), "color_sh_degree": 3}
+        del cvar, s_c
+        log(f"colour covariance {color}")
+
     serving = None
     if not args.no_serving:
         serving = serving_bench(ctx, w, dsc, gamma, L, log)
@@ -416,6 +432,7 @@ def main():
         "precision": precision,
         "serving": serving,
         "exact_validation": exact,
+        "color_covariance": color,
         "cpu_baseline": cpu,
     }
     ctx.close()

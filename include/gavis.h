@@ -206,6 +206,23 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
                          const gv_uq_params *params, float *scores, float *maps,
                          const gv_workspace *plan, void *workspace, void *hip_stream);
 
+/* vf_query_views with a per-Gaussian colour covariance in place of the
+ * constant Q_c (Appendix, integration with FisherRF; the hook through which
+ * a radiance-field uncertainty method refines the colour term of eq. huber).
+ * The colour is linear in its SH coefficients, so with independent
+ * coefficients channel k of Gaussian g seen in direction d has variance
+ * Q_k(d) = sum_j Y_j(d)^2 var_gjk, and the record's colour constant becomes
+ * 1/2 sum_k log max(Q_k(d), 1e-30) + 3/2 log(2 pi e).
+ * color_var: device float, planar [3][Kc][n]: the variance of colour SH
+ * coefficient j (index l^2 + l + m, real basis as for gamma) in channel k of
+ * Gaussian g at color_var[(k * Kc + j) * n + g], Kc = (color_sh_degree+1)^2,
+ * color_sh_degree 0..3.  params->half_logdet_Qc is not used.  Other
+ * arguments, outputs and errors as vf_query_views. */
+gv_status vf_query_views_color(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                               int32_t sh_degree, int64_t n_train, const float *color_var, int32_t color_sh_degree,
+                               const gv_camera *cand, int32_t n_cand, const gv_uq_params *params, float *scores,
+                               float *maps, const gv_workspace *plan, void *workspace, void *hip_stream);
+
 /* Validation mode of vf_query_views: the same Alg. 6 rasterisation and
  * scores, with each Gaussian's visibility in direction d = camera -> Gaussian
  * taken exactly from the per-view visibilities instead of from the field and

@@ -24,6 +24,7 @@ EXPORTS = (
     "gv_workspace_check", "gv_workspace_bytes", "select_next_view",
     "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name", "vf_multiview_visibility",
     "gv_set_tuning", "gv_get_tuning", "vf_view_visibility", "vf_query_views_exact",
+    "vf_query_views_color",
 )
 GV_PROFILE_STAGES = 9
 
@@ -108,6 +109,9 @@ def load(path: str = LIB_PATH):
     L.vf_query_views_exact.argtypes = [vp, P(gv_gaussians), vp, vp, i32, ctypes.c_float, P(gv_camera), i32,
                                        P(gv_uq_params), vp, vp, P(gv_workspace), vp, vp]
     L.vf_query_views_exact.restype = st
+    L.vf_query_views_color.argtypes = [vp, P(gv_gaussians), vp, ctypes.c_int, i32, i64, vp, i32, P(gv_camera), i32,
+                                       P(gv_uq_params), vp, vp, P(gv_workspace), vp, vp]
+    L.vf_query_views_color.restype = st
     L.vf_query_workspace_size.argtypes = [vp, P(gv_gaussians), P(gv_camera), i32, P(gv_uq_params), i32,
                                           P(gv_workspace), vp]
     L.vf_query_workspace_size.restype = st

@@ -191,6 +191,39 @@ class Context:
                                              _ptr(out), ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
         return out
 
+    def vf_query_views_color(self, dsc: DeviceScene, gamma: torch.Tensor, sh_degree: int, n_train: int,
+                             color_var: torch.Tensor, cams, params: Optional[_lib.gv_uq_params] = None,
+                             ws: Optional[Workspace] = None, want_maps: bool = False,
+                             scores: Optional[torch.Tensor] = None, maps: Optional[torch.Tensor] = None,
+                             stream=None):
+        """vf_query_views with the colour covariance of every Gaussian taken
+        from the variances of its colour SH coefficients, color_var float32
+        [3][Kc][n] (FisherRF integration); same outputs."""
+        if params is None:
+            params = _lib.default_uq_params()
+        params.write_maps = 1 if want_maps else 0
+        if color_var.dtype != torch.float32 or color_var.dim() != 3 or color_var.shape[0] != 3 \
+                or color_var.shape[2] != dsc.n:
+            raise ValueError("color_var must be float32 [3][Kc][n]")
+        Lc = int(round(color_var.shape[1] ** 0.5)) - 1
+        if (Lc + 1) ** 2 != color_var.shape[1]:
+            raise ValueError("color_var's second dimension must be (Lc+1)^2")
+        color_var = color_var.contiguous()
+        if ws is None:
+            ws = self.query_workspace(dsc, cams, params, sh_degree, stream)
+        dev = f"cuda:{self.device}"
+        if scores is None:
+            scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
+        if want_maps and maps is None:
+            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+        gdt = {torch.float32: GV_F32, torch.float16: GV_F16, torch.bfloat16: GV_BF16}[gamma.dtype]
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_query_views_color(self.h, ctypes.byref(dsc.c), _ptr(gamma), gdt, sh_degree, int(n_train),
+                                          _ptr(color_var), Lc, cc, cams.n, ctypes.byref(params), _ptr(scores),
+                                          _ptr(maps) if want_maps else None, ctypes.byref(ws.plan), _ptr(ws.buf),
+                                          _stream(stream)))
+        return scores, maps
+
     def view_visibility(self, dsc: DeviceScene, cams, params: Optional[_lib.gv_vf_params] = None,
                         ws: Optional[Workspace] = None, stream=None):
         """Per-view single-view visibility v_p[g] (Alg. 2), float [n_views][n],

@@ -279,6 +279,11 @@ __device__ __forceinline__ int kth_set_bit(uint32_t x, uint32_t k) {
 //   unit direction from training camera p, summed as logs and finished with
 //   expm1 so that small V keep their relative precision.  A training camera
 //   at the Gaussian's centre contributes nothing.
+// With cvar (query modes), also the colour term's constant of the record,
+// rcc[r] = 1/2 log|Q_c(d)| + 3/2 log(2 pi e), where channel k of the colour
+// covariance is Q_k(d) = sum_j Y_j(d)^2 cvar[(k Kc + j) n + g] (the colour is
+// linear in its SH coefficients, whose variances cvar holds), floored at
+// 1e-30; 3/2 log(2 pi e) alone for a Gaussian at the camera centre.
 template <typename TG, typename TGam, int MODE, int L>
 __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                                 float znear, float lowpass, float cut,
@@ -286,7 +291,8 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 int mw, const Status *__restrict__ st, uint32_t rcap,
                                                 const TGam *__restrict__ gamma, float n_train,
                                                 const float *__restrict__ vtrain, const float *__restrict__ tc,
-                                                int ntv, float kappa_log2e,
+                                                int ntv, float kappa_log2e, const float *__restrict__ cvar, int Lc,
+                                                float c3, float *__restrict__ rcc,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                 Bin *__restrict__ bin) {
     constexpr int K = (L + 1) * (L + 1);
@@ -413,6 +419,30 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                         }
                     }
                     R.v = vis;
+                    if constexpr (MODE != 0) {
+                        if (cvar) {
+                            float cc = c3;
+                            float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
+                            const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+                            if (nrm > 0.0f) {
+                                const float inv = 1.0f / nrm;
+                                float Y[16];
+                                sh_eval<3>(dx * inv, dy * inv, dz * inv, Y);
+                                const int Kc = (Lc + 1) * (Lc + 1);
+                                float h = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < 3; ++k) {
+                                    float Q = 0.0f;
+#pragma unroll
+                                    for (int j = 0; j < 16; ++j)
+                                        if (j < Kc) Q = fmaf(Y[j] * Y[j], cvar[(int64_t)(k * Kc + j) * G.n + g], Q);
+                                    h += logf(fmaxf(Q, 1e-30f));
+                                }
+                                cc = fmaf(0.5f, h, c3);
+                            }
+                            rcc[r] = cc;
+                        }
+                    }
                     rec[r] = R;
                     key[r] = __float_as_uint((float)Pj.z);
                     b.tile0 = (uint32_t)(V.tile_base + Pj.y0 * V.tiles_x + Pj.x0);
@@ -940,7 +970,7 @@ static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, 
     const TGam *gm = (const TGam *)q.gamma;
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
-        q.view_vis, q.train_centres, q.n_train_views, kl, rec, key, bin
+        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, rec, key, bin
     if constexpr (MODE != 1) {   // no SH evaluation
         hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
     } else {
@@ -959,7 +989,7 @@ static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views
                                  const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
                                  const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
     if (!q) {
-        const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f};
+        const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr};
         project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, s);
         return;
     }

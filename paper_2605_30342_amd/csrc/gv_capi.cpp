@@ -104,7 +104,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
-    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, total;
+    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, total;
 };
 
 Layout make_layout(const gv_workspace &p) {
@@ -145,6 +145,7 @@ Layout make_layout(const gv_workspace &p) {
         L.gam32 = take(N * (uint64_t)K * 4);
     } else {
         L.tpart = take(T * 4);
+        L.rcc = take(R * 4);
     }
     L.total = o;
     return L;
@@ -777,15 +778,18 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     u.eps_T = prm->eps_T;
     u.qcut = (float)(0.5 * prm->cut / std::log(2.0));
     float *mp = prm->write_maps ? maps : nullptr;
+    QueryArgs qa = q;
+    qa.c3 = (float)c3;
+    qa.rcc = q.color_var ? at<float>(workspace, Lay.rcc) : nullptr;
     auto enqueue = [&]() -> gv_status {
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &q, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &qa, s, bz));
         float *tpart = at<float>(workspace, Lay.tpart);
         {
             StageScope sc(ctx, ST_RASTER_UQ, s);
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), u, tpart, mp,
+                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), qa.rcc, u, tpart, mp,
                              prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
@@ -800,13 +804,14 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     // the key below (the cameras themselves live in the view table, uploaded
     // above on the same stream before the replay).
     struct Key {
-        const void *ws, *gamma, *vtrain, *tc, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
+        const void *ws, *gamma, *vtrain, *tc, *cvar, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
         int64_t n, n_virtual, rcap, mcap, tiles, nbytes;
-        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv;
+        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv, csh;
         float f[10];
     } key;
     std::memset(&key, 0, sizeof(key));
     key.ws = workspace; key.gamma = q.gamma; key.vtrain = q.view_vis; key.tc = q.train_centres;
+    key.cvar = q.color_var; key.csh = q.color_sh_degree;
     key.scores = scores; key.maps = mp;
     key.means = g->means; key.scales = g->scales; key.quats = g->quats; key.opac = g->opacity; key.anchors = g->anchors;
     key.n = g->n; key.n_virtual = g->n_virtual; key.rcap = plan->max_records;
@@ -872,6 +877,28 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
         return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
     if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
     QueryArgs q = {1, sh_degree, gamma, (int)gamma_dtype, (float)n_train, nullptr, nullptr, 0, 0.f};
+    return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, plan, workspace, hip_stream);
+}
+
+gv_status vf_query_views_color(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                               int32_t sh_degree, int64_t n_train, const float *color_var, int32_t color_sh_degree,
+                               const gv_camera *cand, int32_t n_cand, const gv_uq_params *prm, float *scores,
+                               float *maps, const gv_workspace *plan, void *workspace, void *hip_stream) {
+    if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    GV_TRY(check_gauss(g));
+    if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "sh_degree %d not in 0..%d", sh_degree, GV_MAX_SH_DEGREE);
+    if (color_sh_degree < 0 || color_sh_degree > GV_MAX_SH_DEGREE)
+        return fail(GV_ERR_UNSUPPORTED, "color_sh_degree %d not in 0..%d", color_sh_degree, GV_MAX_SH_DEGREE);
+    if (n_train < 0) return fail(GV_ERR_INVALID_ARG, "n_train < 0");
+    if (g->n > 0 && !color_var) return fail(GV_ERR_INVALID_ARG, "color_var is NULL");
+    if (n_train > 0 && g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
+    if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
+        return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
+    if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
+    QueryArgs q = {1, sh_degree, gamma, (int)gamma_dtype, (float)n_train, nullptr, nullptr, 0, 0.f};
+    q.color_var = color_var;
+    q.color_sh_degree = color_sh_degree;
     return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, plan, workspace, hip_stream);
 }
 

@@ -43,6 +43,13 @@ struct QueryArgs {
     const float *train_centres;   // mode 2: [n_train][3]
     int32_t n_train_views;        // mode 2
     float kappa;                  // mode 2
+    // optional per-Gaussian colour covariance (both modes): variances of the
+    // colour SH coefficients, planar [3][Kc][n], Kc = (color_sh_degree + 1)^2;
+    // the projection writes c_c per record into rcc
+    const float *color_var;
+    int color_sh_degree;
+    float c3;                     // 3/2 log(2 pi e)
+    float *rcc;
 };
 
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
@@ -78,9 +85,10 @@ void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, ui
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
                        int batch, hipStream_t s);
+// rcc: per-record colour constants c_c (NULL: the uniform u.cQc)
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps,
-                      unsigned long long *pairs, int batch, hipStream_t s);
+                      const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
+                      float *maps, unsigned long long *pairs, int batch, hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);

@@ -332,16 +332,21 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
 
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
 
-template <int RB, bool MAPS, bool COUNT>
+// CC: the colour term's constant c_c = 1/2 log|Q_c| + 3/2 log(2 pi e) comes
+// per record from rcc[] (a per-Gaussian colour covariance seen from this
+// view) instead of the uniform u.cQc; costs one more LDS value per entry and
+// one multiply-add per evaluated pair.
+template <int RB, bool MAPS, bool COUNT, bool CC>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
-                                                  const Rec *__restrict__ rec,
+                                                  const Rec *__restrict__ rec, const float *__restrict__ rcc,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   unsigned long long *__restrict__ pairs) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21
     __shared__ float4 wB[WAVES][LCAP];     // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
+    __shared__ float wC[CC ? WAVES : 1][CC ? LCAP : 1];   // c_c of the record
     __shared__ int scnt[WAVES * WAVES];
     __shared__ int slen[WAVES];
     __shared__ float red[WAVES];
@@ -359,6 +364,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     // per pixel: sx = sum w* v, sxl = sum w* v log2(w* v), sw = sum w*; the
     // entropy bound is formed from them after the last Gaussian
     float T = inside ? 1.0f : 0.0f, sx = 0.0f, sxl = 0.0f, sw = 0.0f;
+    float sxc = 0.0f;   // sum w* v c_c, with per-record constants
     uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
@@ -367,6 +373,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const bool loader = t < RB;
     uint32_t r1 = 0, r2 = 0, k1 = 0, k2 = 0;   // record indices and instance keys
     Rec R1 = {};
+    float C1 = 0.0f;
     if (loader && rg.x + t < rg.y) {
         r1 = ival[rg.x + t];
         k1 = ikey[rg.x + t];
@@ -375,16 +382,23 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         r2 = ival[rg.x + RB + t];
         k2 = ikey[rg.x + RB + t];
     }
-    if (loader && rg.x + t < rg.y) R1 = rec[r1];
+    if (loader && rg.x + t < rg.y) {
+        R1 = rec[r1];
+        if (CC) C1 = rcc[r1];
+    }
 
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
         if (__syncthreads_count(T >= u.eps_T) == 0) break;
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
+        const float Cr = C1;
         const uint32_t kq = k1;
         r1 = r2;
         k1 = k2;
-        if (loader && b + RB + t < rg.y) R1 = rec[r1];
+        if (loader && b + RB + t < rg.y) {
+            R1 = rec[r1];
+            if (CC) C1 = rcc[r1];
+        }
         if (loader && b + 2 * RB + t < rg.y) {
             r2 = ival[b + 2 * RB + t];
             k2 = ikey[b + 2 * RB + t];
@@ -405,6 +419,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             if (pos[q] >= 0) {
                 wA[q][pos[q]] = a4;
                 wB[q][pos[q]] = b4;
+                if (CC) wC[q][pos[q]] = Cr;
             }
         }
         {
@@ -413,6 +428,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             if (k >= 0) {
                 wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
                 wB[q][k] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+                if (CC) wC[q][k] = 0.0f;
             }
         }
         __syncthreads();
@@ -423,6 +439,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             constexpr int G = decltype(gs)::value;
             const float4 A = wA[w][i0 + jl];
             const float4 B = wB[w][i0 + jl];
+            const float Cg = CC ? wC[w][i0 + jl] : 0.0f;
             static_for<0, G>([&](auto jc) {
                 // products and sums are rounded separately, so that every
                 // broadcast operand folds into its instruction
@@ -441,6 +458,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                     const float x = row_bcast<jj>(B.w) * wt;                                         // w* v
                     sxl = fmaf(x, fast_log2(fmaxf(x, 1e-30f)), sxl);
                     sx += x;
+                    if (CC) sxc = fmac_row_bcast<jj>(sxc, Cg, x);                                    // x c_c
                     sw += wt;
                     T -= wt;                                                                         // T (1 - alpha*)
                     if (COUNT) npairs += hit ? 1u : 0u;
@@ -455,7 +473,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         __syncthreads();
     }
     // H = sum_hits x (cQc - ln x) + w0 (cQ0 - ln w0), w0 = sum w* (1 - v) = sw - sx >= 0
-    float H = fmaf(u.cQc, sx, -LN2 * sxl);
+    float H = CC ? fmaf(-LN2, sxl, sxc) : fmaf(u.cQc, sx, -LN2 * sxl);
     const float w0 = sw - sx;
     if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
     if (!inside) H = 0.0f;
@@ -738,29 +756,39 @@ void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint
     }
 }
 
-template <int RB>
+template <int RB, bool CC>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                         const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
-                         hipStream_t s) {
+                         const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
+                         float *maps, unsigned long long *pairs, hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
+#define GV_UQ_ARGS views, nv, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs
     if (maps && pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, true>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC>), g, b, 0, s, GV_UQ_ARGS);
     else if (maps)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, false>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC>), g, b, 0, s, GV_UQ_ARGS);
     else if (pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, false, true>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, false, true, CC>), g, b, 0, s, GV_UQ_ARGS);
     else
-        hipLaunchKernelGGL((k_raster_uq<RB, false, false>), g, b, 0, s, views, nv, ranges, ival, ikey, rec, u, tile_part, maps, pairs);
+        hipLaunchKernelGGL((k_raster_uq<RB, false, false, CC>), g, b, 0, s, GV_UQ_ARGS);
+#undef GV_UQ_ARGS
+}
+
+template <int RB>
+static void raster_uq_cc(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                         const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
+                         float *maps, unsigned long long *pairs, hipStream_t s) {
+    if (rcc) raster_uq_rb<RB, true>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s);
+    else raster_uq_rb<RB, false>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s);
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const UqArgs &u, float *tile_part, float *maps, unsigned long long *pairs,
-                      int batch, hipStream_t s) {
+                      const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
+                      float *maps, unsigned long long *pairs, int batch, hipStream_t s) {
     if (total_tiles <= 0) return;
     switch (batch) {
-    case 64: raster_uq_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
-    case 256: raster_uq_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
-    default: raster_uq_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, u, tile_part, maps, pairs, s); break;
+    case 64: raster_uq_cc<64>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
+    case 256: raster_uq_cc<256>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
+    default: raster_uq_cc<128>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
     }
 }
 

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Scene", "Cameras", "Workload", "look_at", "make_cameras", "tiny_scene",
     "rooms_scene", "sphere_cameras", "ellipse_path_cameras", "room_candidates",
-    "workload", "subset_scene", "WORKLOADS",
+    "workload", "subset_scene", "WORKLOADS", "uniform_draws", "color_sh_variances",
 ]
 
 
@@ -263,6 +263,20 @@ def uniform_draws(n: int, seed: int) -> np.ndarray:
     """n seeded samples of U[0, 1)^3 (the random positions density control
     draws are passed in from here)."""
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=(n, 3))
+
+
+def color_sh_variances(n: int, Lc: int, seed: int) -> np.ndarray:
+    """Seeded stand-in for the diagonal variances of the colour SH
+    coefficients a Laplace approximation would give: float32 [3][Kc][n],
+    Kc = (Lc + 1)^2.  Per Gaussian a log-uniform scale in [1e-4, 1e-1] (well
+    and poorly observed particles), times 2^-l for degree l and a log-normal
+    factor (sigma 0.5) per coefficient and channel."""
+    rng = np.random.default_rng(seed)
+    Kc = (Lc + 1) ** 2
+    base = 10.0 ** rng.uniform(-4.0, -1.0, size=n)
+    deg = np.array([l for l in range(Lc + 1) for _ in range(2 * l + 1)], dtype=np.float64)
+    f = np.exp(rng.normal(0.0, 0.5, size=(3, Kc, n)))
+    return (base[None, None, :] * (2.0 ** -deg)[None, :, None] * f).astype(np.float32)
 
 
 def subset_scene(scene: Scene, idx) -> Scene:
