@@ -26,12 +26,15 @@
  * Readings where the paper is silent (kept identical on the GPU side, listed
  * in the design notes): alpha = o * exp(-m/2) with m the Mahalanobis distance
  * under the 2D covariance; "overlapping" means m <= cut (cut = 9, 3 sigma);
- * termination is T < eps_T tested after the update; depth is camera-space z;
- * directions are camera centre -> particle; the SH frame is the world frame.
+ * termination is T < eps_T tested after the update; depth is camera-space z,
+ * and the depth order is decided on z rounded to FP32 (the kernels' sort-key
+ * precision), ties by index; directions are camera centre -> particle; the SH
+ * frame is the world frame.
  *
  * Parity flags.  Where an FP32 evaluation can take a different discrete
  * decision than this FP64 one (a pair near the overlap boundary, a
- * transmittance near eps_T, two nearly equal depths), the oracle marks the
+ * transmittance near eps_T, a depth that another FP64 evaluation order could
+ * round to a neighbouring FP32 key), the oracle marks the
  * affected pixel (query) or Gaussian (build) so that the comparison can
  * leave it out and report how many were left out.
  */
@@ -248,12 +251,41 @@ static inline double mahal2(const oproj *o, double qx, double qy)
  * lies just outside the overlap boundary (kind 1, kept only so that the parity
  * flags know where a boundary flip would sit in depth order). */
 typedef struct {
-    double z;
+    double z;       /* depth, FP64 */
+    double zk;      /* depth key: z rounded to FP32 (the precision the order is decided in) */
     double m;
     int32_t g;
     int32_t kind;   /* 0 real, 1 ghost */
     int32_t near;   /* 1 if |m - cut| is inside the FP32 error band */
+    int32_t zamb;   /* 1 if z lies so close to an FP32 rounding midpoint that
+                       another FP64 evaluation order may round it the other way */
 } oentry;
+
+/* The depth order "sorted by increasing z" is a discrete decision taken on a
+ * floating-point value; it is taken here in the precision of the kernels'
+ * sort keys (FP32 z, ties by index), so both sides order every pixel's list
+ * identically.  The key is ambiguous only when z sits within 1e-12 |z| of a
+ * rounding midpoint (a differently ordered FP64 evaluation may land on the
+ * other side); such entries are flagged when a neighbour's key is equal or
+ * adjacent. */
+static void depth_key(double z, double *zk, int32_t *zamb)
+{
+    float f = (float)z;
+    double d = z - (double)f;
+    double mid = d >= 0.0 ? 0.5 * ((double)f + (double)nextafterf(f, INFINITY))
+                          : 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
+    *zk = (double)f;
+    *zamb = fabs(z - mid) <= 1e-12 * fabs(z);
+}
+
+/* 1 if the FP32 keys of a and b may order them differently in another
+ * evaluation: one key is ambiguous and they are equal or adjacent. */
+static int depth_tie(const oentry *a, const oentry *b)
+{
+    if (!a->zamb && !b->zamb) return 0;
+    float fa = (float)a->zk, fb = (float)b->zk;
+    return fa == fb || nextafterf(fa, INFINITY) == fb || nextafterf(fb, INFINITY) == fa;
+}
 
 typedef struct {
     int64_t *start;  /* [npix + 1] */
@@ -263,8 +295,8 @@ typedef struct {
 static int cmp_entry(const void *pa, const void *pb)
 {
     const oentry *a = (const oentry *)pa, *b = (const oentry *)pb;
-    if (a->z < b->z) return -1;
-    if (a->z > b->z) return 1;
+    if (a->zk < b->zk) return -1;
+    if (a->zk > b->zk) return 1;
     if (a->g < b->g) return -1;
     if (a->g > b->g) return 1;
     return 0;
@@ -355,7 +387,7 @@ static int gather(const oproj *P, int64_t n, const ocam *c, double cut, int mode
                         int64_t pix = (int64_t)j * c->w + i;
                         if (pass == 0) { cnt[pix]++; continue; }
                         oentry *e = &L->e[fill[pix]++];
-                        e->z = o->z; e->m = m; e->g = (int32_t)g; e->kind = real ? 0 : 1; e->near = near;
+                        e->z = o->z; depth_key(o->z, &e->zk, &e->zamb); e->m = m; e->g = (int32_t)g; e->kind = real ? 0 : 1; e->near = near;
                     }
             }
         } else {
@@ -371,7 +403,7 @@ static int gather(const oproj *P, int64_t n, const ocam *c, double cut, int mode
                     if (!real && !near) continue;
                     if (pass == 0) { cnt[pix]++; continue; }
                     oentry *e = &L->e[fill[pix]++];
-                    e->z = o->z; e->m = m; e->g = (int32_t)g; e->kind = real ? 0 : 1; e->near = near;
+                    e->z = o->z; depth_key(o->z, &e->zk, &e->zamb); e->m = m; e->g = (int32_t)g; e->kind = real ? 0 : 1; e->near = near;
                 }
             }
         }
@@ -394,9 +426,6 @@ static void free_lists(olists *L)
     L->e = NULL;
 }
 
-/* relative depth band inside which FP32 depth keys may order two entries
- * differently from FP64 */
-#define ORA_ZBAND 1e-6
 /* relative band on the termination test */
 #define ORA_TBAND 1e-4
 
@@ -503,7 +532,7 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
                     rel += alpha / (1.0 - alpha);
                 }
                 if (flag_next) { os[g] += T; on[g] += 1; flag_next = 0; }
-                if (last >= 0 && fabs(en->z - L.e[last].z) <= ORA_ZBAND * fabs(en->z)) {
+                if (last >= 0 && depth_tie(en, &L.e[last])) {
                     /* the two may swap: each one's T changes by T_last times the other's alpha */
                     dd[L.e[last].g] += T_last * alpha;
                     dd[g] += T_last * a_last;
@@ -525,7 +554,7 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
                 for (int64_t j = k + 1; j < e; ++j) {
                     if (L.e[j].kind != 0) continue;
                     if (flag_next) { os[L.e[j].g] += T; on[L.e[j].g] += 1; }
-                    if (last >= 0 && fabs(L.e[j].z - L.e[last].z) <= ORA_ZBAND * fabs(L.e[j].z)) {
+                    if (last >= 0 && depth_tie(&L.e[j], &L.e[last])) {
                         os[L.e[j].g] += T_last;
                         on[L.e[j].g] += 1;
                         dd[L.e[last].g] += T_last;
@@ -788,7 +817,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                 const oentry *en = &Ls.e[k];
                 if (en->kind == 1) { flag = 1; continue; }
                 if (en->near) flag = 1;
-                if (last >= 0 && fabs(en->z - Ls.e[last].z) <= ORA_ZBAND * fabs(en->z)) flag = 1;
+                if (last >= 0 && depth_tie(en, &Ls.e[last])) flag = 1;
                 int32_t g = en->g;
                 double vg = v[g];
                 double alpha = opac[g] * exp(-0.5 * en->m);
@@ -806,7 +835,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
             if (k < e) {
                 for (int64_t j = k + 1; j < e; ++j) {
                     if (Ls.e[j].kind != 0) continue;
-                    if (last >= 0 && fabs(Ls.e[j].z - Ls.e[last].z) <= ORA_ZBAND * fabs(Ls.e[j].z)) flag = 1;
+                    if (last >= 0 && depth_tie(&Ls.e[j], &Ls.e[last])) flag = 1;
                     break;
                 }
             }
