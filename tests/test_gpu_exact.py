@@ -122,21 +122,29 @@ def test_exact_query_graph_replay_equals_eager(ctx, tiny):
 
 
 def test_gpu_view_visibility_feeds_exact_query(ctx, tiny):
-    """End to end on the GPU: per-view visibility -> exact query, against the
-    oracle's exact query on the GPU's per-view visibilities; the SH query of
-    the GPU's own field stays within the AM-GM and truncation gap of it."""
-    say("case: GPU view visibility -> GPU exact query, tiny")
+    """End to end on the GPU (per-view visibility -> exact query) against the
+    oracle end to end (its own per-view visibilities -> exact query): the
+    per-view visibilities agree to 1e-4 plus near-tie allowances, so maps are
+    held to 1e-3 on unflagged pixels and scores to 1e-3 sum|H|.  The SH
+    query of the GPU's own field is reported beside it."""
+    say("case: GPU view visibility -> GPU exact query vs oracle end to end, tiny")
     import torch
     from tests._gpu import gpu_build, gpu_query
     prm = oracle_params()
     dsc = _dsc(tiny.scene)
     vis, centres = ctx.view_visibility(dsc, tiny.train)
     torch.cuda.synchronize()
-    vg = vis.cpu().numpy().astype(np.float64)
-    s, mp = _gpu_exact(ctx, dsc, vg, centres.cpu().numpy(), 1.0, tiny.cand)
-    q = oracle.vf_query_exact(tiny.scene, vg, tiny.train, prm.kappa, tiny.cand, prm)
-    worst, _ = compare_maps(mp, q)
+    s, mp = _gpu_exact(ctx, dsc, vis.cpu().numpy(), centres.cpu().numpy(), 1.0, tiny.cand)
+    b = oracle.vf_build(tiny.scene, tiny.train, 0, prm, want_views=True)
+    q = oracle.vf_query_exact(tiny.scene, b["vview"], tiny.train, prm.kappa, tiny.cand, prm)
+    worst, _ = compare_maps(mp, q, rel=1e-3)
+    say(f"  map worst ratio at 1e-3: {worst:.3f}")
     assert worst <= 1.0
+    off = 0
+    for v, m in enumerate(q["maps"]):
+        absH = np.abs(q["maps_flat"][off:off + m.size]).sum()
+        assert abs(s[v] - q["scores"][v]) <= 1e-3 * absH
+        off += m.size
     g = gpu_build(ctx, dsc, tiny.train, 2)
     s_sh, _, _ = gpu_query(ctx, dsc, g, 2, tiny.train.n, tiny.cand, maps=False)
     gap = np.abs(s_sh - s) / np.abs(s)
