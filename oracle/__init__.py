@@ -70,6 +70,9 @@ def lib():
         L.ora_vf_query_color.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, vp, i32, i32, vp, vp, vp, vp,
                                          d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
         L.ora_vf_query_color.restype = ctypes.c_int
+        L.ora_vf_query_depth.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
+                                         d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
+        L.ora_vf_query_depth.restype = ctypes.c_int
         L.ora_multiview_visibility.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, d, d, d, d, i32, vp, vp]
         L.ora_multiview_visibility.restype = ctypes.c_int
         L.ora_argmax.argtypes = [vp, i32]
@@ -193,10 +196,14 @@ def query_visibility(gamma_g, L: int, n_train: int, d) -> float:
 
 
 def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), gather_mode: int = 0,
-             want_maps: bool = True, want_vq: bool = False):
+             want_maps: bool = True, want_vq: bool = False, want_depth: bool = False):
     """Alg. 4 + Alg. 6 for every view in `cams`.  gamma is [n][K] (float64 or
     float32; promoted).  Returns dict: scores [V], maps (list of [h, w]),
-    flags (list of [h, w] bool), stats (pairs, entries, flagged px, px), vq."""
+    flags (list of [h, w] bool), stats (pairs, entries, flagged px, px), vq,
+    and with want_depth the expected-depth maps depth_flat (eq. id's d_p^mn:
+    sum w* z / sum w* under the compositing weights, 0 without any)."""
+    if want_depth:
+        return _vf_query_depth(scene, gamma, L, n_train, cams, prm, gather_mode)
     R, t, K, wh = _cams(cams)
     m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
     g = _f64(gamma)
@@ -221,6 +228,31 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
         off += n
     return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
             "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+
+
+def _vf_query_depth(scene, gamma, L, n_train, cams, prm, gather_mode):
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    g = _f64(gamma)
+    npx = int(np.sum(wh[:, 0].astype(np.int64) * wh[:, 1]))
+    maps, depth = np.zeros(npx), np.zeros(npx)
+    pflags = np.zeros(npx, dtype=np.uint8)
+    scores = np.zeros(cams.n)
+    stats = np.zeros(4, dtype=np.int64)
+    rc = lib().ora_vf_query_depth(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
+                                  int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
+                                  prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass,
+                                  prm.cut, gather_mode, _p(maps), _p(depth), _p(scores), _p(pflags), _p(stats))
+    if rc:
+        raise RuntimeError("oracle vf_query failed")
+    out_maps, out_flags, off = [], [], 0
+    for (w, h) in wh:
+        n = int(w) * int(h)
+        out_maps.append(maps[off:off + n].reshape(h, w))
+        out_flags.append(pflags[off:off + n].reshape(h, w).astype(bool))
+        off += n
+    return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": None,
+            "maps_flat": maps, "flags_flat": pflags.astype(bool), "depth_flat": depth}
 
 
 def camera_centres(cams) -> np.ndarray:

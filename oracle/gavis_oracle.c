@@ -15,6 +15,7 @@
  *     and the bound approximate (validation mode)
  *   - per-Gaussian colour covariance from SH-coefficient   (Appendix, integration with FisherRF)
  *     variances, in place of the constant Q_c
+ *   - expected depth per pixel under the same weights      (eq. id: the d_p^mn of f_corr)
  *   - uncertainty-quantification rasterisation             (Alg. 6, eq. alpha_comp, eq. huber)
  *   - view score and next-best-view argmax                 (eq. i_gain, eq. id with f_corr = 0)
  *
@@ -765,6 +766,11 @@ static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
  * replaced per Gaussian and view by 1/2 log|Q_c(d)| + 1.5 log(2 pi e), Q_c(d)
  * from the SH-coefficient variances (ora_half_logdet_color).
  *
+ * depth (optional, packed like maps) receives each pixel's expected depth
+ * under the same compositing weights, D = sum w* z / sum w* (0 where no
+ * Gaussian contributes): the d_p^mn that the spatial-correlation correction
+ * of eq. id takes.
+ *
  * gamma is [n][K].  maps (optional) is packed view after view, row major;
  * pflags (optional) likewise, 1 where a near-tie decision touches the pixel.
  * vq (optional) [n_views][n] receives the queried visibility.
@@ -775,8 +781,8 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                          const double *color_var, int32_t Lc, int32_t n_views, const double *camR, const double *camT, const double *camK,
                          const int32_t *camWH, double beta, double o0, double half_logdet_Q0,
                          double half_logdet_Qc, double eps_T, double znear, double lowpass, double cut,
-                         int32_t gather_mode, double *maps, double *scores, double *vq, uint8_t *pflags,
-                         int64_t *stats)
+                         int32_t gather_mode, double *maps, double *depth, double *scores, double *vq,
+                         uint8_t *pflags, int64_t *stats)
 {
     if (n < 0 || n_views < 0 || L < 0 || L > ORA_LMAX || n_virtual < 0 || n_virtual > n) return -1;
     int K = (L + 1) * (L + 1);
@@ -810,7 +816,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : score, vpairs, vflag)
         for (int64_t pix = 0; pix < npix; ++pix) {
             int64_t s = Ls.start[pix], e = Ls.start[pix + 1];
-            double T = 1.0, w0 = 0.0, H = 0.0;
+            double T = 1.0, w0 = 0.0, H = 0.0, sw = 0.0, swz = 0.0;
             int flag = 0;
             int64_t last = -1, k;
             for (k = s; k < e; ++k) {
@@ -825,6 +831,8 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                 double w = astar * T;
                 double x = w * vg;
                 H += xlogx_neg(x) + x * cc[g];
+                sw += w;
+                swz += w * en->z;
                 w0 += w * (1.0 - vg);
                 T *= (1.0 - astar);
                 vpairs++;
@@ -841,6 +849,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
             }
             H += xlogx_neg(w0) + w0 * cQ0;
             if (maps) maps[pix_off + pix] = H;
+            if (depth) depth[pix_off + pix] = sw > 0.0 ? swz / sw : 0.0;
             if (pflags) pflags[pix_off + pix] = (uint8_t)flag;
             score += H;
             vflag += flag;
@@ -867,7 +876,20 @@ int ora_vf_query(int64_t n, const double *means, const double *scales, const dou
 {
     return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
                          n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
-                         lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
+                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
+}
+
+/* ora_vf_query that also writes the expected-depth maps (packed like maps). */
+int ora_vf_query_depth(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                       int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
+                       int32_t n_views, const double *camR, const double *camT, const double *camK,
+                       const int32_t *camWH, double beta, double o0, double half_logdet_Q0, double half_logdet_Qc,
+                       double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
+                       double *maps, double *depth, double *scores, uint8_t *pflags, int64_t *stats)
+{
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
+                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
+                         lowpass, cut, gather_mode, maps, depth, scores, NULL, pflags, stats);
 }
 
 /* The same with the per-Gaussian colour covariance: color_var [3][Kc][n]
@@ -882,7 +904,7 @@ int ora_vf_query_color(int64_t n, const double *means, const double *scales, con
     if (!color_var && n > 0) return -1;
     return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, color_var, Lc,
                          n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, 0.0, eps_T, znear,
-                         lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
+                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
 }
 
 /* The same with the exact multi-view visibility in place of the SH query:
@@ -899,7 +921,7 @@ int ora_vf_query_exact(int64_t n, const double *means, const double *scales, con
     if (n_train < 0 || (n_train > 0 && (!vtrain || !trainC))) return -1;
     return vf_query_core(n, means, scales, quats, opac, n_virtual, NULL, 0, n_train, vtrain, trainC, kappa,
                          NULL, 0, n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T,
-                         znear, lowpass, cut, gather_mode, maps, scores, vq, pflags, stats);
+                         znear, lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
 }
 
 /* Next-best view (eq. i_gain): index of the largest score, lowest index on

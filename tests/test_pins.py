@@ -648,3 +648,46 @@ def test_color_query_single_pixel_closed_form():
     x = float(np.float32(0.6))
     closed = -x * math.log(x) + x * (-3.0930103207851394 + 1.5 * math.log(2 * math.pi * math.e))
     assert out["maps"][0][0, 0] == pytest.approx(closed, rel=1e-12)
+
+
+# ---------------------------------------------------------------- expected depth (eq. id's d_p^mn)
+
+def test_expected_depth_closed_forms():
+    """Two Gaussians on a 1x1 image's pixel centre at z = 2 (o = 0.6) and z = 3
+    (o = 0.5).  With V = 1 (gamma_00 only, |P| = 1): alpha* = alpha, weights
+    0.6 and 0.5 (1 - 0.6) = 0.2, D = (0.6*2 + 0.2*3) / 0.8 = 2.25.  With no
+    training view (V = 0): alpha* = alpha/2 + 0.075, weights 0.375 and
+    0.325 * 0.625 = 0.203125, D = 2.3513514.  One Gaussian alone: D = z."""
+    cam = axis_camera(1, 1, 50.0)
+    sc = stack_scene([2.0, 3.0], [0.6, 0.5], scale=0.01)
+    g = np.zeros((2, 9))
+    g[:, 0] = 1.0 / (0.5 / math.sqrt(math.pi))
+    out = oracle.vf_query(sc, g, 2, 1, cam, want_depth=True)
+    assert out["depth_flat"][0] == pytest.approx(2.25, abs=1e-7)
+    out = oracle.vf_query(sc, g, 2, 0, cam, want_depth=True)
+    assert out["depth_flat"][0] == pytest.approx(2.3513514, abs=1e-7)
+    one = stack_scene([4.5], [0.3], scale=0.01)
+    out = oracle.vf_query(one, g[:1], 2, 1, cam, want_depth=True)
+    assert out["depth_flat"][0] == pytest.approx(4.5, rel=1e-15)
+    # the entropy maps are those of the plain query
+    assert oracle.vf_query(sc, g, 2, 1, cam, want_depth=True)["maps_flat"][0] == \
+        oracle.vf_query(sc, g, 2, 1, cam)["maps_flat"][0]
+
+
+def test_expected_depth_empty_pixels_and_range():
+    """Pixels no Gaussian reaches get D = 0; elsewhere D lies between the
+    nearest and farthest depth in view (a convex combination)."""
+    from paper_2605_30342_amd import scenes
+    w = scenes.workload("tiny", scale=0.25)
+    b = oracle.vf_build(w.scene, w.train, 2)
+    out = oracle.vf_query(w.scene, b["gamma"], 2, w.train.n, w.cand, want_depth=True)
+    D = out["depth_flat"]
+    H = out["maps_flat"]
+    assert np.all(D[H == 0.0] == 0.0)
+    zmin, zmax = np.inf, 0.0
+    for i in range(w.cand.n):
+        pr = oracle.project_view(w.scene, w.cand, i)
+        ok = pr["ok"] > 0
+        zmin, zmax = min(zmin, pr["z"][ok].min()), max(zmax, pr["z"][ok].max())
+    live = D > 0
+    assert live.mean() > 0.3 and D[live].min() >= zmin * (1 - 1e-12) and D[live].max() <= zmax * (1 + 1e-12)
