@@ -71,37 +71,60 @@ def traffic_for(kernel: str):
     return e.get("bytes_per_launch")
 
 
-def serving_bench(ctx, w, dsc, gamma, L, log):
-    """Poisson stream of candidate-view requests over three resident scenes:
-    continuous batching (3 slots, same-scene merging) against a plain queue
-    (one slot, one request at a time)."""
+SERVING_SCENES = (   # name, Gaussians, rooms (x, y), storage
+    ("s100k", 100_000, 1, 1, "f32"), ("room200k", 200_000, 1, 1, "f32"), ("s400k", 400_000, 1, 1, "bf16"),
+    ("s700k", 700_000, 2, 1, "bf16"), ("s1m", 1_000_000, 2, 1, "f32"), ("s1500k", 1_500_000, 2, 1, "bf16"),
+    ("s2m", 2_000_000, 2, 2, "f32"), ("s3m", 3_000_000, 2, 2, "bf16"))
+
+
+def serving_bench(ctx, w, dsc, gamma, L, log, n_requests=96):
+    """Poisson stream of candidate-view requests over eight resident scenes
+    (100k-3M Gaussians, FP32 and BF16 storage, prebuilt fields), each request
+    16-512 views (log-uniform) of one class of 160x120 / 320x240 / 640x480:
+    continuous batching (3 slots, same-scene merging, memory admission)
+    against a plain queue (one slot, one request at a time)."""
     import numpy as np
     import torch
     from paper_2605_30342_amd import scenes
     from paper_2605_30342_amd.api import DeviceScene
     from paper_2605_30342_amd.serve import GpuBackend, Server, replay
-    resident = {"room200k": (dsc, gamma, w.train.n)}
-    for name, n, seed in (("room100k", 100_000, 2100), ("room50k", 50_000, 2200)):
-        sc = scenes.rooms_scene(n, 1, 1, seed=seed)
-        tr = scenes.ellipse_path_cameras(24, seed + 1, 400, 400)
-        d = DeviceScene(sc)
-        resident[name] = (d, ctx.vf_build(d, tr, L), tr.n)
+    resident, extents = {}, {}
+    t0 = time.time()
+    for i, (name, n, nx, ny, dt) in enumerate(SERVING_SCENES):
+        if name == "room200k":
+            resident[name] = (dsc, gamma, w.train.n)
+            extents[name] = w.scene.extent
+            continue
+        sc = scenes.rooms_scene(n, nx, ny, seed=2100 + 100 * i)
+        if dt != "f32":
+            sc = scenes.subset_scene(sc, scenes.morton_order(sc))
+        tr = scenes.ellipse_path_cameras(24, 2101 + 100 * i, 400, 400)
+        d = DeviceScene(sc, dtype=dt)
+        resident[name] = (d, ctx.vf_build(d, tr, L, gamma_dtype=dt), tr.n)
+        extents[name] = sc.extent
     names = list(resident)
-    classes = ((160, 120), (320, 240), (400, 400))
+    classes = ((160, 120), (320, 240), (640, 480))
     pool = []
     rng = np.random.default_rng(77)
-    for i in range(96):
-        nv = int(np.exp(rng.uniform(np.log(16), np.log(64))))
+    for i in range(n_requests):
+        nv = int(np.exp(rng.uniform(np.log(16), np.log(512))))
         wh = classes[int(rng.integers(0, 3))]
-        pool.append((names[int(rng.integers(0, 3))], scenes.room_candidates(nv, 9000 + i, w.scene.extent, *wh)))
-    out = {"requests": len(pool), "views": int(sum(c.n for _, c in pool)), "memory_budget_gib": 8, "rates": {}}
+        sid = names[int(rng.integers(0, len(names)))]
+        pool.append((sid, scenes.room_candidates(nv, 9000 + i, extents[sid], *wh)))
+    torch.cuda.synchronize()
+    budget = 48 << 30
+    out = {"scenes": [f"{nm}:{n}:{dt}" for nm, n, _, _, dt in SERVING_SCENES], "requests": len(pool),
+           "views": int(sum(c.n for _, c in pool)), "pixels": int(sum(c.pixels() for _, c in pool)),
+           "memory_budget_gib": budget >> 30, "rates": {}}
+    log(f"serving: {len(names)} scenes resident, {out['views']} views / {out['pixels'] / 1e6:.0f} Mpix in "
+        f"{len(pool)} requests (setup {time.time() - t0:.1f}s)")
     backends = {}
     for label, slots in (("continuous_batching", 3), ("plain_queue", 1)):
         be = GpuBackend(ctx, n_slots=slots)
         for k, (d, g, nt) in resident.items():
             be.add_scene(k, d, g, L, nt)
         backends[label] = (be, slots)
-    for rate in (300.0, 3000.0, 30000.0):          # Poisson arrivals, requests per second
+    for rate in (100.0, 300.0, 3000.0):          # Poisson arrivals, requests per second
         rr = np.random.default_rng(int(rate))
         t, arrivals = 0.0, []
         for sid, cams in pool:
@@ -109,10 +132,10 @@ def serving_bench(ctx, w, dsc, gamma, L, log):
             arrivals.append((t, sid, cams))
         res = {}
         for label, (be, slots) in backends.items():
-            maxv = 256 if slots > 1 else 0
-            replay(Server(be, memory_budget=8 << 30, n_slots=slots, max_batch_views=maxv), arrivals[:8])
+            maxv = 512 if slots > 1 else 0
+            replay(Server(be, memory_budget=budget, n_slots=slots, max_batch_views=maxv), arrivals[:8])
             torch.cuda.synchronize()
-            st = replay(Server(be, memory_budget=8 << 30, n_slots=slots, max_batch_views=maxv), arrivals)
+            st = replay(Server(be, memory_budget=budget, n_slots=slots, max_batch_views=maxv), arrivals)
             res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
             log(f"serving rate {rate:.0f}/s {label}: {res[label]}")
         out["rates"][str(int(rate))] = res
@@ -380,8 +403,18 @@ def main():
         color = {"query_ms": round(c_ms, 4), "mpix_s": round(px / (c_ms / 1e3) / 1e6, 3),
                  "constant_covariance_query_ms": round(batched_ms, 4),
                  "best_view": int(torch.argmax(s_c).item()), "color_sh_degree": 3}
-        del cvar, s_c
-        log(f"colour covariance {color}")
+        # expected-depth maps beside the entropy maps (the depth eq. id's
+        # correction takes), against the entropy maps alone
+        mbuf = torch.empty(2 * px, dtype=torch.float32, device="cuda")
+        m_ms = timed(lambda: ctx.vf_query_views(dsc, gamma, L, w.train.n, w.cand, uprm, ws_q, scores=s_c,
+                                                want_maps=True, maps=mbuf))
+        d_ms = timed(lambda: ctx.vf_query_views(dsc, gamma, L, w.train.n, w.cand, uprm, ws_q, scores=s_c,
+                                                maps=mbuf, want_depth=True))
+        uprm.write_maps, uprm.write_depth = 0, 0
+        color["maps_query_ms"] = round(m_ms, 4)
+        color["maps_and_depth_query_ms"] = round(d_ms, 4)
+        del cvar, s_c, mbuf
+        log(f"colour covariance / depth {color}")
 
     serving = None
     if not args.no_serving:
@@ -432,7 +465,7 @@ def main():
         "precision": precision,
         "serving": serving,
         "exact_validation": exact,
-        "color_covariance": color,
+        "color_covariance_and_depth": color,
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -113,6 +113,12 @@ typedef struct {
                                    replay it while shapes and pointers repeat */
     int32_t count_pairs;        /* 1: count composited (pixel, Gaussian) pairs, read
                                    back by gv_workspace_check (costs one add per pair) */
+    int32_t write_depth;        /* 1 (with write_maps): maps also receives each pixel's
+                                   expected depth under the same compositing weights,
+                                   sum w* z / sum w* (0 where nothing contributes), the
+                                   per-pixel depth of the spatial-correlation correction
+                                   of eq. id; it follows the entropy maps in the same
+                                   packing, so maps then holds 2 x total pixels floats */
 } gv_uq_params;
 
 /* Workspace plan, filled by the *_workspace_size calls.  The caller
@@ -198,7 +204,8 @@ gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const 
  * scores: device [n_cand] float, sum over the view's pixels of the entropy
  * bound.  maps: device float, optional (NULL, or params->write_maps = 0):
  * the per-pixel maps packed view after view, row major, view v starting at
- * the sum of width*height of views < v.  Enqueue only; a capacity overflow
+ * the sum of width*height of views < v (followed by the expected-depth maps
+ * when params->write_depth is set).  Enqueue only; a capacity overflow
  * is reported by gv_workspace_check (the scores of an overflowed call are
  * NaN). */
 gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,

@@ -57,7 +57,7 @@ class gv_uq_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_float), ("o0", ctypes.c_float), ("half_logdet_Q0", ctypes.c_float),
                 ("half_logdet_Qc", ctypes.c_float), ("eps_T", ctypes.c_float), ("znear", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("cut", ctypes.c_float), ("write_maps", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("count_pairs", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("count_pairs", ctypes.c_int32), ("write_depth", ctypes.c_int32)]
 
 
 class gv_tuning(ctypes.Structure):

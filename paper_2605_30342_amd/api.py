@@ -158,17 +158,23 @@ class Context:
     def vf_query_views(self, dsc: DeviceScene, gamma: torch.Tensor, sh_degree: int, n_train: int, cams,
                        params: Optional[_lib.gv_uq_params] = None, ws: Optional[Workspace] = None,
                        want_maps: bool = False, scores: Optional[torch.Tensor] = None,
-                       maps: Optional[torch.Tensor] = None, stream=None):
+                       maps: Optional[torch.Tensor] = None, stream=None, want_depth: bool = False):
+        """Alg. 4 + Alg. 6 over the candidate views: (scores [n_views], maps).
+        maps (with want_maps) packs the entropy maps view after view; with
+        want_depth it is twice as long and its second half holds the
+        expected-depth maps in the same packing."""
         if params is None:
             params = _lib.default_uq_params()
+        want_maps = want_maps or want_depth
         params.write_maps = 1 if want_maps else 0
+        params.write_depth = 1 if want_depth else 0
         if ws is None:
             ws = self.query_workspace(dsc, cams, params, sh_degree, stream)
         dev = f"cuda:{self.device}"
         if scores is None:
             scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
         if want_maps and maps is None:
-            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+            maps = torch.empty(cams.pixels() * (2 if params.write_depth else 1), dtype=torch.float32, device=dev)
         gdt = {torch.float32: GV_F32, torch.float16: GV_F16, torch.bfloat16: GV_BF16}[gamma.dtype]
         cc = _lib.cameras_to_c(cams)
         check(self.L.vf_query_views(self.h, ctypes.byref(dsc.c), _ptr(gamma), gdt, sh_degree, int(n_train), cc,
@@ -215,7 +221,7 @@ class Context:
         if scores is None:
             scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
         if want_maps and maps is None:
-            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+            maps = torch.empty(cams.pixels() * (2 if params.write_depth else 1), dtype=torch.float32, device=dev)
         gdt = {torch.float32: GV_F32, torch.float16: GV_F16, torch.bfloat16: GV_BF16}[gamma.dtype]
         cc = _lib.cameras_to_c(cams)
         check(self.L.vf_query_views_color(self.h, ctypes.byref(dsc.c), _ptr(gamma), gdt, sh_degree, int(n_train),
@@ -263,7 +269,7 @@ class Context:
         if scores is None:
             scores = torch.empty(cams.n, dtype=torch.float32, device=dev)
         if want_maps and maps is None:
-            maps = torch.empty(cams.pixels(), dtype=torch.float32, device=dev)
+            maps = torch.empty(cams.pixels() * (2 if params.write_depth else 1), dtype=torch.float32, device=dev)
         cc = _lib.cameras_to_c(cams)
         check(self.L.vf_query_views_exact(self.h, ctypes.byref(dsc.c), _ptr(view_vis), _ptr(train_centres),
                                           n_train, float(kappa), cc, cams.n, ctypes.byref(params), _ptr(scores),

@@ -279,6 +279,7 @@ __device__ __forceinline__ int kth_set_bit(uint32_t x, uint32_t k) {
 //   unit direction from training camera p, summed as logs and finished with
 //   expm1 so that small V keep their relative precision.  A training camera
 //   at the Gaussian's centre contributes nothing.
+// With rz (query modes), also the record's depth rz[r] = z (FP32).
 // With cvar (query modes), also the colour term's constant of the record,
 // rcc[r] = 1/2 log|Q_c(d)| + 3/2 log(2 pi e), where channel k of the colour
 // covariance is Q_k(d) = sum_j Y_j(d)^2 cvar[(k Kc + j) n + g] (the colour is
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 const TGam *__restrict__ gamma, float n_train,
                                                 const float *__restrict__ vtrain, const float *__restrict__ tc,
                                                 int ntv, float kappa_log2e, const float *__restrict__ cvar, int Lc,
-                                                float c3, float *__restrict__ rcc,
+                                                float c3, float *__restrict__ rcc, float *__restrict__ rz,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                 Bin *__restrict__ bin) {
     constexpr int K = (L + 1) * (L + 1);
@@ -442,6 +443,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                             }
                             rcc[r] = cc;
                         }
+                        if (rz) rz[r] = (float)Pj.z;
                     }
                     rec[r] = R;
                     key[r] = __float_as_uint((float)Pj.z);
@@ -970,7 +972,7 @@ static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, 
     const TGam *gm = (const TGam *)q.gamma;
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
-        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, rec, key, bin
+        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin
     if constexpr (MODE != 1) {   // no SH evaluation
         hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
     } else {
@@ -989,7 +991,7 @@ static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views
                                  const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
                                  const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
     if (!q) {
-        const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr};
+        const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr, nullptr};
         project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, s);
         return;
     }

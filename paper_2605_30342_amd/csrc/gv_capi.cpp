@@ -104,7 +104,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
-    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, total;
+    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, rz, total;
 };
 
 Layout make_layout(const gv_workspace &p) {
@@ -146,6 +146,7 @@ Layout make_layout(const gv_workspace &p) {
     } else {
         L.tpart = take(T * 4);
         L.rcc = take(R * 4);
+        L.rz = take(R * 4);
     }
     L.total = o;
     return L;
@@ -440,6 +441,8 @@ void gv_default_uq_params(gv_uq_params *p) {
     p->cut = 9.0f;
     p->write_maps = 0;
     p->use_graph = 0;
+    p->count_pairs = 0;
+    p->write_depth = 0;
 }
 
 gv_status gv_create(int device, gv_context **out) {
@@ -758,6 +761,7 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     if (!std::isfinite(prm->half_logdet_Q0) || !std::isfinite(prm->half_logdet_Qc))
         return fail(GV_ERR_INVALID_ARG, "non-finite covariance log-determinants");
     if (prm->write_maps && !maps) return fail(GV_ERR_INVALID_ARG, "write_maps set but maps is NULL");
+    if (prm->write_depth && !prm->write_maps) return fail(GV_ERR_INVALID_ARG, "write_depth needs write_maps");
     DeviceGuard dg(ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<ViewDev> &views = ctx->host_views;
@@ -778,9 +782,11 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     u.eps_T = prm->eps_T;
     u.qcut = (float)(0.5 * prm->cut / std::log(2.0));
     float *mp = prm->write_maps ? maps : nullptr;
+    float *dmp = prm->write_maps && prm->write_depth ? maps + pixels : nullptr;
     QueryArgs qa = q;
     qa.c3 = (float)c3;
     qa.rcc = q.color_var ? at<float>(workspace, Lay.rcc) : nullptr;
+    qa.rz = dmp ? at<float>(workspace, Lay.rz) : nullptr;
     auto enqueue = [&]() -> gv_status {
         Binned bz;
         GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &qa, s, bz));
@@ -789,7 +795,7 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
             StageScope sc(ctx, ST_RASTER_UQ, s);
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), qa.rcc, u, tpart, mp,
+                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
                              prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
@@ -806,12 +812,12 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     struct Key {
         const void *ws, *gamma, *vtrain, *tc, *cvar, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
         int64_t n, n_virtual, rcap, mcap, tiles, nbytes;
-        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv, csh;
+        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv, csh, depth;
         float f[10];
     } key;
     std::memset(&key, 0, sizeof(key));
     key.ws = workspace; key.gamma = q.gamma; key.vtrain = q.view_vis; key.tc = q.train_centres;
-    key.cvar = q.color_var; key.csh = q.color_sh_degree;
+    key.cvar = q.color_var; key.csh = q.color_sh_degree; key.depth = dmp != nullptr;
     key.scores = scores; key.maps = mp;
     key.means = g->means; key.scales = g->scales; key.quats = g->quats; key.opac = g->opacity; key.anchors = g->anchors;
     key.n = g->n; key.n_virtual = g->n_virtual; key.rcap = plan->max_records;

@@ -50,6 +50,7 @@ struct QueryArgs {
     int color_sh_degree;
     float c3;                     // 3/2 log(2 pi e)
     float *rcc;
+    float *rz;                    // optional: the projection writes each record's depth here
 };
 
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
@@ -85,10 +86,13 @@ void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, ui
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
                        int batch, hipStream_t s);
-// rcc: per-record colour constants c_c (NULL: the uniform u.cQc)
+// rcc: per-record colour constants c_c (NULL: the uniform u.cQc); rz and
+// dmaps: per-record depths and the expected-depth maps (both NULL: none;
+// depth maps need maps)
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
-                      float *maps, unsigned long long *pairs, int batch, hipStream_t s);
+                      const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                      float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
+                      hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);

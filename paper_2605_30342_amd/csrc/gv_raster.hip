@@ -336,17 +336,22 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
 // per record from rcc[] (a per-Gaussian colour covariance seen from this
 // view) instead of the uniform u.cQc; costs one more LDS value per entry and
 // one multiply-add per evaluated pair.
-template <int RB, bool MAPS, bool COUNT, bool CC>
+// DEPTH: also the expected depth of every pixel under the same weights,
+// sum w* z / sum w* (0 where nothing contributes), from the per-record depths
+// rz[], into dmaps (packed like maps); the same cost again.
+template <int RB, bool MAPS, bool COUNT, bool CC, bool DEPTH>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
                                                   const Rec *__restrict__ rec, const float *__restrict__ rcc,
+                                                  const float *__restrict__ rz,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
-                                                  unsigned long long *__restrict__ pairs) {
+                                                  float *__restrict__ dmaps, unsigned long long *__restrict__ pairs) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21
     __shared__ float4 wB[WAVES][LCAP];     // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
     __shared__ float wC[CC ? WAVES : 1][CC ? LCAP : 1];   // c_c of the record
+    __shared__ float wD[DEPTH ? WAVES : 1][DEPTH ? LCAP : 1];   // depth of the record
     __shared__ int scnt[WAVES * WAVES];
     __shared__ int slen[WAVES];
     __shared__ float red[WAVES];
@@ -365,6 +370,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     // entropy bound is formed from them after the last Gaussian
     float T = inside ? 1.0f : 0.0f, sx = 0.0f, sxl = 0.0f, sw = 0.0f;
     float sxc = 0.0f;   // sum w* v c_c, with per-record constants
+    float swz = 0.0f;   // sum w* z
     uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const bool loader = t < RB;
     uint32_t r1 = 0, r2 = 0, k1 = 0, k2 = 0;   // record indices and instance keys
     Rec R1 = {};
-    float C1 = 0.0f;
+    float C1 = 0.0f, Z1 = 0.0f;
     if (loader && rg.x + t < rg.y) {
         r1 = ival[rg.x + t];
         k1 = ikey[rg.x + t];
@@ -385,19 +391,21 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     if (loader && rg.x + t < rg.y) {
         R1 = rec[r1];
         if (CC) C1 = rcc[r1];
+        if (DEPTH) Z1 = rz[r1];
     }
 
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
         if (__syncthreads_count(T >= u.eps_T) == 0) break;
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
-        const float Cr = C1;
+        const float Cr = C1, Zr = Z1;
         const uint32_t kq = k1;
         r1 = r2;
         k1 = k2;
         if (loader && b + RB + t < rg.y) {
             R1 = rec[r1];
             if (CC) C1 = rcc[r1];
+            if (DEPTH) Z1 = rz[r1];
         }
         if (loader && b + 2 * RB + t < rg.y) {
             r2 = ival[b + 2 * RB + t];
@@ -420,6 +428,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                 wA[q][pos[q]] = a4;
                 wB[q][pos[q]] = b4;
                 if (CC) wC[q][pos[q]] = Cr;
+                if (DEPTH) wD[q][pos[q]] = Zr;
             }
         }
         {
@@ -429,6 +438,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                 wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
                 wB[q][k] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
                 if (CC) wC[q][k] = 0.0f;
+                if (DEPTH) wD[q][k] = 0.0f;
             }
         }
         __syncthreads();
@@ -440,6 +450,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             const float4 A = wA[w][i0 + jl];
             const float4 B = wB[w][i0 + jl];
             const float Cg = CC ? wC[w][i0 + jl] : 0.0f;
+            const float Zg = DEPTH ? wD[w][i0 + jl] : 0.0f;
             static_for<0, G>([&](auto jc) {
                 // products and sums are rounded separately, so that every
                 // broadcast operand folds into its instruction
@@ -459,6 +470,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                     sxl = fmaf(x, fast_log2(fmaxf(x, 1e-30f)), sxl);
                     sx += x;
                     if (CC) sxc = fmac_row_bcast<jj>(sxc, Cg, x);                                    // x c_c
+                    if (DEPTH) swz = fmac_row_bcast<jj>(swz, Zg, wt);                                // w* z
                     sw += wt;
                     T -= wt;                                                                         // T (1 - alpha*)
                     if (COUNT) npairs += hit ? 1u : 0u;
@@ -478,6 +490,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
     if (!inside) H = 0.0f;
     if (MAPS && inside) maps[V.pix_base + (int64_t)(oy + qy) * V.w + (ox + qx)] = H;
+    if (DEPTH && inside) dmaps[V.pix_base + (int64_t)(oy + qy) * V.w + (ox + qx)] = sw > 0.0f ? swz / sw : 0.0f;
     const float s = wave_sum(H);
     if (lane == 0) red[w] = s;
     __syncthreads();
@@ -756,40 +769,55 @@ void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint
     }
 }
 
-template <int RB, bool CC>
+template <int RB, bool CC, bool DEPTH>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                         const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
-                         float *maps, unsigned long long *pairs, hipStream_t s) {
+                         const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                         float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
-#define GV_UQ_ARGS views, nv, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs
-    if (maps && pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC>), g, b, 0, s, GV_UQ_ARGS);
-    else if (maps)
-        hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC>), g, b, 0, s, GV_UQ_ARGS);
-    else if (pairs)
-        hipLaunchKernelGGL((k_raster_uq<RB, false, true, CC>), g, b, 0, s, GV_UQ_ARGS);
-    else
-        hipLaunchKernelGGL((k_raster_uq<RB, false, false, CC>), g, b, 0, s, GV_UQ_ARGS);
+#define GV_UQ_ARGS views, nv, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs
+    if constexpr (DEPTH) {   // depth maps come with the entropy maps
+        if (pairs)
+            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true>), g, b, 0, s, GV_UQ_ARGS);
+        else
+            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, true>), g, b, 0, s, GV_UQ_ARGS);
+    } else {
+        if (maps && pairs)
+            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+        else if (maps)
+            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+        else if (pairs)
+            hipLaunchKernelGGL((k_raster_uq<RB, false, true, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+        else
+            hipLaunchKernelGGL((k_raster_uq<RB, false, false, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+    }
 #undef GV_UQ_ARGS
 }
 
 template <int RB>
-static void raster_uq_cc(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                         const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
-                         float *maps, unsigned long long *pairs, hipStream_t s) {
-    if (rcc) raster_uq_rb<RB, true>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s);
-    else raster_uq_rb<RB, false>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s);
+static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
+                          const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
+    const bool depth = dmaps && maps && rz;
+    if (rcc && depth) raster_uq_rb<RB, true, true>(GV_UQ_ARGS);
+    else if (rcc) raster_uq_rb<RB, true, false>(GV_UQ_ARGS);
+    else if (depth) raster_uq_rb<RB, false, true>(GV_UQ_ARGS);
+    else raster_uq_rb<RB, false, false>(GV_UQ_ARGS);
+#undef GV_UQ_ARGS
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const float *rcc, const UqArgs &u, float *tile_part,
-                      float *maps, unsigned long long *pairs, int batch, hipStream_t s) {
+                      const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                      float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
+                      hipStream_t s) {
     if (total_tiles <= 0) return;
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
     switch (batch) {
-    case 64: raster_uq_cc<64>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
-    case 256: raster_uq_cc<256>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
-    default: raster_uq_cc<128>(views, nv, total_tiles, ranges, ival, ikey, rec, rcc, u, tile_part, maps, pairs, s); break;
+    case 64: raster_uq_var<64>(GV_UQ_ARGS); break;
+    case 256: raster_uq_var<256>(GV_UQ_ARGS); break;
+    default: raster_uq_var<128>(GV_UQ_ARGS); break;
     }
+#undef GV_UQ_ARGS
 }
 
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,

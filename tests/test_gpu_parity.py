@@ -178,14 +178,20 @@ def test_kappa_zero_isotropic_on_gpu(ctx, tiny):
 
 # ---------------------------------------------------------------- edge cases
 
+def _ragged_cams(w):
+    """Five views of mixed and ragged sizes (37x23, 1x1, 128x96, 200x17,
+    16x16) from the first candidate's centre, looking at the origin."""
+    C = w.cand.centers[:1].repeat(5, 0)
+    sizes = [(37, 23), (1, 1), (128, 96), (200, 17), (16, 16)]
+    return Cameras.concat([scenes.make_cameras(C[i:i + 1], np.zeros((1, 3)), ww, hh, 60.0)
+                           for i, (ww, hh) in enumerate(sizes)])
+
+
 def test_ragged_and_mixed_resolutions_in_one_call(ctx, tiny, tiny_ref):
     say("case: ragged/mixed resolutions 37x23, 1x1, 128x96, 200x17, 16x16")
     _, g32, _ = tiny_ref
     prm = oracle_params()
-    C = tiny.cand.centers[:1].repeat(5, 0)
-    sizes = [(37, 23), (1, 1), (128, 96), (200, 17), (16, 16)]
-    cams = Cameras.concat([scenes.make_cameras(C[i:i + 1], np.zeros((1, 3)), w, h, 60.0)
-                           for i, (w, h) in enumerate(sizes)])
+    cams = _ragged_cams(tiny)
     q = oracle.vf_query(tiny.scene, g32, 2, tiny.train.n, cams, prm)
     s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, tiny.train.n, cams)
     assert compare_maps(mp, q)[0] <= 1.0
