@@ -598,8 +598,10 @@ __device__ __forceinline__ void radix_chunk(uint64_t n, uint64_t &start, uint64_
     if (start > n) start = n;
 }
 
+// drop: keys whose tile field (key & TILE_KEY_MASK) equals it are left out of
+// the pass (DEAD_KEY: none); their count does not enter the histogram.
 __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
-                                                   int shift, int nbits, uint32_t *__restrict__ hist) {
+                                                   int shift, int nbits, uint32_t drop, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[WAVES][RADIX];
     const int t = threadIdx.x, w = t >> 6;
 #pragma unroll
@@ -618,7 +620,7 @@ __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ 
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
             const uint64_t e = s + (uint64_t)i * WG + t;
-            if (e < end) atomicAdd(&h[w][(k[i] >> shift) & mask], 1u);
+            if (e < end && (k[i] & TILE_KEY_MASK) != drop) atomicAdd(&h[w][(k[i] >> shift) & mask], 1u);
         }
     }
     __syncthreads();
@@ -669,21 +671,28 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) 
     return base + inc - x;
 }
 
+// With drop (see k_radix_hist) the kept pairs are written compacted and their
+// total goes to *n_kept (by one thread of block 0), the count the following
+// passes take.
 __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                      const uint32_t *n_dev, int shift, int nbits,
+                                                      const uint32_t *n_dev, int shift, int nbits, uint32_t drop,
                                                       const uint32_t *__restrict__ hist,
-                                                      const uint32_t *__restrict__ dtot) {
+                                                      const uint32_t *__restrict__ dtot,
+                                                      uint32_t *__restrict__ n_kept) {
     __shared__ uint32_t run[RADIX];          // output position of this block's next pair of each digit
     __shared__ uint32_t wcnt[WAVES][RADIX];  // wave counts, then wave offsets inside the digit
     __shared__ uint32_t lbase[RADIX];        // first slot of each digit in the staged tile
     __shared__ uint32_t goff[RADIX];         // output position minus staged slot, per digit
     __shared__ uint32_t wtot[WAVES];
+    __shared__ uint32_t skept;               // pairs staged in the current tile
     __shared__ uint32_t sk[RTILE], sv[RTILE];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     {   // digit bases: exclusive scan of the digit totals plus this block's offset
         const uint32_t d = dtot[t];
-        run[t] = block_excl_scan(d, wtot) + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
+        const uint32_t ex = block_excl_scan(d, wtot);
+        run[t] = ex + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
+        if (n_kept && blockIdx.x == 0 && t == RADIX - 1) *n_kept = ex + d;
     }
     uint64_t start, end;
     radix_chunk(*n_dev, start, end);
@@ -691,11 +700,13 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
     for (uint64_t s = start; s < end; s += RTILE) {
         const uint64_t base = s + (uint64_t)w * RWAVE + lane;
         uint32_t k[RITEMS], v[RITEMS], pos[RITEMS];
+        bool keep[RITEMS];
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
             const uint64_t e = base + (uint64_t)i * 64;
             k[i] = e < end ? kin[e] : 0u;
             v[i] = e < end ? (vin ? vin[e] : (uint32_t)e) : 0u;
+            keep[i] = e < end && (k[i] & TILE_KEY_MASK) != drop;
         }
         // this wave's counters start the tile at zero (wave-private row)
 #pragma unroll
@@ -705,7 +716,7 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
-            const bool valid = base + (uint64_t)i * 64 < end;
+            const bool valid = keep[i];
             const uint32_t d = (k[i] >> shift) & mask;
             unsigned long long peers = __builtin_amdgcn_ballot_w64(valid);
             for (int bb = 0; bb < nbits; ++bb) {
@@ -736,12 +747,13 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
             lbase[t] = lb;
             goff[t] = run[t] - lb;
             run[t] += tot;
+            if (t == RADIX - 1) skept = lb + tot;
         }
         __syncthreads();
         // stage the tile in digit order ...
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
-            if (base + (uint64_t)i * 64 < end) {
+            if (keep[i]) {
                 const uint32_t d = (k[i] >> shift) & mask;
                 const uint32_t slot = lbase[d] + wcnt[w][d] + pos[i];
                 sk[slot] = k[i];
@@ -750,7 +762,7 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
         }
         __syncthreads();
         // ... and write it out: consecutive lanes write consecutive positions of a digit run
-        const uint32_t cnt = (uint32_t)min((uint64_t)RTILE, end - s);
+        const uint32_t cnt = skept;
         for (uint32_t j = t; j < cnt; j += WG) {
             const uint32_t key = sk[j];
             const uint32_t o = goff[(key >> shift) & mask] + j;
@@ -875,7 +887,7 @@ __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, 
 __global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key, const Status *__restrict__ st,
                                                uint32_t dead_tile, uint2 *__restrict__ ranges) {
     if (st->overflow) return;
-    const uint64_t n = st->M_eff;
+    const uint64_t n = st->M_live;
     // four consecutive keys per thread (one 16-byte load where aligned and
     // complete) and the key before them; run ends are found against the next
     // key, which is the first of the following thread's four
@@ -1033,7 +1045,7 @@ size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / S
 // in (k0, v0), 1 if it is in (k1, v1).  With iota set, the input values are
 // the indices 0..n-1 and v0 is only used as a buffer.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
-                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s) {
+                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept) {
     int cur = 0;
     const uint32_t *vin = iota ? nullptr : v0;
     // digits of equal width (at most RADIX_BITS): a narrow last digit would
@@ -1043,9 +1055,14 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         const int nb = (bits - shift + (passes - p) - 1) / (passes - p);
         uint32_t *ki = cur ? k1 : k0, *ko = cur ? k0 : k1;
         uint32_t *vo = cur ? v0 : v1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, n_dev, shift, nb, hist);
+        // the first pass drops the `drop` keys; later passes sort the kept ones
+        const uint32_t dk = p == 0 ? drop : DEAD_KEY;
+        uint32_t *kept = p == 0 && drop != DEAD_KEY ? n_kept : nullptr;
+        hipLaunchKernelGGL(k_radix_hist, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, n_dev, shift, nb, dk, hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, hist, dtot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, dk,
+                           hist, dtot, kept);
+        if (kept) n_dev = kept;
         cur ^= 1;
         vin = cur ? v1 : v0;
         shift += nb;

@@ -397,8 +397,10 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     int tres;
     {
         StageScope sc(ctx, ST_SORT_TILE, s);
-        // tile ids 0..tiles, where tiles marks dead instances
-        tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles + 1), false, hist, dtot, s);
+        // tile ids 0..tiles - 1; the first pass drops the dead instances (tile
+        // id `tiles`) and leaves the live count in M_live
+        tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s,
+                                 (uint32_t)tiles, &st->M_live);
     }
     const uint32_t *skey = tres ? ik1 : ik0;
     {
