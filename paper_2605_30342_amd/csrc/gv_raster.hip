@@ -366,9 +366,10 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     quadrant_pixel(t, qx, qy);
     const float px = (float)qx + 0.5f, py = (float)qy + 0.5f;
     const bool inside = (ox + qx < V.w) && (oy + qy < V.h);
-    // per pixel: sx = sum w* v, sxl = sum w* v log2(w* v), sw = sum w*; the
-    // entropy bound is formed from them after the last Gaussian
-    float T = inside ? 1.0f : 0.0f, sx = 0.0f, sxl = 0.0f, sw = 0.0f;
+    // per pixel: sx = sum w* v, sxl = sum w* v log2(w* v); the entropy bound is
+    // formed from them after the last Gaussian, with sum w* = 1 - T (every
+    // composited w* = alpha* T is taken off T)
+    float T = inside ? 1.0f : 0.0f, sx = 0.0f, sxl = 0.0f;
     float sxc = 0.0f;   // sum w* v c_c, with per-record constants
     float swz = 0.0f;   // sum w* z
     uint32_t npairs = 0;
@@ -471,7 +472,6 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                     sx += x;
                     if (CC) sxc = fmac_row_bcast<jj>(sxc, Cg, x);                                    // x c_c
                     if (DEPTH) swz = fmac_row_bcast<jj>(swz, Zg, wt);                                // w* z
-                    sw += wt;
                     T -= wt;                                                                         // T (1 - alpha*)
                     if (COUNT) npairs += hit ? 1u : 0u;
                 }
@@ -486,6 +486,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     }
     // H = sum_hits x (cQc - ln x) + w0 (cQ0 - ln w0), w0 = sum w* (1 - v) = sw - sx >= 0
     float H = CC ? fmaf(-LN2, sxl, sxc) : fmaf(u.cQc, sx, -LN2 * sxl);
+    const float sw = inside ? 1.0f - T : 0.0f;
     const float w0 = sw - sx;
     if (w0 > 0.0f) H = fmaf(w0, fmaf(-LN2, fast_log2(w0), u.cQ0), H);
     if (!inside) H = 0.0f;
