@@ -295,7 +295,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 int ntv, float kappa_log2e, const float *__restrict__ cvar, int Lc,
                                                 float c3, float *__restrict__ rcc, float *__restrict__ rz,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
-                                                Bin *__restrict__ bin) {
+                                                Bin *__restrict__ bin, uint32_t *__restrict__ ntr) {
     constexpr int K = (L + 1) * (L + 1);
     __shared__ uint32_t srel[WAVES][64];   // first record of each entry (relative)
     __shared__ uint8_t cl[WAVES][64];      // lanes of the entries that own records, in order
@@ -364,6 +364,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 Bin b = {};
                 if (!Pj.ok) {
                     bin[r] = b;
+                    ntr[r] = 0u;
                     key[r] = DEAD_KEY;
                     rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
@@ -461,6 +462,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     b.l21 = R.l21;
                     b.l22 = R.l22;
                     bin[r] = b;
+                    ntr[r] = bin_ntiles(b.dims);
                 }
             }
             started += (uint32_t)__popcll(P);
@@ -776,12 +778,13 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
 
 // ---------------------------------------------------------------- binning
 
-// Tile count of every record, in depth order.
-__global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
+// Tile count of every record, in depth order, gathered from the dense
+// per-record counts the projection wrote.
+__global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict__ sval, const uint32_t *__restrict__ ntr,
                                                       const uint32_t *n_dev, uint32_t *__restrict__ icnt) {
     const uint64_t n = *n_dev;
     for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
-        icnt[i] = bin_ntiles(bin[sval[i]].dims);
+        icnt[i] = ntr[sval[i]];
 }
 
 // One (global tile id, record) instance per tile of every record, written in
@@ -977,14 +980,14 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
 template <typename TG, typename TGam, int MODE>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
-                               const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+                               const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
     const uint64_t chunks = ((uint64_t)a.n * PROJ_SPLIT + 63) / 64;
     const unsigned grid = (unsigned)std::min<uint64_t>((chunks + WAVES - 1) / WAVES, 4096);
     const int mw = mask_words(nv);
     const TGam *gm = (const TGam *)q.gamma;
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
-        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin
+        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr
     if constexpr (MODE != 1) {   // no SH evaluation
         hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
     } else {
@@ -1001,32 +1004,32 @@ static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, 
 template <typename TG>
 static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                  const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
-                                 const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, hipStream_t s) {
+                                 const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
     if (!q) {
         const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr, nullptr};
-        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, s);
+        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, ntr, s);
         return;
     }
     if (q->mode == 2) {
-        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s);
+        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s);
         return;
     }
     switch (q->gamma_dtype) {
-    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
-    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
-    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, s); break;
+    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
+    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
+    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
     }
 }
 
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, hipStream_t s) {
+                    uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
     if (a.n == 0) return;
     const int L = q ? q->sh_degree : 0;
     switch (a.dtype) {
-    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
-    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
-    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, s); break;
+    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
+    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
+    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
     }
 }
 
@@ -1070,8 +1073,8 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
     return cur;
 }
 
-void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_ntiles, dim3(2048), dim3(WG), 0, s, sval, bin, n_dev, icnt);
+void launch_gather_ntiles(const uint32_t *sval, const uint32_t *ntr, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_ntiles, dim3(2048), dim3(WG), 0, s, sval, ntr, n_dev, icnt);
 }
 
 void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,

@@ -103,7 +103,7 @@ bool finite_cam(const gv_camera &c) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, icnt, ioff;
+    size_t status, views, cnt, vmask, offs, blk, rec, bin, ntr, key0, val0, key1, val1, icnt, ioff;
     size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, rz, total;
 };
 
@@ -126,6 +126,7 @@ Layout make_layout(const gv_workspace &p) {
     L.blk = take(scan_blk_count(std::max(N * PROJ_SPLIT, R)) * 8);
     L.rec = take(R * sizeof(Rec));
     L.bin = take(R * sizeof(Bin));
+    L.ntr = take(R * 4);
     L.key0 = take(R * 4);
     L.val0 = take(R * 4);
     L.key1 = take(R * 4);
@@ -361,6 +362,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     unsigned long long *blk = at<unsigned long long>(ws, L.blk);
     Rec *rec = at<Rec>(ws, L.rec);
     Bin *bin = at<Bin>(ws, L.bin);
+    uint32_t *ntr = at<uint32_t>(ws, L.ntr);
     uint32_t *k0 = at<uint32_t>(ws, L.key0), *v0 = at<uint32_t>(ws, L.val0);
     uint32_t *k1 = at<uint32_t>(ws, L.key1), *v1 = at<uint32_t>(ws, L.val1);
     uint32_t *icnt = at<uint32_t>(ws, L.icnt), *ioff = at<uint32_t>(ws, L.ioff);
@@ -379,7 +381,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     }
     {
         StageScope sc(ctx, ST_PROJECT, s);
-        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, s);
+        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, ntr, s);
     }
     int dres;
     {
@@ -389,7 +391,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     const uint32_t *sval = dres ? v1 : v0;
     {
         StageScope sc(ctx, ST_EMIT, s);
-        launch_gather_ntiles(sval, bin, &st->R_eff, icnt, s);
+        launch_gather_ntiles(sval, ntr, &st->R_eff, icnt, s);
         launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
         launch_emit(sval, bin, ioff, st, (float)(0.5 * geo.cut / std::log(2.0)), (uint32_t)tiles, ik0, iv0, s);

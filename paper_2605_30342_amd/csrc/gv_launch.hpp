@@ -64,7 +64,7 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, hipStream_t s);
+                    uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s);
 
 size_t scan_blk_count(uint64_t n_cap);
 void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
@@ -83,7 +83,7 @@ void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, cons
 void launch_vis_finish(int64_t n, float *out, hipStream_t s);
 void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *vmask, int mw, const float *acc_T,
                      const uint32_t *acc_c, const Status *st, float *out, unsigned long long *pairs, hipStream_t s);
-void launch_gather_ntiles(const uint32_t *sval, const Bin *bin, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
+void launch_gather_ntiles(const uint32_t *sval, const uint32_t *ntr, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
 void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
                  uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s);
