@@ -431,11 +431,19 @@ def main():
         tr = w.train.subset([0, w.train.n // 3, 2 * w.train.n // 3])
         g = oracle.vf_build(w.scene, tr, L, prm)["gamma"]
         tc = time.perf_counter()
-        oracle.vf_query(w.scene, g, L, tr.n, sub, prm, want_maps=False)
+        qo = oracle.vf_query(w.scene, g, L, tr.n, sub, prm, want_maps=False)
         dt = time.perf_counter() - tc
         cpu = {"value": round(sub.pixels() / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": f"VF QUERY of {sub.n} of the {w.cand.n} candidate views "
                                           f"({sub.pixels()} px, full scene, field of 3 training views), {dt:.1f} s"}
+        # the batched GPU form (all candidates in one call, same FP32-rounded
+        # field) against these FP64 scores
+        gdev = torch.from_numpy(np.ascontiguousarray(g.astype(np.float32).T)).cuda()
+        s_b = torch.empty_like(scores)
+        ctx.vf_query_views(dsc, gdev, L, tr.n, w.cand, uprm, ws_q, scores=s_b)
+        torch.cuda.synchronize()
+        rel = np.abs(s_b.double().cpu().numpy()[:sub.n] - qo["scores"]) / np.abs(qo["scores"])
+        cpu["batched_gpu_vs_oracle_max_rel_score_error"] = float(rel.max())
         log(f"cpu baseline {cpu}")
 
     out = {
