@@ -150,3 +150,40 @@ def test_gpu_view_visibility_feeds_exact_query(ctx, tiny):
     gap = np.abs(s_sh - s) / np.abs(s)
     say(f"  SH-query score gap to exact: max {gap.max():.4f}")
     assert np.all(np.isfinite(s_sh)) and np.all(np.isfinite(s))
+
+
+def test_extension_arguments_are_rejected(ctx, tiny):
+    """The exact, colour and depth entry points validate their arguments
+    before enqueuing anything (errors come back as GvError, no launch)."""
+    say("case: argument validation of the extension entry points")
+    import ctypes
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd._lib import GvError, check
+    dsc = _dsc(tiny.scene)
+    prm = _lib.default_uq_params()
+    ws = ctx.query_workspace(dsc, tiny.cand, prm, 2)
+    n = tiny.scene.n
+    vis = torch.zeros((2, n), device="cuda")
+    cen = torch.zeros((2, 3), device="cuda")
+    with pytest.raises(GvError):   # negative kappa
+        ctx.vf_query_views_exact(dsc, vis, cen, -1.0, tiny.cand, prm, ws)
+    with pytest.raises(ValueError):   # centres of the wrong shape (caught by the binding)
+        ctx.vf_query_views_exact(dsc, vis, torch.zeros((3, 3), device="cuda"), 1.0, tiny.cand, prm, ws)
+    cc = _lib.cameras_to_c(tiny.cand)
+    scores = torch.empty(tiny.cand.n, device="cuda")
+    with pytest.raises(GvError):   # NULL per-view visibility with training views (direct C call)
+        check(ctx.L.vf_query_views_exact(ctx.h, ctypes.byref(dsc.c), None, ctypes.c_void_p(cen.data_ptr()), 2,
+                                         1.0, cc, tiny.cand.n, ctypes.byref(prm),
+                                         ctypes.c_void_p(scores.data_ptr()), None, ctypes.byref(ws.plan),
+                                         ctypes.c_void_p(ws.buf.data_ptr()), None))
+    g = torch.zeros((9, n), device="cuda")
+    cv = torch.zeros((3, 25, n), device="cuda")   # colour degree 4: unsupported
+    with pytest.raises(GvError):
+        ctx.vf_query_views_color(dsc, g, 2, 8, cv, tiny.cand, prm, ws)
+    bad = _lib.default_uq_params(write_depth=1)   # depth without maps
+    with pytest.raises(GvError):
+        check(ctx.L.vf_query_views(ctx.h, ctypes.byref(dsc.c), ctypes.c_void_p(g.data_ptr()), 0, 2, 8, cc,
+                                   tiny.cand.n, ctypes.byref(bad), ctypes.c_void_p(scores.data_ptr()), None,
+                                   ctypes.byref(ws.plan), ctypes.c_void_p(ws.buf.data_ptr()), None))
+    torch.cuda.synchronize()
