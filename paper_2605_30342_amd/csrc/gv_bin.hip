@@ -264,6 +264,16 @@ __device__ __forceinline__ int kth_set_bit(uint32_t x, uint32_t k) {
     return pos;
 }
 
+// log(1 - a) for a in [0, 1], accurate also for small a: with u = 1 - a
+// rounded, log(u) a / (1 - u) cancels the rounding error of u (the log1p
+// identity of Goldberg, "What every computer scientist should know about
+// floating-point arithmetic", 1991).  u = 1 gives -a, u = 0 gives -infinity.
+__device__ __forceinline__ float log_one_minus(float a) {
+    const float u = 1.0f - a;
+    const float l = __builtin_amdgcn_logf(u) * 0.6931471805599453f * (a * __builtin_amdgcn_rcpf(1.0f - u));
+    return u == 1.0f ? -a : l;
+}
+
 // Projection of every surviving (Gaussian, view) pair into its record slot,
 // one record per lane.  A wave takes 64 consecutive (Gaussian, view subset)
 // entries and enumerates their records in chunks of 64: the entry owning a
@@ -390,6 +400,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                             const float inv = 1.0f / nrm;
                             dx *= inv; dy *= inv; dz *= inv;
                             float lsum = 0.0f;   // sum_p log(1 - v_p nu_p)
+#pragma unroll 4
                             for (int p = 0; p < ntv; ++p) {
                                 const float vp = vtrain[(int64_t)p * G.n + g];
                                 const float ex = m[0] - tc[3 * p], ey = m[1] - tc[3 * p + 1], ez = m[2] - tc[3 * p + 2];
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                 const float cosang = fmaf(dx, ex, fmaf(dy, ey, dz * ez)) * rsqrtf(e2);
                                 const float nu = exp2f(kappa_log2e * (cosang - 1.0f));
                                 const float a = e2 > 0.0f ? fminf(vp * nu, 1.0f) : 0.0f;
-                                lsum += log1pf(-a);
+                                lsum += log_one_minus(a);
                             }
                             vis = -expm1f(lsum);
                         }
