@@ -234,4 +234,30 @@ __device__ __forceinline__ uint32_t quadrant_mask_bands(float ux, float uy, floa
     return m;
 }
 
+// The same test for the sixteen 4 x 4 sub-blocks of the tile: bit 4 q + r is
+// set when the ellipse reaches sub-block r (2 row + column inside the
+// quadrant) of quadrant q, from four bands of four pixel rows and four blocks
+// of four pixel columns, with the same widening.
+__device__ __forceinline__ uint32_t subblock_mask_bands(float ux, float uy, float kx, float ia, float c, float eyR,
+                                                        float hy, float qc) {
+    const float mg = fmaf(1e-5f, fabsf(ux), 0.01f);
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float lo = fmaxf(uy - (4.0f * j + 3.5f), -hy), hi = fminf(uy - (4.0f * j + 0.5f), hy);
+        const float eR = __builtin_amdgcn_fmed3f(eyR, lo, hi), eL = __builtin_amdgcn_fmed3f(-eyR, lo, hi);
+        const float tR = c * eR, tL = c * eL;
+        const float sR = sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f)), sL = sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
+        const float xmax = fmaf(sR, ia, fmaf(kx, eR, ux)) + mg;
+        const float xmin = fmaf(-sL, ia, fmaf(kx, eL, ux)) - mg;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool in = lo <= hi && xmax >= 4.0f * i + 0.5f && xmin <= 4.0f * i + 3.5f;
+            const int q = ((j >> 1) << 1) + (i >> 1), r = ((j & 1) << 1) + (i & 1);
+            m |= in ? 1u << (4 * q + r) : 0u;
+        }
+    }
+    return m;
+}
+
 }  // namespace gv

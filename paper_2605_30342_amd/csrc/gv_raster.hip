@@ -332,6 +332,21 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
 
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
 
+// Lane -> pixel of the query blend: wave w covers quadrant w (8 x 8 pixels)
+// and DPP row r of the wave (16 lanes) the 4 x 4 sub-block r of it.
+__device__ __forceinline__ void subblock_pixel(int t, int &qx, int &qy) {
+    const int w = t >> 6, l = t & 63, r = l >> 4, j = l & 15;
+    qx = ((w & 1) << 3) + ((r & 1) << 2) + (j & 3);
+    qy = ((w >> 1) << 3) + ((r >> 1) << 2) + (j >> 2);
+}
+
+// Each record of a batch is staged once (slot = its index in the batch); the
+// 16 sub-blocks of the tile keep depth-ordered lists of slot indices, built
+// from a 16-bit sub-block mask computed per record at staging.  A wave
+// walks the four lists of its quadrant side by side: lane j of row r reads
+// entry i0 + j of sub-block r's list (or a never-hit slot past its end), and
+// entry jj reaches the row's 16 pixels by row broadcast, so every row
+// composites its own list.  The wave iterates as long as its longest list.
 // CC: the colour term's constant c_c = 1/2 log|Q_c| + 3/2 log(2 pi e) comes
 // per record from rcc[] (a per-Gaussian colour covariance seen from this
 // view) instead of the uniform u.cQc; costs one more LDS value per entry and
@@ -347,13 +362,14 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                                                   const float *__restrict__ rz,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   float *__restrict__ dmaps, unsigned long long *__restrict__ pairs) {
-    constexpr int LCAP = RB + LGROUP;
-    __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21
-    __shared__ float4 wB[WAVES][LCAP];     // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
-    __shared__ float wC[CC ? WAVES : 1][CC ? LCAP : 1];   // c_c of the record
-    __shared__ float wD[DEPTH ? WAVES : 1][DEPTH ? LCAP : 1];   // depth of the record
-    __shared__ int scnt[WAVES * WAVES];
-    __shared__ int slen[WAVES];
+    constexpr int NL = 4 * WAVES;          // sub-block lists per tile
+    __shared__ float4 wA[RB + 1];          // ux, uy, l11, l21 per batch slot (slot RB: never hit)
+    __shared__ float4 wB[RB + 1];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
+    __shared__ float wC[CC ? RB + 1 : 1];        // c_c of the record
+    __shared__ float wD[DEPTH ? RB + 1 : 1];     // depth of the record
+    __shared__ uint16_t idx[NL][RB];       // per sub-block: slots in batch (= depth) order
+    __shared__ int scnt[WAVES][NL];
+    __shared__ int slen[NL];
     __shared__ float red[WAVES];
 
     const int gt = blockIdx.x;
@@ -363,7 +379,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     const int ox = (lt % V.tiles_x) * TILE, oy = (lt / V.tiles_x) * TILE;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     int qx, qy;
-    quadrant_pixel(t, qx, qy);
+    subblock_pixel(t, qx, qy);
     const float px = (float)qx + 0.5f, py = (float)qy + 0.5f;
     const bool inside = (ox + qx < V.w) && (oy + qy < V.h);
     // per pixel: sx = sum w* v, sxl = sum w* v log2(w* v); the entropy bound is
@@ -375,20 +391,22 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     uint32_t npairs = 0;
     const uint2 rg = ranges[gt];
     const float ob = u.o0 * (1.0f - u.beta);
+    const float qcb = band_threshold(u.qcut), sqb = sqrtf(qcb);
+    const int mylist = 4 * w + (lane >> 4);
+    if (t == 0) {
+        wA[RB] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
+        wB[RB] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+        if (CC) wC[RB] = 0.0f;
+        if (DEPTH) wD[RB] = 0.0f;
+    }
 
     // records are prefetched as in the VF CONST blend
     const bool loader = t < RB;
-    uint32_t r1 = 0, r2 = 0, k1 = 0, k2 = 0;   // record indices and instance keys
+    uint32_t r1 = 0, r2 = 0;   // record indices
     Rec R1 = {};
     float C1 = 0.0f, Z1 = 0.0f;
-    if (loader && rg.x + t < rg.y) {
-        r1 = ival[rg.x + t];
-        k1 = ikey[rg.x + t];
-    }
-    if (loader && rg.x + RB + t < rg.y) {
-        r2 = ival[rg.x + RB + t];
-        k2 = ikey[rg.x + RB + t];
-    }
+    if (loader && rg.x + t < rg.y) r1 = ival[rg.x + t];
+    if (loader && rg.x + RB + t < rg.y) r2 = ival[rg.x + RB + t];
     if (loader && rg.x + t < rg.y) {
         R1 = rec[r1];
         if (CC) C1 = rcc[r1];
@@ -400,58 +418,61 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
         const float Cr = C1, Zr = Z1;
-        const uint32_t kq = k1;
         r1 = r2;
-        k1 = k2;
         if (loader && b + RB + t < rg.y) {
             R1 = rec[r1];
             if (CC) C1 = rcc[r1];
             if (DEPTH) Z1 = rz[r1];
         }
-        if (loader && b + 2 * RB + t < rg.y) {
-            r2 = ival[b + 2 * RB + t];
-            k2 = ikey[b + 2 * RB + t];
-        }
-        const uint32_t mask = have ? kq >> QMASK_SHIFT : 0u;
-        float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
+        if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
+        // stage the record in its slot and find the sub-blocks it reaches
+        uint32_t smask = 0u;
         if (have) {
             float ux, uy;
             local_centre(R, ox, oy, ux, uy);
             const float v = R.v;
-            a4 = make_float4(ux, uy, R.l11, R.l21);
-            b4 = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
+            wA[t] = make_float4(ux, uy, R.l11, R.l21);
+            wB[t] = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
+            if (CC) wC[t] = Cr;
+            if (DEPTH) wD[t] = Zr;
+            const EllipseBands E = ellipse_bands(R.l11, R.l21, R.l22, sqb);
+            smask = subblock_mask_bands(ux, uy, E.kx, E.ia, R.l22, E.eyR, E.hy, qcb);
         }
-        int pos[WAVES];
-        list_positions(mask, pos, scnt, slen);
+        // slot lists: this wave's counts per list, then offsets across waves
 #pragma unroll
-        for (int q = 0; q < WAVES; ++q) {
-            if (pos[q] >= 0) {
-                wA[q][pos[q]] = a4;
-                wB[q][pos[q]] = b4;
-                if (CC) wC[q][pos[q]] = Cr;
-                if (DEPTH) wD[q][pos[q]] = Zr;
-            }
-        }
-        {
-            int q;
-            const int k = pad_slot(slen, q);
-            if (k >= 0) {
-                wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
-                wB[q][k] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
-                if (CC) wC[q][k] = 0.0f;
-                if (DEPTH) wD[q][k] = 0.0f;
-            }
+        for (int l = 0; l < NL; ++l) {
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((smask >> l) & 1u) != 0u);
+            if (lane == 0) scnt[w][l] = (int)__popcll(bal);
         }
         __syncthreads();
-        const int len = __builtin_amdgcn_readfirstlane(slen[w]);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((smask >> l) & 1u) != 0u);
+            if ((smask >> l) & 1u) {
+                int off = (int)lanes_below(bal);
+                for (int ww = 0; ww < w; ++ww) off += scnt[ww][l];
+                idx[l][off] = (uint16_t)t;
+            }
+        }
+        if (t < NL) {
+            int n = 0;
+#pragma unroll
+            for (int ww = 0; ww < WAVES; ++ww) n += scnt[ww][t];
+            slen[t] = n;
+        }
+        __syncthreads();
+        const int mylen = slen[mylist];
+        const int len = __builtin_amdgcn_readfirstlane(
+            max(max(slen[4 * w], slen[4 * w + 1]), max(slen[4 * w + 2], slen[4 * w + 3])));
         const int jl = lane & (LGROUP - 1);
-        // one group of G entries (G = LGROUP, or LPAD for the last few)
+        // one group of G entries per row (G = LGROUP, or LPAD for the last few)
         auto group = [&](int i0, auto gs) {
             constexpr int G = decltype(gs)::value;
-            const float4 A = wA[w][i0 + jl];
-            const float4 B = wB[w][i0 + jl];
-            const float Cg = CC ? wC[w][i0 + jl] : 0.0f;
-            const float Zg = DEPTH ? wD[w][i0 + jl] : 0.0f;
+            const int slot = i0 + jl < mylen ? (int)idx[mylist][i0 + jl] : RB;
+            const float4 A = wA[slot];
+            const float4 B = wB[slot];
+            const float Cg = CC ? wC[slot] : 0.0f;
+            const float Zg = DEPTH ? wD[slot] : 0.0f;
             static_for<0, G>([&](auto jc) {
                 // products and sums are rounded separately, so that every
                 // broadcast operand folds into its instruction
