@@ -588,7 +588,8 @@ __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ i
 // ---------------------------------------------------------------- LSD radix sort
 
 // Each pass sorts (key, value) pairs stably by one digit of up to 8 bits.
-// The n pairs are cut into RADIX_BLOCKS contiguous chunks of whole tiles
+// The n pairs are cut into one contiguous chunk of whole tiles per block (the
+// grid is sized from the capacity so that a block gets about one tile)
 // (RTILE = 2048 pairs).  Block b histograms its chunk; the histograms are
 // scanned digit-major; block b then walks its chunk tile by tile.  In a tile,
 // wave w owns pairs [w * 512, (w + 1) * 512) and loads all eight of its keys
@@ -602,7 +603,7 @@ constexpr int RTILE = WG * RITEMS;
 constexpr int RWAVE = 64 * RITEMS;
 
 __device__ __forceinline__ void radix_chunk(uint64_t n, uint64_t &start, uint64_t &end) {
-    uint64_t ch = (n + RADIX_BLOCKS - 1) / RADIX_BLOCKS;
+    uint64_t ch = (n + gridDim.x - 1) / gridDim.x;
     ch = (ch + RTILE - 1) / RTILE * RTILE;
     if (ch == 0) ch = RTILE;
     start = (uint64_t)blockIdx.x * ch;
@@ -637,17 +638,20 @@ __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ 
         }
     }
     __syncthreads();
-    hist[(size_t)t * RADIX_BLOCKS + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+    hist[(size_t)t * gridDim.x + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
-// One block per digit: exclusive scan of that digit's RADIX_BLOCKS counts.
-__global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t *__restrict__ dtot) {
+// One block per digit: exclusive scan of that digit's nblk counts (one per
+// block of the histogram pass, nblk <= RADIX_BLOCKS).
+__global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t *__restrict__ dtot,
+                                                   int nblk) {
     constexpr int PER = RADIX_BLOCKS / WG;
-    uint32_t *row = hist + (size_t)blockIdx.x * RADIX_BLOCKS;
+    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
     uint32_t v[PER];
     uint32_t s = 0;
     for (int k = 0; k < PER; ++k) {
-        v[k] = row[threadIdx.x * PER + k];
+        const int i = (int)threadIdx.x * PER + k;
+        v[k] = i < nblk ? row[i] : 0u;
         s += v[k];
     }
     __shared__ uint32_t buf[WG];
@@ -661,7 +665,8 @@ __global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, 
     }
     uint32_t run = buf[threadIdx.x] - s;
     for (int k = 0; k < PER; ++k) {
-        row[threadIdx.x * PER + k] = run;
+        const int i = (int)threadIdx.x * PER + k;
+        if (i < nblk) row[i] = run;
         run += v[k];
     }
     if (threadIdx.x == WG - 1) dtot[blockIdx.x] = buf[WG - 1];
@@ -704,7 +709,7 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
     {   // digit bases: exclusive scan of the digit totals plus this block's offset
         const uint32_t d = dtot[t];
         const uint32_t ex = block_excl_scan(d, wtot);
-        run[t] = ex + hist[(size_t)t * RADIX_BLOCKS + blockIdx.x];
+        run[t] = ex + hist[(size_t)t * gridDim.x + blockIdx.x];
         if (n_kept && blockIdx.x == 0 && t == RADIX - 1) *n_kept = ex + d;
     }
     uint64_t start, end;
@@ -1059,8 +1064,12 @@ size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / S
 // in (k0, v0), 1 if it is in (k1, v1).  With iota set, the input values are
 // the indices 0..n-1 and v0 is only used as a buffer.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
-                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept) {
+                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
+                      uint64_t n_cap) {
     int cur = 0;
+    // about one tile of pairs per block at the capacity: fewer, fuller blocks
+    // than a fixed grid when the sort is short
+    const int nblk = (int)std::min<uint64_t>(std::max<uint64_t>((n_cap + RTILE - 1) / RTILE, 256), RADIX_BLOCKS);
     const uint32_t *vin = iota ? nullptr : v0;
     // digits of equal width (at most RADIX_BITS): a narrow last digit would
     // pile the whole histogram onto a few counters
@@ -1072,9 +1081,9 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         // the first pass drops the `drop` keys; later passes sort the kept ones
         const uint32_t dk = p == 0 ? drop : DEAD_KEY;
         uint32_t *kept = p == 0 && drop != DEAD_KEY ? n_kept : nullptr;
-        hipLaunchKernelGGL(k_radix_hist, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, n_dev, shift, nb, dk, hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(RADIX_BLOCKS), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, dk,
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(WG), 0, s, ki, n_dev, shift, nb, dk, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot, nblk);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, dk,
                            hist, dtot, kept);
         if (kept) n_dev = kept;
         cur ^= 1;

@@ -386,7 +386,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     int dres;
     {
         StageScope sc(ctx, ST_SORT_DEPTH, s);
-        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s);
+        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R);
     }
     const uint32_t *sval = dres ? v1 : v0;
     {
@@ -402,7 +402,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
         // tile ids 0..tiles - 1; the first pass drops the dead instances (tile
         // id `tiles`) and leaves the live count in M_live
         tres = launch_radix_sort(ik0, iv0, ik1, iv1, &st->M_eff, bits_for((uint64_t)tiles), false, hist, dtot, s,
-                                 (uint32_t)tiles, &st->M_live);
+                                 (uint32_t)tiles, &st->M_live, M);
     }
     const uint32_t *skey = tres ? ik1 : ik0;
     {

@@ -73,10 +73,11 @@ void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint6
 // LSD radix sort of (key, value) pairs on the low `bits` bits; returns 1 when
 // the result is in (k1, v1).  drop (DEAD_KEY: none): pairs whose tile field
 // equals it are removed by the first pass, which writes the kept count to
-// *n_kept for the rest of the sort.
+// *n_kept for the rest of the sort.  n_cap: the most pairs *n_dev can hold
+// (sizes the grid).
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
-                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop = DEAD_KEY,
-                      uint32_t *n_kept = nullptr);
+                      bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
+                      uint64_t n_cap);
 void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s);
