@@ -142,6 +142,94 @@ def serving_bench(ctx, w, dsc, gamma, L, log, n_requests=96):
     return out
 
 
+def batched_bench(ctx, uprm, timed, log):
+    """Batched workload at full size: 1M Gaussians in two rooms, VF build over
+    300 training views 1280x720 (50 views per pass), and 256 candidates of
+    mixed 160x120 / 320x240 / 640x480 queried one call per view, in one call
+    and as one graph replay."""
+    import torch
+    from paper_2605_30342_amd import _lib, scenes
+    from paper_2605_30342_amd.api import DeviceScene
+    t0 = time.time()
+    w = scenes.workload("batched")
+    L = w.sh_degree
+    d = DeviceScene(w.scene)
+    vp = _lib.default_vf_params(sh_degree=L, kappa=w.kappa, views_per_pass=50)
+    wsb = ctx.build_workspace(d, w.train, vp)
+    g = torch.empty(((L + 1) ** 2, w.scene.n), dtype=torch.float32, device="cuda")
+    build_ms = timed(lambda: ctx.vf_build(d, w.train, L, vp, wsb, g), reps=2)
+    wsq = ctx.query_workspace(d, w.cand, uprm, L)
+    sc = torch.empty(w.cand.n, dtype=torch.float32, device="cuda")
+    q_ms = timed(lambda: ctx.vf_query_views(d, g, L, w.train.n, w.cand, uprm, wsq, scores=sc))
+    gprm = _lib.default_uq_params(use_graph=1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g_ms = timed(lambda: ctx.vf_query_views(d, g, L, w.train.n, w.cand, gprm, wsq, scores=sc))
+    torch.cuda.synchronize()
+    singles = [w.cand.subset([v]) for v in range(w.cand.n)]
+    one = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def plain():
+        for c in singles:
+            ctx.vf_query_views(d, g, L, w.train.n, c, uprm, wsq, scores=one)
+    p_ms = timed(plain, reps=2)
+    st, _ = ctx.check_workspace(wsq)
+    assert st == 0, "batched workload: query workspace overflow"
+    px = w.cand.pixels()
+    out = {"workload": f"batched: {w.scene.n} Gaussians, {w.train.n} training views 1280x720, {w.cand.n} "
+                       f"candidates of mixed 160x120/320x240/640x480 ({px} px), SH degree {L}",
+           "vf_build_ms": round(build_ms, 3), "query_ms": round(q_ms, 4), "mpix_s": round(px / (q_ms / 1e3) / 1e6, 3),
+           "graph_replay_ms": round(g_ms, 4), "plain_per_view_ms": round(p_ms, 4),
+           "speedup_batched_vs_plain": round(p_ms / q_ms, 3), "speedup_graph_vs_plain": round(p_ms / g_ms, 3)}
+    log(f"batched workload {out} (setup and runs {time.time() - t0:.1f}s)")
+    del wsb, wsq, g, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_bench(ctx, uprm, timed, log):
+    """Precision workload at full size: 3M Gaussians (Morton ordered) in a 2x2
+    grid of rooms, field built in FP32 from 300 training views 640x480, then
+    512 candidates 320x240 queried with the scene and field stored in FP32,
+    FP16 and BF16 (FP32 arithmetic, FP32 depth keys and 2D inversion)."""
+    import torch
+    from paper_2605_30342_amd import _lib, scenes
+    from paper_2605_30342_amd.api import DeviceScene
+    t0 = time.time()
+    w = scenes.workload("precision")
+    L = w.sh_degree
+    d32 = DeviceScene(w.scene)
+    vp = _lib.default_vf_params(sh_degree=L, kappa=w.kappa, views_per_pass=100)
+    wsb = ctx.build_workspace(d32, w.train, vp)
+    g32 = ctx.vf_build(d32, w.train, L, vp, wsb)
+    del wsb
+    px = w.cand.pixels()
+    out = {"workload": f"precision: {w.scene.n} Gaussians, {w.train.n} training views 640x480, {w.cand.n} "
+                       f"candidates 320x240 ({px} px), SH degree {L}"}
+    ws = ctx.query_workspace(d32, w.cand, uprm, L)
+    s32 = torch.empty(w.cand.n, dtype=torch.float32, device="cuda")
+    t32 = timed(lambda: ctx.vf_query_views(d32, g32, L, w.train.n, w.cand, uprm, ws, scores=s32))
+    out["f32"] = {"query_ms": round(t32, 4), "mpix_s": round(px / (t32 / 1e3) / 1e6, 3),
+                  "scene_bytes": d32.nbytes() + g32.numel() * 4}
+    for dt in ("f16", "bf16"):
+        dh = DeviceScene(w.scene, dtype=dt)
+        gh = g32.to(torch.float16 if dt == "f16" else torch.bfloat16)
+        wsh = ctx.query_workspace(dh, w.cand, uprm, L)
+        sh = torch.empty_like(s32)
+        t_ms = timed(lambda: ctx.vf_query_views(dh, gh, L, w.train.n, w.cand, uprm, wsh, scores=sh))
+        torch.cuda.synchronize()
+        rel = ((sh.double() - s32.double()).abs() / s32.double().abs())
+        out[dt] = {"query_ms": round(t_ms, 4), "mpix_s": round(px / (t_ms / 1e3) / 1e6, 3),
+                   "max_rel_score_diff_vs_f32": float(rel.max().item()),
+                   "median_rel_score_diff_vs_f32": float(rel.median().item()),
+                   "scene_bytes": dh.nbytes() + gh.numel() * gh.element_size()}
+        del dh, gh, wsh
+    log(f"precision workload {out} (setup and runs {time.time() - t0:.1f}s)")
+    del ws, g32, d32
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +241,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-visibility validation mode")
     ap.add_argument("--no-color", action="store_true", help="skip the per-Gaussian colour covariance query")
+    ap.add_argument("--no-configs", action="store_true", help="skip the batched and precision workloads")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default blend batch sizes instead of tuning them on this workload")
     ap.add_argument("--profile-only", action="store_true",
@@ -340,33 +429,12 @@ def main():
                 "speedup_graph_vs_plain": round(plain_ms / graph_ms, 3)}
     log(f"batching {batching}")
 
-    # precision: attributes and gamma stored in FP16 / BF16, FP32 arithmetic
-    # (the scene is Morton-ordered so that each 256-Gaussian anchor block is compact)
-    precision = {}
-    order = scenes.morton_order(w.scene)
-    sm = scenes.subset_scene(w.scene, order)
-    dm = DeviceScene(sm)
-    gm = gamma[:, torch.from_numpy(order).cuda()].contiguous()
-    wsm = ctx.query_workspace(dm, w.cand, uprm, L)
-    s32 = torch.empty_like(scores)
-    t32 = timed(lambda: ctx.vf_query_views(dm, gm, L, w.train.n, w.cand, uprm, wsm, scores=s32))
-    precision["f32"] = {"query_ms": round(t32, 4), "mpix_s": round(px / (t32 / 1e3) / 1e6, 3),
-                        "scene_bytes": dm.nbytes() + gm.numel() * 4}
-    for dt in ("f16", "bf16"):
-        dh = DeviceScene(sm, dtype=dt)
-        gh = gm.to(torch.float16 if dt == "f16" else torch.bfloat16)
-        wsh = ctx.query_workspace(dh, w.cand, uprm, L)
-        sh = torch.empty_like(scores)
-        t_ms = timed(lambda: ctx.vf_query_views(dh, gh, L, w.train.n, w.cand, uprm, wsh, scores=sh))
-        torch.cuda.synchronize()
-        rel = ((sh.double() - s32.double()).abs() / s32.double().abs())
-        precision[dt] = {"query_ms": round(t_ms, 4), "mpix_s": round(px / (t_ms / 1e3) / 1e6, 3),
-                         "max_rel_score_diff_vs_f32": float(rel.max().item()),
-                         "median_rel_score_diff_vs_f32": float(rel.median().item()),
-                         "scene_bytes": dh.nbytes() + gh.numel() * gh.element_size()}
-        del dh, gh, wsh
-    del dm, gm, wsm
-    log(f"precision {precision}")
+    # the batched and precision workloads at full size (the launch
+    # configurations of those workloads; figures reported beside the room line)
+    batched_cfg = precision = None
+    if not args.no_configs:
+        batched_cfg = batched_bench(ctx, uprm, timed, log)
+        precision = precision_bench(ctx, uprm, timed, log)
 
     # validation mode: the exact multi-view visibility (O(|P|) per record) in
     # place of the field's AM-GM query, and the score gap between the two
@@ -473,6 +541,7 @@ def main():
         "roofline": roof,
         "raster_uq_roofline": uq_frac,
         "batching": batching,
+        "batched_workload": batched_cfg,
         "precision": precision,
         "serving": serving,
         "exact_validation": exact,
