@@ -295,7 +295,9 @@ __device__ __forceinline__ float log_one_minus(float a) {
 // covariance is Q_k(d) = sum_j Y_j(d)^2 cvar[(k Kc + j) n + g] (the colour is
 // linear in its SH coefficients, whose variances cvar holds), floored at
 // 1e-30; 3/2 log(2 pi e) alone for a Gaussian at the camera centre.
-template <typename TG, typename TGam, int MODE, int L>
+// EXTRA: the colour constants and depths above are requested (compiled out
+// otherwise, so that the plain query keeps its scalar registers).
+template <typename TG, typename TGam, int MODE, int L, bool EXTRA>
 __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                                 float znear, float lowpass, float cut,
                                                 const uint32_t *__restrict__ offs, const uint32_t *__restrict__ vmask,
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                         }
                     }
                     R.v = vis;
-                    if constexpr (MODE != 0) {
+                    if constexpr (MODE != 0 && EXTRA) {
                         if (cvar) {
                             float cc = c3;
                             float dx = m[0] - V.C[0], dy = m[1] - V.C[1], dz = m[2] - V.C[2];
@@ -1004,16 +1006,25 @@ static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, 
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
         q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr
-    if constexpr (MODE != 1) {   // no SH evaluation
-        hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
+    const bool extra = q.color_var || q.rz;
+#define GV_PROJECT_LAUNCH(LL) \
+    do { \
+        if (extra) hipLaunchKernelGGL((k_project<TG, TGam, MODE, LL, true>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); \
+        else hipLaunchKernelGGL((k_project<TG, TGam, MODE, LL, false>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); \
+    } while (0)
+    if constexpr (MODE == 0) {   // the build: no SH evaluation, no side outputs
+        hipLaunchKernelGGL((k_project<TG, TGam, 0, 0, false>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS);
+    } else if constexpr (MODE == 2) {
+        GV_PROJECT_LAUNCH(0);
     } else {
         switch (L) {
-        case 0: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 0>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
-        case 1: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 1>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
-        case 2: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 2>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
-        default: hipLaunchKernelGGL((k_project<TG, TGam, MODE, 3>), dim3(grid), dim3(WG), 0, s, GV_PROJECT_ARGS); break;
+        case 0: GV_PROJECT_LAUNCH(0); break;
+        case 1: GV_PROJECT_LAUNCH(1); break;
+        case 2: GV_PROJECT_LAUNCH(2); break;
+        default: GV_PROJECT_LAUNCH(3); break;
         }
     }
+#undef GV_PROJECT_LAUNCH
 #undef GV_PROJECT_ARGS
 }
 
