@@ -799,7 +799,7 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
             StageScope sc(ctx, ST_RASTER_UQ, s);
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
-                             bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
+                             bz.ival, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
                              prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);

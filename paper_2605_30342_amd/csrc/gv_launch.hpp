@@ -96,7 +96,7 @@ void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint
 // dmaps: per-record depths and the expected-depth maps (both NULL: none;
 // depth maps need maps)
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                      const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
                       hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,

@@ -357,7 +357,7 @@ __device__ __forceinline__ void subblock_pixel(int t, int &qx, int &qy) {
 template <int RB, bool MAPS, bool COUNT, bool CC, bool DEPTH>
 __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
+                                                  const uint32_t *__restrict__ ival,
                                                   const Rec *__restrict__ rec, const float *__restrict__ rcc,
                                                   const float *__restrict__ rz,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
@@ -793,10 +793,10 @@ void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint
 
 template <int RB, bool CC, bool DEPTH>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                         const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                         const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
-#define GV_UQ_ARGS views, nv, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs
+#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs
     if constexpr (DEPTH) {   // depth maps come with the entropy maps
         if (pairs)
             hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true>), g, b, 0, s, GV_UQ_ARGS);
@@ -817,9 +817,9 @@ static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const ui
 
 template <int RB>
 static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                          const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                          const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                           float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
     const bool depth = dmaps && maps && rz;
     if (rcc && depth) raster_uq_rb<RB, true, true>(GV_UQ_ARGS);
     else if (rcc) raster_uq_rb<RB, true, false>(GV_UQ_ARGS);
@@ -829,11 +829,11 @@ static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const u
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                      const uint32_t *ikey, const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
+                      const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
                       hipStream_t s) {
     if (total_tiles <= 0) return;
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
     switch (batch) {
     case 64: raster_uq_var<64>(GV_UQ_ARGS); break;
     case 256: raster_uq_var<256>(GV_UQ_ARGS); break;
