@@ -203,12 +203,15 @@ struct EllipseBands {
 
 __device__ __forceinline__ float band_threshold(float qcut) { return fmaf(qcut, 1.001f, 0.01f); }
 
+// The hardware reciprocal, square root and reciprocal square root (1 ulp)
+// are used here and in the band tests below: their error is far inside the
+// widening of the threshold and of the x-extent.
 __device__ __forceinline__ EllipseBands ellipse_bands(float a, float b, float c, float sq) {
     EllipseBands E;
-    E.ia = 1.0f / a;
+    E.ia = __builtin_amdgcn_rcpf(a);
     E.kx = b * E.ia;
-    const float ic = 1.0f / c, bc = b * ic;
-    E.eyR = sq * bc * ic / sqrtf(fmaf(bc, bc, 1.0f));
+    const float ic = __builtin_amdgcn_rcpf(c), bc = b * ic;
+    E.eyR = sq * bc * ic * __builtin_amdgcn_rsqf(fmaf(bc, bc, 1.0f));
     E.hy = sq * ic;
     return E;
 }
@@ -222,7 +225,8 @@ __device__ __forceinline__ uint32_t quadrant_mask_bands(float ux, float uy, floa
         const float lo = fmaxf(uy - (8.0f * j + 7.5f), -hy), hi = fminf(uy - (8.0f * j + 0.5f), hy);
         const float eR = __builtin_amdgcn_fmed3f(eyR, lo, hi), eL = __builtin_amdgcn_fmed3f(-eyR, lo, hi);
         const float tR = c * eR, tL = c * eL;
-        const float sR = sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f)), sL = sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
+        const float sR = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f));
+        const float sL = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
         const float xmax = fmaf(sR, ia, fmaf(kx, eR, ux)) + mg;
         const float xmin = fmaf(-sL, ia, fmaf(kx, eL, ux)) - mg;
 #pragma unroll
@@ -247,7 +251,8 @@ __device__ __forceinline__ uint32_t subblock_mask_bands(float ux, float uy, floa
         const float lo = fmaxf(uy - (4.0f * j + 3.5f), -hy), hi = fminf(uy - (4.0f * j + 0.5f), hy);
         const float eR = __builtin_amdgcn_fmed3f(eyR, lo, hi), eL = __builtin_amdgcn_fmed3f(-eyR, lo, hi);
         const float tR = c * eR, tL = c * eL;
-        const float sR = sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f)), sL = sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
+        const float sR = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f));
+        const float sL = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
         const float xmax = fmaf(sR, ia, fmaf(kx, eR, ux)) + mg;
         const float xmin = fmaf(-sL, ia, fmaf(kx, eL, ux)) - mg;
 #pragma unroll
