@@ -89,13 +89,15 @@ __device__ __forceinline__ bool cons_visible(const float m[3], float smax, const
     if (pz < znear + mg) return true;
     const float px = V.R[0] * m[0] + V.R[1] * m[1] + V.R[2] * m[2] + V.t[0];
     const float py = V.R[3] * m[0] + V.R[4] * m[1] + V.R[5] * m[2] + V.t[1];
-    const float iz = 1.0f / pz;
+    // hardware reciprocal and square roots: their 1-ulp error is far inside
+    // the test's margins
+    const float iz = __builtin_amdgcn_rcpf(pz);
     const float ax = px * iz, ay = py * iz;
     const float s2 = smax * smax;
     const float wx2 = V.fx * V.fx * iz * iz * (1.0f + ax * ax);
     const float wy2 = V.fy * V.fy * iz * iz * (1.0f + ay * ay);
-    const float rx = sqrtf(cut * (wx2 * s2 + lowpass)) * 1.01f + 2.0f;
-    const float ry = sqrtf(cut * (wy2 * s2 + lowpass)) * 1.01f + 2.0f;
+    const float rx = __builtin_amdgcn_sqrtf(cut * (wx2 * s2 + lowpass)) * 1.01f + 2.0f;
+    const float ry = __builtin_amdgcn_sqrtf(cut * (wy2 * s2 + lowpass)) * 1.01f + 2.0f;
     const float ux = V.fx * ax + V.cx, uy = V.fy * ay + V.cy;
     const float slx = 1e-4f * (fabsf(ux) + V.fx * fabsf(ax) + 1.0f);
     const float sly = 1e-4f * (fabsf(uy) + V.fy * fabsf(ay) + 1.0f);
