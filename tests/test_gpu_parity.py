@@ -524,10 +524,10 @@ def test_half_gamma_output_of_build(ctx, tiny):
 # ---------------------------------------------------------------- serving
 
 def test_serving_results_alone_equal_results_in_the_mix(ctx):
-    """Requests of three resident scenes with mixed view counts and
-    resolutions, served with continuous batching on concurrent streams under
-    a memory budget: every request's scores equal the scores of the same
-    request run alone."""
+    """Requests of three resident scenes (one stored in BF16 with a BF16
+    field) with mixed view counts and resolutions, served with continuous
+    batching on concurrent streams under a memory budget: every request's
+    scores equal the scores of the same request run alone."""
     say("case: continuous-batching server, alone vs mix")
     import torch
     from paper_2605_30342_amd import _lib
@@ -538,8 +538,9 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
     for k in range(3):
         sc = scenes.tiny_scene(1500 + 500 * k, seed=50 + k)
         train = scenes.sphere_cameras(6, 60 + k, width=96, height=96)
-        dsc = DeviceScene(sc)
-        g = ctx.vf_build(dsc, train, 2)
+        dt = "bf16" if k == 2 else "f32"
+        dsc = DeviceScene(sc, dtype=dt)
+        g = ctx.vf_build(dsc, train, 2, gamma_dtype=dt)
         be.add_scene(k, dsc, g, 2, train.n)
     reqs = []
     for i in range(14):
