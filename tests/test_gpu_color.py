@@ -25,13 +25,15 @@ def tiny_gamma(tiny):
     return b["gamma"].astype(np.float32).astype(np.float64)
 
 
-def _gpu_color(ctx, dsc, gamma_nk, L, n_train, var, cams, use_graph=0):
+def _gpu_color(ctx, dsc, gamma_nk, L, n_train, var, cams, use_graph=0, gamma_dtype=None):
     import torch
     from paper_2605_30342_amd import _lib
     prm = _lib.default_uq_params()
     prm.use_graph = use_graph
     ws = ctx.query_workspace(dsc, cams, prm, L)
     g = torch.from_numpy(np.ascontiguousarray(np.asarray(gamma_nk, np.float32).T)).cuda()
+    if gamma_dtype is not None:
+        g = g.to(gamma_dtype)
     cv = torch.from_numpy(np.ascontiguousarray(var, np.float32)).cuda()
     scores, mp = ctx.vf_query_views_color(dsc, g, L, n_train, cv, cams, prm, ws, want_maps=True)
     st, counts = ctx.check_workspace(ws)
@@ -77,3 +79,29 @@ def test_color_query_graph_replay_equals_eager(ctx, tiny, tiny_gamma):
     for _ in range(3):
         s1, m1 = _gpu_color(ctx, dsc, tiny_gamma, 2, tiny.train.n, var, tiny.cand, use_graph=1)
         assert np.array_equal(m0, m1) and np.array_equal(s0, s1)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_color_query_half_storage(ctx, dtype):
+    """Colour covariance with the scene and the field stored in FP16 / BF16:
+    equal to the oracle on the same dequantised attributes and field."""
+    say(f"case: vf_query_views_color with {dtype} storage")
+    import torch
+    from paper_2605_30342_amd.api import DeviceScene
+    from tests.test_gpu_parity import _dequantised
+    w = scenes.workload("room", scale=0.05)
+    sc = scenes.subset_scene(w.scene, scenes.morton_order(w.scene))
+    deq = _dequantised(sc, dtype)
+    prm = oracle_params()
+    train = w.train.subset([0, 3])
+    cand = w.cand.subset([0, 1])
+    b = oracle.vf_build(deq, train, 3, prm)
+    td = torch.float16 if dtype == "f16" else torch.bfloat16
+    gh = torch.from_numpy(b["gamma"].astype(np.float32)).to(td).float().numpy().astype(np.float64)
+    var = scenes.color_sh_variances(sc.n, 3, 7300)
+    q = oracle.vf_query_color(deq, gh, 3, train.n, var.astype(np.float64), 3, cand, prm)
+    s, mp = _gpu_color(ctx, DeviceScene(sc, dtype=dtype), gh, 3, train.n, var, cand, gamma_dtype=td)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(s, q, mp)

@@ -187,3 +187,27 @@ def test_extension_arguments_are_rejected(ctx, tiny):
                                    tiny.cand.n, ctypes.byref(bad), ctypes.c_void_p(scores.data_ptr()), None,
                                    ctypes.byref(ws.plan), ctypes.c_void_p(ws.buf.data_ptr()), None))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_exact_query_half_storage(ctx, dtype):
+    """The exact mode on half-stored attributes equals the oracle run on the
+    same dequantised values (the per-view visibilities come from the oracle
+    on those values too)."""
+    say(f"case: vf_query_views_exact with {dtype} storage")
+    from paper_2605_30342_amd.api import DeviceScene
+    from tests.test_gpu_parity import _dequantised
+    w = scenes.workload("room", scale=0.05)
+    sc = scenes.subset_scene(w.scene, scenes.morton_order(w.scene))
+    deq = _dequantised(sc, dtype)
+    prm = oracle_params()
+    train = w.train.subset([0, 2, 4])
+    cand = w.cand.subset([0, 1])
+    b = oracle.vf_build(deq, train, 0, prm, want_views=True)
+    vt = b["vview"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query_exact(deq, vt, train, prm.kappa, cand, prm)
+    s, mp = _gpu_exact(ctx, DeviceScene(sc, dtype=dtype), vt, oracle.camera_centres(train), prm.kappa, cand)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(s, q, mp)
