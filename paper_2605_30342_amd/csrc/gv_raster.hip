@@ -111,43 +111,31 @@ constexpr int LGROUP = 16;
 // reads of one pass fall in different banks.
 constexpr int SCR_STRIDE = 68;
 
-// Positions of this thread's record in the four per-quadrant lists, each in
-// batch (= depth) order; -1 where the record does not touch the quadrant.
-// Also publishes the list lengths in slen[].  Two barriers.
-__device__ __forceinline__ void list_positions(uint32_t mask, int pos[WAVES], int *scnt, int *slen) {
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    uint32_t pre[WAVES];
-#pragma unroll
-    for (int q = 0; q < WAVES; ++q) {
-        const unsigned long long bal = __builtin_amdgcn_ballot_w64(((mask >> q) & 1u) != 0u);
-        pre[q] = lanes_below(bal);
-        if (lane == 0) scnt[w * WAVES + q] = (int)__popcll(bal);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < WAVES; ++q) {
-        int off = 0;
-        for (int ww = 0; ww < w; ++ww) off += scnt[ww * WAVES + q];
-        pos[q] = ((mask >> q) & 1u) ? off + (int)pre[q] : -1;
-    }
-    if (t < WAVES) {
-        int n = 0;
-        for (int ww = 0; ww < WAVES; ++ww) n += scnt[ww * WAVES + t];
-        slen[t] = n;
-    }
-    __syncthreads();
+// Wave-level counts of one batch go through LDS in [list][wave] order, so
+// that a list's four counts are one 16-byte read.  With the counts, each
+// wave also posts whether any of its pixels is still live; both are read
+// back after the batch's first barrier.
+template <int NLISTS>
+struct BatchCounts {
+    int4 cnt[NLISTS];   // .x .. .w: records of waves 0 .. 3 in the list
+    int4 live;          // .x .. .w: wave 0 .. 3 still has a live pixel
+};
+
+// Records of waves below w in a list, from the list's four wave counts (w uniform).
+__device__ __forceinline__ int waves_below(const int4 c, int w) {
+    return (w > 0 ? c.x : 0) + (w > 1 ? c.y : 0) + (w > 2 ? c.z : 0);
 }
+
+__device__ __forceinline__ int list_total(const int4 c) { return (c.x + c.y) + (c.z + c.w); }
 
 // Lists are padded with never-hit entries to a multiple of LPAD; a list is
 // consumed in groups of LGROUP entries and, for its last 1..LPAD entries, one
-// group of LPAD.  Index of the pad slot thread t fills, or -1 (threads
-// 0 .. 4 LPAD - 1 pad the four lists).
+// group of LPAD.  Index of the pad slot thread t fills in list q (q = t / LPAD),
+// or -1 (threads 0 .. 4 LPAD - 1 pad the four lists); n = length of list q.
 constexpr int LPAD = LGROUP / 2;
-__device__ __forceinline__ int pad_slot(const int *slen, int &q) {
+__device__ __forceinline__ int pad_slot(int n) {
     const int t = threadIdx.x;
-    q = t / LPAD;
     if (t >= WAVES * LPAD) return -1;
-    const int n = slen[q];
     const int k = n + (t % LPAD);
     return k < ((n + LPAD - 1) / LPAD) * LPAD ? k : -1;
 }
@@ -170,8 +158,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     __shared__ uint16_t wS[WAVES][LCAP];   // batch slot of the entry
     // per batch slot (two batches: a batch is flushed while the next one blends)
     __shared__ uint32_t sR[2 * RB];        // record index
-    __shared__ int scnt[WAVES * WAVES];
-    __shared__ int slen[WAVES];
+    __shared__ BatchCounts<WAVES> bc;      // per quadrant list: counts of the four waves
     __shared__ float part[2 * RB];         // sum of T over the tile's hit pixels
     __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
     __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
@@ -220,8 +207,12 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     };
     int cur = 0;
     uint32_t blast = rg.y;   // start of the last blended batch (none yet)
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
-        if (__syncthreads_count(T >= eps_T) == 0) break;
+        // Two barriers per batch.  Before the first: registers, this batch's
+        // slot buffers (sR, part, cpart: the previous batch uses the other
+        // half) and the wave counts.  Between the two: the lists, which the
+        // previous batch's blend has finished reading at the first barrier.
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
         const uint32_t r = r1, kq = k1;
@@ -243,28 +234,47 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             part[cur * RB + t] = 0.0f;
             cpart[cur * RB + t] = 0u;
         }
-        int pos[WAVES];
-        list_positions(mask, pos, scnt, slen);
+        uint32_t pre[WAVES];
 #pragma unroll
         for (int q = 0; q < WAVES; ++q) {
-            if (pos[q] >= 0) {
-                wA[q][pos[q]] = make_float4(ux, uy, R.l11, R.l21);
-                wB[q][pos[q]] = make_float2(R.l22, R.o);
-                wS[q][pos[q]] = (uint16_t)(cur * RB + t);
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((mask >> q) & 1u) != 0u);
+            pre[q] = lanes_below(bal);
+            if (lane == 0) (&bc.cnt[q].x)[wu] = (int)__popcll(bal);
+        }
+        {
+            const bool alive = __builtin_amdgcn_ballot_w64(T >= eps_T) != 0ull;
+            if (lane == 0) (&bc.live.x)[wu] = alive ? 1 : 0;
+        }
+        __syncthreads();
+        {
+            const int4 a = bc.live;
+            if ((a.x | a.y | a.z | a.w) == 0) break;   // every pixel of the tile has terminated
+        }
+        // entries in batch (= depth) order: records of the lower waves first
+        int nq[WAVES];
+#pragma unroll
+        for (int q = 0; q < WAVES; ++q) {
+            const int4 c = bc.cnt[q];
+            nq[q] = list_total(c);
+            if ((mask >> q) & 1u) {
+                const int pos = waves_below(c, wu) + (int)pre[q];
+                wA[q][pos] = make_float4(ux, uy, R.l11, R.l21);
+                wB[q][pos] = make_float2(R.l22, R.o);
+                wS[q][pos] = (uint16_t)(cur * RB + t);
             }
         }
         {
-            int q;
-            const int k = pad_slot(slen, q);
+            const int q = (t / LPAD) & (WAVES - 1);
+            const int k = pad_slot(q == 0 ? nq[0] : q == 1 ? nq[1] : q == 2 ? nq[2] : nq[3]);
             if (k >= 0) {
                 wA[q][k] = make_float4(1e18f, 1e18f, 1.0f, 0.0f);
                 wB[q][k] = make_float2(1.0f, 0.0f);
                 wS[q][k] = 0;
             }
         }
+        const int len = wu == 0 ? nq[0] : wu == 1 ? nq[1] : wu == 2 ? nq[2] : nq[3];
         __syncthreads();
         if (blast != rg.y) flush(cur ^ 1, blast);
-        const int len = __builtin_amdgcn_readfirstlane(slen[w]);
         const int jl = lane & (LGROUP - 1);
         // one group of G entries (G = LGROUP, or LPAD for the last few)
         auto group = [&](int i0, auto gs) {
@@ -368,8 +378,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     __shared__ float wC[CC ? RB + 1 : 1];        // c_c of the record
     __shared__ float wD[DEPTH ? RB + 1 : 1];     // depth of the record
     __shared__ uint16_t idx[NL][RB];       // per sub-block: slots in batch (= depth) order
-    __shared__ int scnt[WAVES][NL];
-    __shared__ int slen[NL];
+    __shared__ BatchCounts<NL> bc;         // per sub-block list: counts of the four waves
     __shared__ float red[WAVES];
 
     const int gt = blockIdx.x;
@@ -413,8 +422,11 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
         if (DEPTH) Z1 = rz[r1];
     }
 
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     for (uint32_t b = rg.x; b < rg.y; b += RB) {
-        if (__syncthreads_count(T >= u.eps_T) == 0) break;
+        // Two barriers per batch: registers and wave counts before the first;
+        // the staged records and the lists (which the previous batch's blend
+        // has finished reading at the first barrier) between the two.
         const bool have = loader && b + t < rg.y;
         const Rec R = R1;
         const float Cr = C1, Zr = Z1;
@@ -425,45 +437,46 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
             if (DEPTH) Z1 = rz[r1];
         }
         if (loader && b + 2 * RB + t < rg.y) r2 = ival[b + 2 * RB + t];
-        // stage the record in its slot and find the sub-blocks it reaches
+        // the sub-blocks the record reaches
         uint32_t smask = 0u;
+        float ux = 0.0f, uy = 0.0f;
         if (have) {
-            float ux, uy;
             local_centre(R, ox, oy, ux, uy);
+            const EllipseBands E = ellipse_bands(R.l11, R.l21, R.l22, sqb);
+            smask = subblock_mask_bands(ux, uy, E.kx, E.ia, R.l22, E.eyR, E.hy, qcb);
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((smask >> l) & 1u) != 0u);
+            if (lane == 0) (&bc.cnt[l].x)[wu] = (int)__popcll(bal);
+        }
+        {
+            const bool alive = __builtin_amdgcn_ballot_w64(T >= u.eps_T) != 0ull;
+            if (lane == 0) (&bc.live.x)[wu] = alive ? 1 : 0;
+        }
+        __syncthreads();
+        {
+            const int4 a = bc.live;
+            if ((a.x | a.y | a.z | a.w) == 0) break;   // every pixel of the tile has terminated
+        }
+        // stage the record in its slot; slot lists in batch (= depth) order,
+        // records of the lower waves first
+        if (have) {
             const float v = R.v;
             wA[t] = make_float4(ux, uy, R.l11, R.l21);
             wB[t] = make_float4(R.l22, R.o * fmaf(u.beta, 1.0f - v, v), ob * (1.0f - v), v);
             if (CC) wC[t] = Cr;
             if (DEPTH) wD[t] = Zr;
-            const EllipseBands E = ellipse_bands(R.l11, R.l21, R.l22, sqb);
-            smask = subblock_mask_bands(ux, uy, E.kx, E.ia, R.l22, E.eyR, E.hy, qcb);
         }
-        // slot lists: this wave's counts per list, then offsets across waves
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const unsigned long long bal = __builtin_amdgcn_ballot_w64(((smask >> l) & 1u) != 0u);
-            if (lane == 0) scnt[w][l] = (int)__popcll(bal);
+            if ((smask >> l) & 1u) idx[l][waves_below(bc.cnt[l], wu) + (int)lanes_below(bal)] = (uint16_t)t;
         }
+        const int mylen = list_total(bc.cnt[mylist]);
+        const int len = max(max(list_total(bc.cnt[4 * wu]), list_total(bc.cnt[4 * wu + 1])),
+                            max(list_total(bc.cnt[4 * wu + 2]), list_total(bc.cnt[4 * wu + 3])));
         __syncthreads();
-#pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((smask >> l) & 1u) != 0u);
-            if ((smask >> l) & 1u) {
-                int off = (int)lanes_below(bal);
-                for (int ww = 0; ww < w; ++ww) off += scnt[ww][l];
-                idx[l][off] = (uint16_t)t;
-            }
-        }
-        if (t < NL) {
-            int n = 0;
-#pragma unroll
-            for (int ww = 0; ww < WAVES; ++ww) n += scnt[ww][t];
-            slen[t] = n;
-        }
-        __syncthreads();
-        const int mylen = slen[mylist];
-        const int len = __builtin_amdgcn_readfirstlane(
-            max(max(slen[4 * w], slen[4 * w + 1]), max(slen[4 * w + 2], slen[4 * w + 3])));
         const int jl = lane & (LGROUP - 1);
         // one group of G entries per row (G = LGROUP, or LPAD for the last few)
         auto group = [&](int i0, auto gs) {
