@@ -8,7 +8,7 @@
 namespace gv {
 
 // Raster tile: 16x16 pixels, one 256-thread workgroup (4 waves of 64), one
-// pixel per lane.  Each wave covers a 16x4 strip of the tile.
+// pixel per lane.  Each wave covers an 8x8 quadrant of the tile.
 constexpr int TILE = 16;
 constexpr int TILE_SHIFT = 4;
 constexpr int WG = 256;

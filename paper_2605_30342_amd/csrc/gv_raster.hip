@@ -102,9 +102,8 @@ __device__ __forceinline__ void quadrant_pixel(int t, int &qx, int &qy) {
     qy = ((w >> 1) << 3) + (l >> 3);
 }
 
-// Records staged per batch (RB, a launch-time choice: 64, 128 or 256) and the
-// padding granule of a per-quadrant list (lists are padded with never-hit
-// entries up to a multiple of LGROUP).
+// Records are staged in batches of RB (a launch-time choice: 64, 128 or 256);
+// a wave blends its lists in groups of LGROUP entries.
 constexpr int LGROUP = 16;
 // Row stride (floats) of the per-wave transpose buffer: a multiple of 4 so that
 // 16-byte reads stay aligned, and 4 mod 64 banks so that the four quads'
