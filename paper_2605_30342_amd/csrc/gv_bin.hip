@@ -695,13 +695,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) 
 
 // With drop (see k_radix_hist) the kept pairs are written compacted and their
 // total goes to *n_kept (by one thread of block 0), the count the following
-// passes take.
+// passes take.  With gdst set, gdst[o] = gsrc[value] is also written for
+// every output position o (a per-value word gathered into sorted order).
 __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                       const uint32_t *n_dev, int shift, int nbits, uint32_t drop,
                                                       const uint32_t *__restrict__ hist,
                                                       const uint32_t *__restrict__ dtot,
-                                                      uint32_t *__restrict__ n_kept) {
+                                                      uint32_t *__restrict__ n_kept,
+                                                      const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst) {
     __shared__ uint32_t run[RADIX];          // output position of this block's next pair of each digit
     __shared__ uint32_t wcnt[WAVES][RADIX];  // wave counts, then wave offsets inside the digit
     __shared__ uint32_t lbase[RADIX];        // first slot of each digit in the staged tile
@@ -785,11 +787,21 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
         __syncthreads();
         // ... and write it out: consecutive lanes write consecutive positions of a digit run
         const uint32_t cnt = skept;
-        for (uint32_t j = t; j < cnt; j += WG) {
-            const uint32_t key = sk[j];
-            const uint32_t o = goff[(key >> shift) & mask] + j;
-            kout[o] = key;
-            vout[o] = sv[j];
+        if (gdst) {
+            for (uint32_t j = t; j < cnt; j += WG) {
+                const uint32_t key = sk[j], val = sv[j];
+                const uint32_t o = goff[(key >> shift) & mask] + j;
+                kout[o] = key;
+                vout[o] = val;
+                gdst[o] = gsrc[val];
+            }
+        } else {
+            for (uint32_t j = t; j < cnt; j += WG) {
+                const uint32_t key = sk[j];
+                const uint32_t o = goff[(key >> shift) & mask] + j;
+                kout[o] = key;
+                vout[o] = sv[j];
+            }
         }
         // no barrier here: the next tile writes sk / sv / goff only after its
         // first block-wide barrier, which every thread reaches after this loop
@@ -797,15 +809,6 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
 }
 
 // ---------------------------------------------------------------- binning
-
-// Tile count of every record, in depth order, gathered from the dense
-// per-record counts the projection wrote.
-__global__ __launch_bounds__(WG) void k_gather_ntiles(const uint32_t *__restrict__ sval, const uint32_t *__restrict__ ntr,
-                                                      const uint32_t *n_dev, uint32_t *__restrict__ icnt) {
-    const uint64_t n = *n_dev;
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG)
-        icnt[i] = ntr[sval[i]];
-}
 
 // One (global tile id, record) instance per tile of every record, written in
 // depth order so that a stable sort by tile id keeps depth order in a tile.
@@ -1078,7 +1081,7 @@ size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / S
 // the indices 0..n-1 and v0 is only used as a buffer.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
-                      uint64_t n_cap) {
+                      uint64_t n_cap, const uint32_t *gather_src, uint32_t *gather_dst) {
     int cur = 0;
     // about one tile of pairs per block at the capacity: fewer, fuller blocks
     // than a fixed grid when the sort is short
@@ -1096,8 +1099,9 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         uint32_t *kept = p == 0 && drop != DEAD_KEY ? n_kept : nullptr;
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(WG), 0, s, ki, n_dev, shift, nb, dk, hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot, nblk);
+        const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, dk,
-                           hist, dtot, kept);
+                           hist, dtot, kept, last ? gather_src : nullptr, last ? gather_dst : nullptr);
         if (kept) n_dev = kept;
         cur ^= 1;
         vin = cur ? v1 : v0;
@@ -1106,9 +1110,6 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
     return cur;
 }
 
-void launch_gather_ntiles(const uint32_t *sval, const uint32_t *ntr, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_ntiles, dim3(2048), dim3(WG), 0, s, sval, ntr, n_dev, icnt);
-}
 
 void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
                  uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {

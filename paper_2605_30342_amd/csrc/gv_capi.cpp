@@ -386,12 +386,13 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     int dres;
     {
         StageScope sc(ctx, ST_SORT_DEPTH, s);
-        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R);
+        // the last pass also gathers each record's tile count into depth order
+        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R, ntr,
+                                 icnt);
     }
     const uint32_t *sval = dres ? v1 : v0;
     {
         StageScope sc(ctx, ST_EMIT, s);
-        launch_gather_ntiles(sval, ntr, &st->R_eff, icnt, s);
         launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
         launch_emit(sval, bin, ioff, st, (float)(0.5 * geo.cut / std::log(2.0)), (uint32_t)tiles, ik0, iv0, s);

@@ -74,17 +74,17 @@ void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint6
 // the result is in (k1, v1).  drop (DEAD_KEY: none): pairs whose tile field
 // equals it are removed by the first pass, which writes the kept count to
 // *n_kept for the rest of the sort.  n_cap: the most pairs *n_dev can hold
-// (sizes the grid).
+// (sizes the grid).  gather_dst (optional): the last pass also writes
+// gather_dst[i] = gather_src[sorted value i] for every output position i.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
-                      uint64_t n_cap);
+                      uint64_t n_cap, const uint32_t *gather_src = nullptr, uint32_t *gather_dst = nullptr);
 void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s);
 void launch_vis_finish(int64_t n, float *out, hipStream_t s);
 void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *vmask, int mw, const float *acc_T,
                      const uint32_t *acc_c, const Status *st, float *out, unsigned long long *pairs, hipStream_t s);
-void launch_gather_ntiles(const uint32_t *sval, const uint32_t *ntr, const uint32_t *n_dev, uint32_t *icnt, hipStream_t s);
 void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
                  uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s);

@@ -144,8 +144,9 @@ __device__ __forceinline__ int pad_slot(int n) {
 // Contributions of LGROUP consecutive list entries are kept per lane (acc[])
 // and summed over the wave's 64 pixels with one transpose through LDS,
 // instead of a cross-lane reduction per Gaussian.
+// With RB = 64 the registers and LDS of a workgroup fit six per CU.
 template <int RB>
-__global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
+__global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
                                                    const uint2 *__restrict__ ranges,
                                                    const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
                                                    const Rec *__restrict__ rec,
@@ -156,7 +157,6 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
     __shared__ uint16_t wS[WAVES][LCAP];   // batch slot of the entry
     // per batch slot (two batches: a batch is flushed while the next one blends)
-    __shared__ uint32_t sR[2 * RB];        // record index
     __shared__ BatchCounts<WAVES> bc;      // per quadrant list: counts of the four waves
     __shared__ float part[2 * RB];         // sum of T over the tile's hit pixels
     __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
@@ -190,17 +190,19 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
     }
     if (loader && rg.x + t < rg.y) R1 = rec[r1];
 
-    // Adds a finished batch's per-slot sums to the per-record accumulators.
-    // Done one batch late, in the middle of the next batch, so that the
-    // atomics are long complete when the next record prefetch is waited for.
+    // Adds a finished batch's per-slot sums to the per-record accumulators
+    // (thread t holds slot t: record rlast).  Done one batch late, in the
+    // middle of the next batch, so that the atomics are long complete when
+    // the next record prefetch is waited for.
+    uint32_t rlast = 0;
     auto flush = [&](int buf, uint32_t bstart) {
         const int cnt = (int)min((uint32_t)RB, rg.y - bstart);
         if (t < cnt) {
             const int sl = buf * RB + t;
             const uint32_t c = cpart[sl];
             if (c) {
-                atomicAdd(&acc_T[sR[sl]], part[sl]);
-                atomicAdd(&acc_c[sR[sl]], c);
+                atomicAdd(&acc_T[rlast], part[sl]);
+                atomicAdd(&acc_c[rlast], c);
             }
         }
     };
@@ -225,10 +227,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
         // quadrants of this tile the record's ellipse reaches (from the binning)
         const uint32_t mask = have ? kq >> QMASK_SHIFT : 0u;
         float ux = 0.f, uy = 0.f;
-        if (have) {
-            local_centre(R, ox, oy, ux, uy);
-            sR[cur * RB + t] = r;
-        }
+        if (have) local_centre(R, ox, oy, ux, uy);
         if (t < RB) {
             part[cur * RB + t] = 0.0f;
             cpart[cur * RB + t] = 0u;
@@ -333,6 +332,7 @@ __global__ __launch_bounds__(WG) void k_raster_vis(const ViewDev *__restrict__ v
             else group(i0, std::integral_constant<int, LPAD>{});
         }
         blast = b;
+        rlast = r;
         cur ^= 1;
     }
     __syncthreads();
