@@ -594,15 +594,15 @@ __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ i
 // Each pass sorts (key, value) pairs stably by one digit of up to 8 bits.
 // The n pairs are cut into one contiguous chunk of whole tiles per block (the
 // grid is sized from the capacity so that a block gets about one tile)
-// (RTILE = 2048 pairs).  Block b histograms its chunk; the histograms are
+// (RTILE = 4096 pairs).  Block b histograms its chunk; the histograms are
 // scanned digit-major; block b then walks its chunk tile by tile.  In a tile,
-// wave w owns pairs [w * 512, (w + 1) * 512) and loads all eight of its keys
-// per lane up front; it ranks equal digits with ballot matching, sub-round by
+// wave w owns pairs [w * 1024, (w + 1) * 1024) and loads all sixteen of its
+// keys per lane up front; it ranks equal digits with ballot matching, sub-round by
 // sub-round, against wave-private LDS counters (no barrier).  One block-wide
 // step turns the four waves' counts into slots of the tile sorted by digit;
 // the tile is staged in LDS in that order and written out so that
 // consecutive lanes store consecutive positions of each digit's run.
-constexpr int RITEMS = 8;
+constexpr int RITEMS = 16;
 constexpr int RTILE = WG * RITEMS;
 constexpr int RWAVE = 64 * RITEMS;
 
