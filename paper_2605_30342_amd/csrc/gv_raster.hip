@@ -232,12 +232,21 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
             part[cur * RB + t] = 0.0f;
             cpart[cur * RB + t] = 0u;
         }
+        // ONE (RB = 64): only wave 0 holds records, so a record's position in a
+        // list is its lanes below, and wave 0 posts the four list lengths in
+        // bc.cnt[0]; the other waves post only their liveness.
+        constexpr bool ONE = RB == 64;
         uint32_t pre[WAVES];
+        if (!ONE || wu == 0) {
+            int c[WAVES];
 #pragma unroll
-        for (int q = 0; q < WAVES; ++q) {
-            const unsigned long long bal = __builtin_amdgcn_ballot_w64(((mask >> q) & 1u) != 0u);
-            pre[q] = lanes_below(bal);
-            if (lane == 0) (&bc.cnt[q].x)[wu] = (int)__popcll(bal);
+            for (int q = 0; q < WAVES; ++q) {
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(((mask >> q) & 1u) != 0u);
+                pre[q] = lanes_below(bal);
+                c[q] = (int)__popcll(bal);
+                if (!ONE && lane == 0) (&bc.cnt[q].x)[wu] = c[q];
+            }
+            if (ONE && lane == 0) bc.cnt[0] = make_int4(c[0], c[1], c[2], c[3]);
         }
         {
             const bool alive = __builtin_amdgcn_ballot_w64(T >= eps_T) != 0ull;
@@ -249,19 +258,28 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
             if ((a.x | a.y | a.z | a.w) == 0) break;   // every pixel of the tile has terminated
         }
         // entries in batch (= depth) order: records of the lower waves first
+        // (every wave stages when RB > 64, so nq is set on every path)
         int nq[WAVES];
-#pragma unroll
-        for (int q = 0; q < WAVES; ++q) {
-            const int4 c = bc.cnt[q];
-            nq[q] = list_total(c);
-            if ((mask >> q) & 1u) {
-                const int pos = waves_below(c, wu) + (int)pre[q];
-                wA[q][pos] = make_float4(ux, uy, R.l11, R.l21);
-                wB[q][pos] = make_float2(R.l22, R.o);
-                wS[q][pos] = (uint16_t)(cur * RB + t);
-            }
+        if constexpr (ONE) {
+            const int4 c = bc.cnt[0];
+            nq[0] = c.x; nq[1] = c.y; nq[2] = c.z; nq[3] = c.w;
         }
-        {
+        if (!ONE || wu == 0) {
+#pragma unroll
+            for (int q = 0; q < WAVES; ++q) {
+                int below = 0;
+                if constexpr (!ONE) {
+                    const int4 c = bc.cnt[q];
+                    nq[q] = list_total(c);
+                    below = waves_below(c, wu);
+                }
+                if ((mask >> q) & 1u) {
+                    const int pos = below + (int)pre[q];
+                    wA[q][pos] = make_float4(ux, uy, R.l11, R.l21);
+                    wB[q][pos] = make_float2(R.l22, R.o);
+                    wS[q][pos] = (uint16_t)(cur * RB + t);
+                }
+            }
             const int q = (t / LPAD) & (WAVES - 1);
             const int k = pad_slot(q == 0 ? nq[0] : q == 1 ? nq[1] : q == 2 ? nq[2] : nq[3]);
             if (k >= 0) {
