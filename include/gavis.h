@@ -260,7 +260,7 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
  * autotuner: the number of depth-ordered records a tile stages into LDS per
  * batch (64, 128 or 256) for the VF CONST and VF QUERY blends.  Larger
  * batches need fewer barriers, smaller ones use less LDS (more resident
- * workgroups).  Results do not depend on the choice.  Defaults 128 / 128. */
+ * workgroups).  Results do not depend on the choice.  Defaults 64 / 256. */
 typedef struct {
     int32_t vis_batch;
     int32_t uq_batch;

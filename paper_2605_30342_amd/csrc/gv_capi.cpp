@@ -193,7 +193,7 @@ struct gv_context {
     };
     std::vector<Graph> graphs;
     bool capturing = false;
-    gv_tuning tuning = {128, 128};
+    gv_tuning tuning = {64, 256};
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     // stage timing
     bool prof_on = false;

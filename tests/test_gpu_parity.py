@@ -611,6 +611,7 @@ def test_schedule_variants_give_identical_results(ctx, tiny, tiny_ref):
     g = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
     prm = _lib.default_uq_params()
     ws = ctx.query_workspace(dsc, tiny.cand, prm, 2)
+    t0 = ctx.get_tuning()
     maps, gams = [], []
     for b in (64, 128, 256):
         ctx.set_tuning(b, b)
@@ -622,8 +623,8 @@ def test_schedule_variants_give_identical_results(ctx, tiny, tiny_ref):
         assert torch.equal(m, maps[0])
     for gg in gams[1:]:
         assert np.all(np.abs(gg - gams[0]) <= 1e-5 * (np.abs(gams[0]).max(1, keepdims=True) + 1e-30))
-    ctx.set_tuning(128, 128)
+    ctx.set_tuning(**t0)
     tuner = Autotuner(ctx)
     r = tuner.tune_query(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws)
     assert r["uq_batch"] in (64, 128, 256) and ctx.get_tuning()["uq_batch"] == r["uq_batch"]
-    ctx.set_tuning(128, 128)
+    ctx.set_tuning(**t0)
