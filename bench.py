@@ -429,6 +429,30 @@ def main():
                 "speedup_graph_vs_plain": round(plain_ms / graph_ms, 3)}
     log(f"batching {batching}")
 
+    # the paper's image geometry: the same scene and field seen by 64
+    # candidates of 512x512 (90 degrees), as one call and as one call per
+    # view (the form in which uncertainty maps are timed per view)
+    paper_geometry = None
+    if not args.no_configs:
+        wc = scenes.workload("ctx512")
+        ws_c = ctx.query_workspace(dsc, wc.cand, uprm, L)
+        s_c = torch.empty(wc.cand.n, dtype=torch.float32, device="cuda")
+        c_ms = timed(lambda: ctx.vf_query_views(dsc, gamma, L, w.train.n, wc.cand, uprm, ws_c, scores=s_c))
+        singles_c = [wc.cand.subset([v]) for v in range(wc.cand.n)]
+
+        def plain_c():
+            for c in singles_c:
+                ctx.vf_query_views(dsc, gamma, L, w.train.n, c, uprm, ws_c, scores=one)
+        pc_ms = timed(plain_c, reps=3)
+        pxc = wc.cand.pixels()
+        paper_geometry = {"workload": f"room scene and field, {wc.cand.n} candidates 512x512 (90 deg FOV)",
+                          "query_ms": round(c_ms, 4), "mpix_s": round(pxc / (c_ms / 1e3) / 1e6, 3),
+                          "views_per_s": round(wc.cand.n / (c_ms / 1e3), 1),
+                          "one_call_per_view_ms": round(pc_ms, 4),
+                          "views_per_s_one_call_per_view": round(wc.cand.n / (pc_ms / 1e3), 1)}
+        del ws_c, s_c
+        log(f"paper geometry {paper_geometry}")
+
     # the batched and precision workloads at full size (the launch
     # configurations of those workloads; figures reported beside the room line)
     batched_cfg = precision = None
@@ -541,6 +565,7 @@ def main():
         "roofline": roof,
         "raster_uq_roofline": uq_frac,
         "batching": batching,
+        "paper_geometry": paper_geometry,
         "batched_workload": batched_cfg,
         "precision": precision,
         "serving": serving,

@@ -331,6 +331,28 @@ def test_room_full_size_sampled(ctx):
     _check_scores(np.array([s[5], s[40]]), q, mp_sub)
 
 
+def test_paper_geometry_full_size_sampled(ctx):
+    """The room scene seen at the paper's image geometry (64 candidates of
+    512x512, 90 degrees, all in one call): the oracle recomputes two of the
+    views from an oracle field of one training view."""
+    w = scenes.workload("ctx512")
+    prm = oracle_params()
+    say("case: 512x512 geometry, oracle field of training view 30")
+    train = w.train.subset([30])
+    b = oracle.vf_build(w.scene, train, 3, prm)
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    say("case: 512x512 geometry query, 64 views in one call, oracle on views 7 and 51")
+    s, mp, _ = gpu_query(ctx, _dsc(w.scene), g32, 3, train.n, w.cand)
+    sub = w.cand.subset([7, 51])
+    q = oracle.vf_query(w.scene, g32, 3, train.n, sub, prm)
+    npx = 512 * 512
+    mp_sub = np.concatenate([mp[7 * npx:8 * npx], mp[51 * npx:52 * npx]])
+    worst, flagged = compare_maps(mp_sub, q)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(np.array([s[7], s[51]]), q, mp_sub)
+
+
 def test_batched_full_size_sampled(ctx):
     """The batched workload at full size (1M Gaussians in two rooms; 256
     candidates of mixed 160x120 / 320x240 / 640x480 in one call, as the
