@@ -285,6 +285,75 @@ def room_small():
     return scenes.workload("room", scale=0.1)
 
 
+def _stress_scene(train):
+    """Object-scene Gaussians plus the geometry the binning's conservative
+    tests and the multi-batch tile lists must handle: large Gaussians that
+    cover many tiles, needle-thin ones in random orientations, fully opaque
+    (o = 1) and fully transparent (o = 0, still measured) ones, and small
+    Gaussians just in front of and just behind the near plane of the
+    training cameras (huge footprints, or culled)."""
+    rng = np.random.default_rng(7100)
+
+    def quats(n):
+        q = rng.standard_normal((n, 4))
+        return q / np.linalg.norm(q, axis=1, keepdims=True)
+    parts = []
+    n = 1500   # object-scene base
+    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n),
+                  1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, n)))))
+    n = 12     # large, faint
+    parts.append((rng.uniform(-0.8, 0.8, (n, 3)), rng.uniform(0.3, 0.8, (n, 3)), quats(n),
+                  rng.uniform(0.05, 0.3, n)))
+    n = 150    # needles
+    sc = np.stack([rng.uniform(0.2, 0.5, n), np.full(n, 0.002), np.full(n, 0.002)], axis=1)
+    parts.append((rng.uniform(-1, 1, (n, 3)), sc, quats(n), 1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, n)))))
+    n = 100    # opaque
+    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n), np.ones(n)))
+    n = 50     # transparent but not virtual
+    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n), np.zeros(n)))
+    # around the near plane (0.2) of each training camera: depths 0.15 .. 0.3
+    # along the view axis, small lateral offsets
+    cen = train.centers
+    for v in range(train.n):
+        fwd = train.R[v, 2].astype(np.float64)
+        right = train.R[v, 0].astype(np.float64)
+        down = train.R[v, 1].astype(np.float64)
+        n = 10
+        d = rng.uniform(0.15, 0.3, n)
+        m = (cen[v][None] + d[:, None] * fwd[None] + rng.uniform(-0.05, 0.05, (n, 1)) * right[None]
+             + rng.uniform(-0.05, 0.05, (n, 1)) * down[None])
+        parts.append((m, np.full((n, 3), 0.01), quats(n), rng.uniform(0.1, 0.9, n)))
+    cat = [np.concatenate([p[i] for p in parts]).astype(np.float32) for i in range(4)]
+    return Scene(cat[0], cat[1], cat[2], cat[3], 0, ((-1, 1), (-1, 1), (-1, 1)))
+
+
+def test_stress_geometry_matches_oracle(ctx):
+    """Build and query on the stress scene (large, needle, opaque,
+    transparent and near-plane Gaussians) against the oracle, element by
+    element: the binning's band tests stay conservative and long tile lists
+    run over several batches."""
+    train = scenes.sphere_cameras(3, 7101, width=160, height=120)
+    cand = scenes.sphere_cameras(3, 7102, width=160, height=120)
+    sc = _stress_scene(train)
+    prm = oracle_params()
+    say(f"case: stress geometry build, {sc.n} Gaussians, 3 views 160x120")
+    b = oracle.vf_build(sc, train, 2, prm)
+    dsc = _dsc(sc)
+    g = gpu_build(ctx, dsc, train, 2)
+    worst, frac = compare_gamma(g, b)
+    say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
+    assert worst <= 1.0
+    say("case: stress geometry query, 3 views 160x120")
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, 2, train.n, cand, prm)
+    s, mp, _ = gpu_query(ctx, dsc, g32, 2, train.n, cand)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
+    assert worst <= 1.0 and flagged < 0.02
+    _check_scores(s, q, mp)
+    _check_argmax(ctx, s, q)
+
+
 def test_room_subset_build_and_query(ctx, room_small):
     say("case: room scene 20k Gaussians, L=3, 3 training views 800x800, 4 candidates 400x400")
     w = room_small
