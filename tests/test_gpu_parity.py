@@ -201,6 +201,31 @@ def test_ragged_and_mixed_resolutions_in_one_call(ctx, tiny, tiny_ref):
     assert compare_gamma(bg, bo)[0] <= 1.0
 
 
+def _extreme_views():
+    """Candidates at the largest image sizes the ABI accepts: 16384 x 16 and
+    16 x 16384 pixels (1024 tiles along one axis), looking at the tiny scene."""
+    wide = scenes.make_cameras([[3.0, 0.4, 0.3]], [[0.0, 0.0, 0.0]], 16384, 16, 120.0)
+    tall = scenes.make_cameras([[-0.5, 2.9, 0.2]], [[0.0, 0.0, 0.0]], 16, 16384, 0.5)
+    return Cameras.concat([wide, tall])
+
+
+def test_maximum_image_sizes(ctx, tiny, tiny_ref):
+    """Both largest image shapes in one call against the oracle, element by
+    element (the packed tile-rectangle fields and int16 pixel anchors at their
+    widest)."""
+    say("case: query of a 16384x16 and a 16x16384 view in one call")
+    _, g32, _ = tiny_ref
+    cams = _extreme_views()
+    q = oracle.vf_query(tiny.scene, g32, 2, tiny.train.n, cams, oracle_params())
+    s, mp, _ = gpu_query(ctx, _dsc(tiny.scene), g32, 2, tiny.train.n, cams)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}, "
+        f"covered px {[int((m != 0).sum()) for m in q['maps']]}")
+    assert worst <= 1.0 and flagged < 0.01
+    assert all((m != 0).sum() > 1000 for m in q["maps"])   # both views see the scene
+    _check_scores(s, q, mp)
+
+
 def test_no_training_views_means_invisible(ctx, tiny, tiny_ref):
     say("case: n_train = 0")
     _, g32, _ = tiny_ref
