@@ -379,6 +379,40 @@ def test_stress_geometry_matches_oracle(ctx):
     _check_argmax(ctx, s, q)
 
 
+def test_deep_translucent_stack_matches_oracle(ctx):
+    """A fog of 4000 faint Gaussians (opacity 0.003) in a small cube: about
+    19k tile instances per view over 16 tiles, up to about 3300 in one tile,
+    so the blends run up to about 50 batches of 64 records per tile (the VF
+    CONST blend flushing each one a batch late) with few pixels terminating;
+    build and query against the oracle element by element."""
+    rng = np.random.default_rng(7200)
+    n = 4000
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sc = Scene(rng.uniform(-0.2, 0.2, (n, 3)).astype(np.float32), np.full((n, 3), 0.05, np.float32),
+               q.astype(np.float32), np.full(n, 0.003, np.float32), 0, ((-1, 1), (-1, 1), (-1, 1)))
+    train = scenes.sphere_cameras(2, 7201, width=96, height=96, fov=30.0)
+    cand = scenes.sphere_cameras(2, 7202, width=96, height=96, fov=30.0)
+    prm = oracle_params()
+    say("case: translucent stack build, 4000 Gaussians of opacity 0.003, 2 views 96x96")
+    b = oracle.vf_build(sc, train, 2, prm)
+    dsc = _dsc(sc)
+    g = gpu_build(ctx, dsc, train, 2)
+    worst, frac = compare_gamma(g, b)
+    say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
+    assert worst <= 1.0
+    say("case: translucent stack query, 2 views 96x96")
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    qo = oracle.vf_query(sc, g32, 2, train.n, cand, prm)
+    s, mp, ws = gpu_query(ctx, dsc, g32, 2, train.n, cand)
+    _, counts = ctx.check_workspace(ws)
+    say(f"  instances {counts[1]}, map worst ratio {compare_maps(mp, qo)[0]:.3f}")
+    assert counts[1] > 25000                 # tile instances of the two views
+    worst, flagged = compare_maps(mp, qo)
+    assert worst <= 1.0 and flagged < 0.01
+    _check_scores(s, qo, mp)
+
+
 def test_room_subset_build_and_query(ctx, room_small):
     say("case: room scene 20k Gaussians, L=3, 3 training views 800x800, 4 candidates 400x400")
     w = room_small
