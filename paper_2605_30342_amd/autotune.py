@@ -58,6 +58,7 @@ class Autotuner:
                    rounds: int = 3) -> dict:
         key = workload_class("query", dsc.n, cams)
         if key in self.table:
+            self.apply("query", dsc.n, cams)
             return self.table[key]
         base = self.ctx.get_tuning()
         times, ref = {}, None
@@ -83,6 +84,7 @@ class Autotuner:
     def tune_build(self, dsc, cams, params, ws, gamma, reps: int = 2, rounds: int = 3) -> dict:
         key = workload_class("build", dsc.n, cams)
         if key in self.table:
+            self.apply("build", dsc.n, cams)
             return self.table[key]
         base = self.ctx.get_tuning()
         times, ref = {}, None

@@ -814,9 +814,13 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     // Graph path: every kernel argument and grid of the sequence is fixed by
     // the key below (the cameras themselves live in the view table, uploaded
     // above on the same stream before the replay).
+    // (the whole plan is part of the key: the workspace's region offsets
+    // follow from its capacities, view count and tile count; the call's
+    // pixel total places the depth maps behind the entropy maps)
     struct Key {
         const void *ws, *gamma, *vtrain, *tc, *cvar, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
-        int64_t n, n_virtual, rcap, mcap, tiles, nbytes;
+        int64_t n, n_virtual, tiles, pixels;
+        gv_workspace plan;
         int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv, csh, depth;
         float f[10];
     } key;
@@ -825,8 +829,8 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     key.cvar = q.color_var; key.csh = q.color_sh_degree; key.depth = dmp != nullptr;
     key.scores = scores; key.maps = mp;
     key.means = g->means; key.scales = g->scales; key.quats = g->quats; key.opac = g->opacity; key.anchors = g->anchors;
-    key.n = g->n; key.n_virtual = g->n_virtual; key.rcap = plan->max_records;
-    key.mcap = plan->max_instances; key.tiles = tiles; key.nbytes = (int64_t)plan->bytes;
+    key.n = g->n; key.n_virtual = g->n_virtual; key.tiles = tiles; key.pixels = pixels;
+    key.plan = *plan;
     key.mode = q.mode; key.n_cand = n_cand; key.sh = q.sh_degree; key.gdt = q.gamma_dtype; key.dtype = (int)g->dtype;
     key.anchor_block = g->anchor_block; key.count = prm->count_pairs; key.uq_batch = ctx->tuning.uq_batch;
     key.ntv = q.n_train_views;

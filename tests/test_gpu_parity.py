@@ -578,6 +578,40 @@ def test_graph_replay_matches_eager(ctx, tiny, tiny_ref):
     assert torch.equal(s_g, s_e)
 
 
+def test_graph_replay_follows_pixel_count_and_plan(ctx, tiny, tiny_ref):
+    """Graph replays with expected-depth maps, alternating two camera sets of
+    equal tile counts but different pixel counts (128x128 and 120x120, 8x8
+    tiles each) into one preallocated maps buffer: the depth maps start
+    right behind each call's entropy maps, so a replay captured for the other
+    set must not be reused; every replay equals the eager call."""
+    say("case: graph replay, equal tile counts, different pixel counts, depth maps")
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    g = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    a = tiny.cand
+    b = scenes.make_cameras(a.centers, np.zeros((a.n, 3)), 120, 120, 60.0)
+    tiles = lambda c: int(np.sum(((c.wh[:, 0] + 15) // 16) * ((c.wh[:, 1] + 15) // 16)))  # noqa: E731
+    assert tiles(a) == tiles(b) and a.pixels() != b.pixels()
+    prm_e = _lib.default_uq_params()
+    prm_g = _lib.default_uq_params(use_graph=1)
+    ws = ctx.query_workspace(dsc, Cameras.concat([a, b]), prm_e, 2)
+    buf_e = torch.full((2 * a.pixels(),), -7.0, device="cuda")
+    buf_g = torch.full((2 * a.pixels(),), -7.0, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for it, cams in enumerate([a, b, a, b, b, a]):
+            n2 = 2 * cams.pixels()
+            s_e, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, cams, prm_e, ws, maps=buf_e, want_depth=True)
+            s_e = s_e.clone()
+            s_g, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, cams, prm_g, ws, maps=buf_g, want_depth=True)
+            stream.synchronize()
+            assert torch.equal(s_g, s_e), it
+            assert torch.equal(buf_g[:n2], buf_e[:n2]), it
+            assert torch.all(buf_g[n2:] == buf_e[n2:]), it       # nothing written past the call's maps
+
+
 def test_batched_equals_per_view(ctx, tiny, tiny_ref):
     """All candidates in one call equal one call per candidate."""
     say("case: batched vs per-view query")
