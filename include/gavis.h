@@ -213,6 +213,30 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
                          const gv_uq_params *params, float *scores, float *maps,
                          const gv_workspace *plan, void *workspace, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture setup, tight serving loops, harnesses that forbid hipMalloc):
+ * vf_query_views without a caller workspace.  The workspace is a static
+ * device array of GV_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, part of the
+ * library's code object and held until the process ends; the call allocates
+ * nothing (no hipMalloc, no graph; the host view table was reserved by
+ * gv_create).  It runs the sizing pass of vf_query_workspace_size into that
+ * array and synchronises hip_stream once to read it, then enqueues the query
+ * as vf_query_views does.  Arguments, outputs and results as vf_query_views;
+ * params->use_graph must be 0 (GV_ERR_INVALID_ARG otherwise).  Errors:
+ * GV_ERR_CAPACITY when the views' workspace exceeds GV_NOALLOC_SCRATCH_BYTES
+ * or n_cand exceeds GV_NOALLOC_MAX_VIEWS (nothing is enqueued then);
+ * GV_ERR_HIP if the array's device address could not be taken at gv_create.
+ * Every call on a GPU shares that GPU's array and leaves its contents
+ * behind (each call clears what it needs cleared): calls that overlap on
+ * one GPU -- from two threads, or on two streams before the first has
+ * finished -- race and give undefined results; order them on one stream or
+ * synchronise between them. */
+#define GV_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define GV_NOALLOC_MAX_VIEWS 4096
+gv_status vf_query_views_noalloc(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                                 int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                                 const gv_uq_params *params, float *scores, float *maps, void *hip_stream);
+
 /* vf_query_views with a per-Gaussian colour covariance in place of the
  * constant Q_c (Appendix, integration with FisherRF; the hook through which
  * a radiance-field uncertainty method refines the colour term of eq. huber).

@@ -24,9 +24,11 @@ EXPORTS = (
     "gv_workspace_check", "gv_workspace_bytes", "select_next_view",
     "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name", "vf_multiview_visibility",
     "gv_set_tuning", "gv_get_tuning", "vf_view_visibility", "vf_query_views_exact",
-    "vf_query_views_color",
+    "vf_query_views_color", "vf_query_views_noalloc",
 )
 GV_PROFILE_STAGES = 9
+GV_NOALLOC_SCRATCH_BYTES = 64 << 20
+GV_NOALLOC_MAX_VIEWS = 4096
 
 
 class GvError(RuntimeError):
@@ -118,6 +120,9 @@ def load(path: str = LIB_PATH):
     L.vf_query_views.argtypes = [vp, P(gv_gaussians), vp, ctypes.c_int, i32, i64, P(gv_camera), i32,
                                  P(gv_uq_params), vp, vp, P(gv_workspace), vp, vp]
     L.vf_query_views.restype = st
+    L.vf_query_views_noalloc.argtypes = [vp, P(gv_gaussians), vp, ctypes.c_int, i32, i64, P(gv_camera), i32,
+                                         P(gv_uq_params), vp, vp, vp]
+    L.vf_query_views_noalloc.restype = st
     L.gv_workspace_check.argtypes = [vp, P(gv_workspace), vp, P(i64), vp]
     L.gv_workspace_check.restype = st
     L.gv_workspace_bytes.argtypes = [P(gv_workspace)]

@@ -182,6 +182,25 @@ class Context:
                                     ctypes.byref(ws.plan), _ptr(ws.buf), _stream(stream)))
         return scores, maps
 
+    def vf_query_views_noalloc(self, dsc: DeviceScene, gamma: torch.Tensor, sh_degree: int, n_train: int, cams,
+                               params: Optional[_lib.gv_uq_params] = None, scores: Optional[torch.Tensor] = None,
+                               maps: Optional[torch.Tensor] = None, stream=None):
+        """vf_query_views on the library's static per-GPU scratch instead of
+        a caller workspace (the call itself allocates no device memory; the
+        output tensors are the caller's).  maps, if given, receives the
+        entropy maps (and, with params.write_depth, the depth maps)."""
+        if params is None:
+            params = _lib.default_uq_params()
+        params.write_maps = 1 if maps is not None else 0
+        if scores is None:
+            scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.device}")
+        gdt = {torch.float32: GV_F32, torch.float16: GV_F16, torch.bfloat16: GV_BF16}[gamma.dtype]
+        cc = _lib.cameras_to_c(cams)
+        check(self.L.vf_query_views_noalloc(self.h, ctypes.byref(dsc.c), _ptr(gamma), gdt, sh_degree, int(n_train),
+                                            cc, cams.n, ctypes.byref(params), _ptr(scores), _ptr(maps),
+                                            _stream(stream)))
+        return scores, maps
+
     def multiview_visibility(self, dsc: DeviceScene, cams, params: Optional[_lib.gv_vf_params] = None,
                              ws: Optional[Workspace] = None, out: Optional[torch.Tensor] = None,
                              stream=None) -> torch.Tensor:

@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -166,6 +167,37 @@ int bits_for(uint64_t n) {   // bits needed to hold values 0..n-1
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+
+// Device memory of vf_query_views_noalloc: one array per GPU the library runs
+// on, in the code object's zero-initialised data, held until the process ends.
+// In host code `scratch` is only a stand-in for the symbol: its device address
+// is taken once per device with hipGetSymbolAddress (scratch_address below)
+// and only that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[GV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (the caller has made `device`
+// current); taken on the first request for each device and kept.
+hipError_t scratch_address(int device, unsigned char **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 namespace {
 const char *const kStageNames[GV_PROFILE_STAGES] = {"cull", "project", "sort_depth", "emit", "sort_tile",
                                                      "ranges", "raster_vis", "vf_accum", "raster_uq"};
@@ -192,6 +224,10 @@ struct gv_context {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<Graph> graphs;
+    // this device's static scratch (vf_query_views_noalloc); NULL if its
+    // address could not be taken, with the reason in scratch_err
+    unsigned char *scratch = nullptr;
+    std::string scratch_err;
     bool capturing = false;
     gv_tuning tuning = {64, 256};
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
@@ -465,6 +501,18 @@ gv_status gv_create(int device, gv_context **out) {
         delete c;
         return fail(GV_ERR_OUT_OF_MEMORY, "cannot allocate context counters");
     }
+    // the static scratch of vf_query_views_noalloc: its device address is
+    // taken here, once per device, with that device current
+    {
+        const hipError_t e = scratch_address(device, &c->scratch);
+        if (e != hipSuccess) {
+            c->scratch = nullptr;
+            c->scratch_err = hipGetErrorString(e);
+            (void)hipGetLastError();
+        }
+    }
+    // host view table of the no-allocation call, so that it never grows there
+    c->host_views.reserve(GV_NOALLOC_MAX_VIEWS);
     *out = c;
     return GV_OK;
 }
@@ -878,10 +926,11 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
 
 extern "C" {
 
-gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
-                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
-                         const gv_uq_params *prm, float *scores, float *maps, const gv_workspace *plan,
-                         void *workspace, void *hip_stream) {
+}  // extern "C"
+
+// Argument checks shared by vf_query_views and vf_query_views_noalloc.
+static gv_status check_query_args(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                                  int32_t sh_degree, int64_t n_train, const gv_uq_params *prm) {
     if (!ctx || !prm) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     GV_TRY(check_gauss(g));
     if (sh_degree < 0 || sh_degree > GV_MAX_SH_DEGREE)
@@ -890,9 +939,75 @@ gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gam
     if (n_train > 0 && g->n > 0 && !gamma) return fail(GV_ERR_INVALID_ARG, "gamma is NULL");
     if (gamma_dtype != GV_F32 && gamma_dtype != GV_F16 && gamma_dtype != GV_BF16)
         return fail(GV_ERR_INVALID_ARG, "bad gamma dtype");
+    return GV_OK;
+}
+
+extern "C" {
+
+gv_status vf_query_views(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                         int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                         const gv_uq_params *prm, float *scores, float *maps, const gv_workspace *plan,
+                         void *workspace, void *hip_stream) {
+    GV_TRY(check_query_args(ctx, g, gamma, gamma_dtype, sh_degree, n_train, prm));
     if (plan && plan->sh_degree != sh_degree) return fail(GV_ERR_INVALID_ARG, "plan made for another sh_degree");
     QueryArgs q = {1, sh_degree, gamma, (int)gamma_dtype, (float)n_train, nullptr, nullptr, 0, 0.f};
     return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, plan, workspace, hip_stream);
+}
+
+gv_status vf_query_views_noalloc(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
+                                 int32_t sh_degree, int64_t n_train, const gv_camera *cand, int32_t n_cand,
+                                 const gv_uq_params *prm, float *scores, float *maps, void *hip_stream) {
+    GV_TRY(check_query_args(ctx, g, gamma, gamma_dtype, sh_degree, n_train, prm));
+    if (n_cand < 1 || !cand) return fail(GV_ERR_INVALID_ARG, "need at least one candidate view");
+    if (n_cand > GV_NOALLOC_MAX_VIEWS)
+        return fail(GV_ERR_CAPACITY, "%d candidate views; the no-allocation call takes at most %d", n_cand,
+                    GV_NOALLOC_MAX_VIEWS);
+    if (prm->use_graph) return fail(GV_ERR_INVALID_ARG, "use_graph is not available without allocation");
+    GV_TRY(geom_ok(prm->znear, prm->lowpass, prm->cut, prm->eps_T));
+    if (!ctx->scratch)
+        return fail(GV_ERR_HIP, "the static scratch has no device address: %s", ctx->scratch_err.c_str());
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<ViewDev> &views = ctx->host_views;   // reserved for GV_NOALLOC_MAX_VIEWS at gv_create
+    int64_t tiles, pixels;
+    GV_TRY(make_views(cand, n_cand, views, tiles, pixels));
+    // sizing pass: the view table goes where the query's layout keeps it
+    // (its offset depends on no capacity), the counters are the context's
+    gv_workspace plan;
+    std::memset(&plan, 0, sizeof(plan));
+    plan.kind = 1;
+    plan.n = g->n;
+    plan.sh_degree = sh_degree;
+    plan.n_views = n_cand;
+    plan.total_tiles = (int32_t)tiles;
+    plan.total_pixels = pixels;
+    const size_t views_at = make_layout(plan).views;
+    if (views_at + views.size() * sizeof(ViewDev) > (size_t)GV_NOALLOC_SCRATCH_BYTES)
+        return fail(GV_ERR_CAPACITY, "view table does not fit the static scratch");
+    ViewDev *dviews = reinterpret_cast<ViewDev *>(ctx->scratch + views_at);
+    uint64_t R = 0, M = 0;
+    if (g->n > 0) {
+        GV_HIP(hipMemcpyAsync(dviews, views.data(), views.size() * sizeof(ViewDev), hipMemcpyHostToDevice, s));
+        GV_HIP(hipMemsetAsync(ctx->dev_counters, 0, 4 * sizeof(unsigned long long), s));
+        launch_measure(gargs(g), dviews, n_cand, GeomArgs{prm->znear, prm->lowpass, prm->cut}, ctx->dev_counters, s);
+        GV_HIP(hipGetLastError());
+        unsigned long long h[2] = {0, 0};
+        GV_HIP(hipMemcpyAsync(h, ctx->dev_counters, sizeof(h), hipMemcpyDeviceToHost, s));
+        GV_HIP(hipStreamSynchronize(s));
+        R = h[0];
+        M = h[1];
+    }
+    if (R > 0x7fffffffULL || M > 0x7fffffffULL)
+        return fail(GV_ERR_CAPACITY, "more than 2^31 records or instances in one call; split the views");
+    plan.max_records = (int64_t)R;
+    plan.max_instances = (int64_t)M;
+    plan.bytes = make_layout(plan).total;
+    if (plan.bytes > (size_t)GV_NOALLOC_SCRATCH_BYTES)
+        return fail(GV_ERR_CAPACITY, "these views need %zu bytes of workspace; the static scratch holds %zu "
+                                     "(use vf_query_views with a caller workspace)",
+                    plan.bytes, (size_t)GV_NOALLOC_SCRATCH_BYTES);
+    QueryArgs q = {1, sh_degree, gamma, (int)gamma_dtype, (float)n_train, nullptr, nullptr, 0, 0.f};
+    return query_views(ctx, g, q, cand, n_cand, prm, scores, maps, &plan, ctx->scratch, hip_stream);
 }
 
 gv_status vf_query_views_color(gv_context *ctx, const gv_gaussians *g, const void *gamma, gv_dtype gamma_dtype,
