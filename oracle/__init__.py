@@ -53,13 +53,16 @@ def lib():
         L.ora_vf_build.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, d, d, d, d, d, i32,
                                    vp, vp, vp, vp]
         L.ora_vf_build.restype = ctypes.c_int
-        L.ora_single_view.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, d, i32, vp, vp, vp]
+        L.ora_single_view.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, d, i32, vp, vp, vp, vp, vp, vp]
         L.ora_single_view.restype = ctypes.c_int
         L.ora_query_visibility.argtypes = [vp, i32, i64, vp]
         L.ora_query_visibility.restype = d
         L.ora_vf_query.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
                                    d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp]
         L.ora_vf_query.restype = ctypes.c_int
+        L.ora_vf_query_instr.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
+                                         d, d, d, d, d, d, d, d, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.ora_vf_query_instr.restype = ctypes.c_int
         L.ora_exact_visibility.argtypes = [i64, vp, i64, vp, d, vp, vp]
         L.ora_exact_visibility.restype = d
         L.ora_vf_query_exact.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, i64, d, i32, vp, vp, vp, vp,
@@ -75,6 +78,11 @@ def lib():
         L.ora_vf_query_depth.restype = ctypes.c_int
         L.ora_multiview_visibility.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, d, d, d, d, i32, vp, vp]
         L.ora_multiview_visibility.restype = ctypes.c_int
+        L.ora_vf_build_f32.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, d, d, d, d, d, vp, vp, vp]
+        L.ora_vf_build_f32.restype = ctypes.c_int
+        L.ora_vf_query_f32.argtypes = [i64, vp, vp, vp, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp,
+                                       d, d, d, d, d, d, d, d, vp, vp, vp]
+        L.ora_vf_query_f32.restype = ctypes.c_int
         L.ora_argmax.argtypes = [vp, i32]
         L.ora_argmax.restype = i32
         _lib = L
@@ -154,31 +162,43 @@ def project_view(scene, cams, i, prm: Params = Params()):
     return {k: out[:, j] for j, k in enumerate(keys)}
 
 
-def single_view(scene, cams, i, prm: Params = Params(), gather_mode: int = 0):
-    """Alg. 2 for view i: (v [n], count [n], near-tie allowance on v [n])."""
+def single_view(scene, cams, i, prm: Params = Params(), gather_mode: int = 0, want_pixels: bool = False):
+    """Alg. 2 for view i: (v [n], count [n], near-tie allowance on v [n]);
+    with want_pixels also a dict of per-pixel pairs composited and near-tie
+    flags ([h, w]) and the view's counts (pairs, entries, pairs on unflagged
+    pixels, entries of flagged pixels, flagged pixels, pixels)."""
     R, t, K, wh = _cams(cams)
     m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
     v = np.zeros(scene.n)
     c = np.zeros(scene.n, dtype=np.int64)
     pert = np.zeros(scene.n)
+    w_, h_ = int(wh[i][0]), int(wh[i][1])
+    pxp = np.zeros(w_ * h_, dtype=np.int32) if want_pixels else None
+    pxf = np.zeros(w_ * h_, dtype=np.uint8) if want_pixels else None
+    counts = np.zeros(6, dtype=np.int64)
     rc = lib().ora_single_view(scene.n, _p(m), _p(s), _p(q), _p(o), _p(R[i]), _p(t[i]), _p(K[i]), _p(wh[i]),
-                               prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode, _p(v), _p(c), _p(pert))
+                               prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode, _p(v), _p(c), _p(pert),
+                               _p(pxp), _p(pxf), _p(counts))
     if rc:
         raise RuntimeError("oracle single_view failed")
+    if want_pixels:
+        return v, c, pert, {"pairs": pxp.reshape(h_, w_), "flags": pxf.reshape(h_, w_).astype(bool),
+                            "counts": counts}
     return v, c, pert
 
 
 def vf_build(scene, cams, L: int, prm: Params = Params(), gather_mode: int = 0, want_views: bool = False):
     """Alg. 3 over all views in `cams`.  Returns dict: gamma [n][K], allow
     [n][K] (first-order near-tie allowance on each coefficient), stats
-    (pairs composited, list entries, Gaussians with an allowance, views) and
-    vview [V][n] if asked."""
+    (pairs composited, list entries, Gaussians with an allowance, views,
+    pairs composited on pixels without a near-tie flag, list entries of the
+    flagged pixels, flagged pixels, pixels) and vview [V][n] if asked."""
     R, t, K, wh = _cams(cams)
     m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
     Kc = (L + 1) ** 2
     gamma = np.zeros((scene.n, Kc))
     allow = np.zeros((scene.n, Kc))
-    stats = np.zeros(4, dtype=np.int64)
+    stats = np.zeros(8, dtype=np.int64)
     vview = np.zeros((cams.n, scene.n)) if want_views else None
     rc = lib().ora_vf_build(scene.n, _p(m), _p(s), _p(q), _p(o), cams.n, _p(R), _p(t), _p(K), _p(wh),
                             int(L), prm.kappa, prm.eps_T, prm.znear, prm.lowpass, prm.cut, gather_mode,
@@ -199,7 +219,10 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
              want_maps: bool = True, want_vq: bool = False, want_depth: bool = False):
     """Alg. 4 + Alg. 6 for every view in `cams`.  gamma is [n][K] (float64 or
     float32; promoted).  Returns dict: scores [V], maps (list of [h, w]),
-    flags (list of [h, w] bool), stats (pairs, entries, flagged px, px), vq,
+    flags (list of [h, w] bool), stats (pairs, entries, flagged px, px,
+    pairs on unflagged px, list entries of flagged px), absmaps_flat (per
+    pixel the sum of the magnitudes of H's terms), pxpairs_flat (pairs
+    composited per pixel), vq,
     and with want_depth the expected-depth maps depth_flat (eq. id's d_p^mn:
     sum w* z / sum w* under the compositing weights, 0 without any)."""
     if want_depth:
@@ -211,12 +234,15 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
     maps = np.zeros(npx) if want_maps else None
     pflags = np.zeros(npx, dtype=np.uint8)
     scores = np.zeros(cams.n)
-    stats = np.zeros(4, dtype=np.int64)
+    stats = np.zeros(6, dtype=np.int64)
     vq = np.zeros((cams.n, scene.n)) if want_vq else None
-    rc = lib().ora_vf_query(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
-                            int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
-                            prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass,
-                            prm.cut, gather_mode, _p(maps), _p(scores), _p(vq), _p(pflags), _p(stats))
+    absmaps = np.zeros(npx) if want_maps else None
+    pxpairs = np.zeros(npx, dtype=np.int32)
+    rc = lib().ora_vf_query_instr(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
+                                  int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
+                                  prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass,
+                                  prm.cut, gather_mode, _p(maps), _p(scores), _p(vq), _p(pflags), _p(stats),
+                                  _p(absmaps), _p(pxpairs))
     if rc:
         raise RuntimeError("oracle vf_query failed")
     out_maps, out_flags, off = [], [], 0
@@ -227,7 +253,7 @@ def vf_query(scene, gamma, L: int, n_train: int, cams, prm: Params = Params(), g
         out_flags.append(pflags[off:off + n].reshape(h, w).astype(bool))
         off += n
     return {"scores": scores, "maps": out_maps, "flags": out_flags, "stats": stats, "vq": vq,
-            "maps_flat": maps, "flags_flat": pflags.astype(bool)}
+            "maps_flat": maps, "flags_flat": pflags.astype(bool), "absmaps_flat": absmaps, "pxpairs_flat": pxpairs}
 
 
 def _vf_query_depth(scene, gamma, L, n_train, cams, prm, gather_mode):
@@ -238,7 +264,7 @@ def _vf_query_depth(scene, gamma, L, n_train, cams, prm, gather_mode):
     maps, depth = np.zeros(npx), np.zeros(npx)
     pflags = np.zeros(npx, dtype=np.uint8)
     scores = np.zeros(cams.n)
-    stats = np.zeros(4, dtype=np.int64)
+    stats = np.zeros(6, dtype=np.int64)
     rc = lib().ora_vf_query_depth(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
                                   int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
                                   prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass,
@@ -284,7 +310,7 @@ def vf_query_exact(scene, vtrain, train_cams, kappa: float, cams, prm: Params = 
     maps = np.zeros(npx) if want_maps else None
     pflags = np.zeros(npx, dtype=np.uint8)
     scores = np.zeros(cams.n)
-    stats = np.zeros(4, dtype=np.int64)
+    stats = np.zeros(6, dtype=np.int64)
     vq = np.zeros((cams.n, scene.n)) if want_vq else None
     rc = lib().ora_vf_query_exact(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(vt), _p(tc),
                                   int(train_cams.n), float(kappa), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta,
@@ -330,7 +356,7 @@ def vf_query_color(scene, gamma, L: int, n_train: int, color_var, Lc: int, cams,
     maps = np.zeros(npx) if want_maps else None
     pflags = np.zeros(npx, dtype=np.uint8)
     scores = np.zeros(cams.n)
-    stats = np.zeros(4, dtype=np.int64)
+    stats = np.zeros(6, dtype=np.int64)
     vq = np.zeros((cams.n, scene.n)) if want_vq else None
     rc = lib().ora_vf_query_color(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), L, n_train,
                                   _p(cv), int(Lc), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
@@ -368,6 +394,44 @@ def density_control_keep(vis, n_real: int, eps_v: float = 0.95):
     when its multi-view visibility is at most eps_v."""
     vis = np.asarray(vis)
     return np.nonzero(vis[n_real:] <= eps_v)[0] + n_real
+
+
+def vf_build_f32(scene, cams, L: int, prm: Params = Params()):
+    """Alg. 3 over `cams` with Alg. 2 evaluated per pixel in single precision
+    (parity bookkeeping only: it checks that the FP64 oracle's near-tie flags
+    and allowances cover what float arithmetic can change).  Returns dict:
+    gamma [n][K], pxpairs (pairs composited per pixel, packed view after
+    view), pairs."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    gamma = np.zeros((scene.n, (L + 1) ** 2))
+    pxp = np.zeros(cams.pixels(), dtype=np.int32)
+    pairs = np.zeros(1, dtype=np.int64)
+    rc = lib().ora_vf_build_f32(scene.n, _p(m), _p(s), _p(q), _p(o), cams.n, _p(R), _p(t), _p(K), _p(wh), int(L),
+                                prm.kappa, prm.eps_T, prm.znear, prm.lowpass, prm.cut, _p(gamma), _p(pxp), _p(pairs))
+    if rc:
+        raise RuntimeError("oracle vf_build_f32 failed")
+    return {"gamma": gamma, "pxpairs_flat": pxp, "pairs": int(pairs[0])}
+
+
+def vf_query_f32(scene, gamma, L: int, n_train: int, cams, prm: Params = Params()):
+    """Alg. 4 + Alg. 6 with every per-pixel quantity in single precision
+    (parity bookkeeping only, as vf_build_f32).  Returns dict: maps_flat,
+    pxpairs_flat, scores."""
+    R, t, K, wh = _cams(cams)
+    m, s, q, o = _f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity)
+    g = _f64(gamma)
+    npx = cams.pixels()
+    maps = np.zeros(npx)
+    pxp = np.zeros(npx, dtype=np.int32)
+    scores = np.zeros(cams.n)
+    rc = lib().ora_vf_query_f32(scene.n, _p(m), _p(s), _p(q), _p(o), int(scene.n_virtual), _p(g), int(L),
+                                int(n_train), cams.n, _p(R), _p(t), _p(K), _p(wh), prm.beta, prm.o0,
+                                prm.half_logdet_Q0, prm.half_logdet_Qc, prm.eps_T, prm.znear, prm.lowpass, prm.cut,
+                                _p(maps), _p(pxp), _p(scores))
+    if rc:
+        raise RuntimeError("oracle vf_query_f32 failed")
+    return {"maps_flat": maps, "pxpairs_flat": pxp, "scores": scores}
 
 
 def argmax(scores) -> int:

@@ -293,6 +293,26 @@ typedef struct {
     oentry *e;
 } olists;
 
+/* Work counts of one rasterisation, for the parity of the composited pair
+ * count: every (pixel, Gaussian) pair composited before termination, the
+ * list entries, and the same split by whether a near-tie decision touches
+ * the pixel (there an FP32 evaluation may composite a different number of
+ * pairs, at most the pixel's list length with its ghosts). */
+typedef struct {
+    int64_t pairs;            /* pairs composited */
+    int64_t entries;          /* list entries (overlapping pairs, ghosts included) */
+    int64_t pairs_clean;      /* pairs composited on pixels without a near-tie flag */
+    int64_t entries_flagged;  /* list entries of flagged pixels */
+    int64_t px_flagged;       /* pixels with a near-tie flag */
+    int64_t px;               /* pixels */
+} ocount;
+
+static void count_add(ocount *a, const ocount *b)
+{
+    a->pairs += b->pairs; a->entries += b->entries; a->pairs_clean += b->pairs_clean;
+    a->entries_flagged += b->entries_flagged; a->px_flagged += b->px_flagged; a->px += b->px;
+}
+
 static int cmp_entry(const void *pa, const void *pb)
 {
     const oentry *a = (const oentry *)pa, *b = (const oentry *)pb;
@@ -478,7 +498,7 @@ int ora_project_view(int64_t n, const double *means, const double *scales, const
 static int single_view_visibility(const oproj *P, const double *opac, int64_t n, const ocam *c,
                                   double eps_T, double cut, int mode,
                                   double *v, int64_t *cnt, double *pert,
-                                  int64_t *pairs, int64_t *entries)
+                                  ocount *counts, int32_t *pxpairs, uint8_t *pxflags)
 {
     olists L = {0, 0};
     if (gather(P, n, c, cut, mode, 1, &L)) { free_lists(&L); return -1; }
@@ -490,12 +510,12 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
     double *own_t = (double *)calloc(tot, sizeof(double));
     int64_t *cnt_t = (int64_t *)calloc(tot, sizeof(int64_t));
     int64_t *ownn_t = (int64_t *)calloc(tot, sizeof(int64_t));
-    int64_t npairs = 0;
+    int64_t npairs = 0, nclean = 0, eflag = 0, pflag = 0;
     if (!sumT_t || !dS_t || !own_t || !cnt_t || !ownn_t) {
         free(sumT_t); free(dS_t); free(own_t); free(cnt_t); free(ownn_t); free_lists(&L);
         return -1;
     }
-#pragma omp parallel reduction(+ : npairs)
+#pragma omp parallel reduction(+ : npairs, nclean, eflag, pflag)
     {
 #ifdef _OPENMP
         int tid = omp_get_thread_num();
@@ -515,7 +535,8 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
             int flag_next = 0;       /* reaching the next real entry hinges on a near tie */
             int64_t last = -1;       /* last real entry processed */
             double T_last = 1.0, a_last = 0.0;   /* T received by, and alpha of, that entry */
-            int64_t k;
+            int flagged = 0;         /* a near-tie decision touches this pixel */
+            int64_t k, np = 0;
             for (k = s; k < e; ++k) {
                 const oentry *en = &L.e[k];
                 int32_t g = en->g;
@@ -524,6 +545,7 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
                     os[g] += T;
                     on[g] += 1;
                     rel += af / (1.0 - af);
+                    flagged = 1;
                     continue;
                 }
                 double alpha = opac[g] * exp(-0.5 * en->m);
@@ -531,17 +553,19 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
                     os[g] += T;
                     on[g] += 1;
                     rel += alpha / (1.0 - alpha);
+                    flagged = 1;
                 }
-                if (flag_next) { os[g] += T; on[g] += 1; flag_next = 0; }
+                if (flag_next) { os[g] += T; on[g] += 1; flag_next = 0; flagged = 1; }
                 if (last >= 0 && depth_tie(en, &L.e[last])) {
                     /* the two may swap: each one's T changes by T_last times the other's alpha */
                     dd[L.e[last].g] += T_last * alpha;
                     dd[g] += T_last * a_last;
+                    flagged = 1;
                 }
                 sT[g] += T;
                 cc[g] += 1;
                 dd[g] += T * rel;
-                npairs++;
+                np++;
                 T_last = T;
                 a_last = alpha;
                 T *= (1.0 - alpha);
@@ -554,15 +578,21 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
             if (k < e) {
                 for (int64_t j = k + 1; j < e; ++j) {
                     if (L.e[j].kind != 0) continue;
-                    if (flag_next) { os[L.e[j].g] += T; on[L.e[j].g] += 1; }
+                    if (flag_next) { os[L.e[j].g] += T; on[L.e[j].g] += 1; flagged = 1; }
                     if (last >= 0 && depth_tie(&L.e[j], &L.e[last])) {
                         os[L.e[j].g] += T_last;
                         on[L.e[j].g] += 1;
                         dd[L.e[last].g] += T_last;
+                        flagged = 1;
                     }
                     break;
                 }
             }
+            npairs += np;
+            if (flagged) { pflag++; eflag += e - s; }
+            else nclean += np;
+            if (pxpairs) pxpairs[pix] = (int32_t)np;
+            if (pxflags) pxflags[pix] = (uint8_t)flagged;
         }
     }
     for (int64_t g = 0; g < n; ++g) {
@@ -582,8 +612,10 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
         if (cnum > 0) p += d / (double)cnum;
         pert[g] = p;
     }
-    if (pairs) *pairs += npairs;
-    if (entries) *entries += L.start[npix];
+    if (counts) {
+        ocount c1 = {npairs, L.start[npix], nclean, eflag, pflag, npix};
+        count_add(counts, &c1);
+    }
     free(sumT_t); free(dS_t); free(own_t); free(cnt_t); free(ownn_t);
     free_lists(&L);
     return 0;
@@ -599,8 +631,10 @@ static int single_view_visibility(const oproj *P, const double *opac, int64_t n,
  *   vview  [n_views][n]  per-view v_p[g]
  *   allow  [n][K]        first-order bound on |d gamma_gk| from near-tie decisions:
  *                        sum_p pert_p[g] |a_l Y_k(d_p^g)|
- *   stats  [4]           pairs composited, list entries, Gaussians with a
- *                        nonzero allowance, views processed
+ *   stats  [8]           pairs composited, list entries, Gaussians with a
+ *                        nonzero allowance, views processed, pairs composited
+ *                        on pixels no near-tie decision touches, list entries
+ *                        of the flagged pixels, flagged pixels, pixels
  * gather_mode: 0 = ellipse bounding-box scatter, 1 = brute force. */
 int ora_vf_build(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
                  int32_t n_views, const double *camR, const double *camT, const double *camK, const int32_t *camWH,
@@ -619,7 +653,7 @@ int ora_vf_build(int64_t n, const double *means, const double *scales, const dou
     double *pert = (double *)malloc(sizeof(double) * nn);
     int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * nn);
     uint8_t *touched = (uint8_t *)calloc(nn, 1);
-    int64_t pairs = 0, entries = 0;
+    ocount counts = {0, 0, 0, 0, 0, 0};
     int rc = 0;
     if (!P || !v || !pert || !cnt || !touched) { rc = -1; goto done; }
     for (int32_t p = 0; p < n_views; ++p) {
@@ -628,7 +662,7 @@ int ora_vf_build(int64_t n, const double *means, const double *scales, const dou
 #pragma omp parallel for schedule(static)
         for (int64_t g = 0; g < n; ++g)
             project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
-        if (single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v, cnt, pert, &pairs, &entries)) {
+        if (single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v, cnt, pert, &counts, NULL, NULL)) {
             rc = -1;
             goto done;
         }
@@ -651,18 +685,23 @@ int ora_vf_build(int64_t n, const double *means, const double *scales, const dou
     if (stats) {
         int64_t nt = 0;
         for (int64_t g = 0; g < n; ++g) nt += touched[g];
-        stats[0] = pairs; stats[1] = entries; stats[2] = nt; stats[3] = n_views;
+        stats[0] = counts.pairs; stats[1] = counts.entries; stats[2] = nt; stats[3] = n_views;
+        stats[4] = counts.pairs_clean; stats[5] = counts.entries_flagged;
+        stats[6] = counts.px_flagged; stats[7] = counts.px;
     }
 done:
     free(P); free(v); free(pert); free(cnt); free(touched);
     return rc;
 }
 
-/* Per-view single-view visibility only (Alg. 2), for tests: v_out [n]. */
+/* Per-view single-view visibility only (Alg. 2), for tests: v_out [n];
+ * optional per-pixel outputs (row major): pairs composited and near-tie
+ * flags; counts [6] (optional) as the ocount fields. */
 int ora_single_view(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
                     const double *camR, const double *camT, const double *camK, const int32_t *camWH,
                     double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
-                    double *v_out, int64_t *cnt_out, double *pert_out)
+                    double *v_out, int64_t *cnt_out, double *pert_out, int32_t *pxpairs, uint8_t *pxflags,
+                    int64_t *counts_out)
 {
     ocam c;
     load_cam(&c, camR, camT, camK, camWH);
@@ -673,7 +712,13 @@ int ora_single_view(int64_t n, const double *means, const double *scales, const 
     if (P && pert && cnt) {
         for (int64_t g = 0; g < n; ++g)
             project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
-        rc = single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v_out, cnt, pert, NULL, NULL);
+        ocount counts = {0, 0, 0, 0, 0, 0};
+        rc = single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v_out, cnt, pert, &counts, pxpairs,
+                                    pxflags);
+        if (counts_out) {
+            counts_out[0] = counts.pairs; counts_out[1] = counts.entries; counts_out[2] = counts.pairs_clean;
+            counts_out[3] = counts.entries_flagged; counts_out[4] = counts.px_flagged; counts_out[5] = counts.px;
+        }
         if (cnt_out) memcpy(cnt_out, cnt, sizeof(int64_t) * (size_t)n);
         if (pert_out) memcpy(pert_out, pert, sizeof(double) * (size_t)n);
     }
@@ -774,7 +819,11 @@ static inline double xlogx_neg(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
  * gamma is [n][K].  maps (optional) is packed view after view, row major;
  * pflags (optional) likewise, 1 where a near-tie decision touches the pixel.
  * vq (optional) [n_views][n] receives the queried visibility.
- * stats [4]: pairs composited, list entries, flagged pixels, total pixels. */
+ * absmaps (optional) receives per pixel the sum of the magnitudes of the
+ * terms that make up H (the scale of its rounding error); pxpairs
+ * (optional) the pairs composited per pixel.
+ * stats [6]: pairs composited, list entries, flagged pixels, total pixels,
+ * pairs composited on unflagged pixels, list entries of flagged pixels. */
 static int vf_query_core(int64_t n, const double *means, const double *scales, const double *quats,
                          const double *opac, int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
                          const double *vtrain, const double *trainC, double kappa,
@@ -782,7 +831,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                          const int32_t *camWH, double beta, double o0, double half_logdet_Q0,
                          double half_logdet_Qc, double eps_T, double znear, double lowpass, double cut,
                          int32_t gather_mode, double *maps, double *depth, double *scores, double *vq,
-                         uint8_t *pflags, int64_t *stats)
+                         uint8_t *pflags, int64_t *stats, double *absmaps, int32_t *pxpairs)
 {
     if (n < 0 || n_views < 0 || L < 0 || L > ORA_LMAX || n_virtual < 0 || n_virtual > n) return -1;
     int K = (L + 1) * (L + 1);
@@ -793,7 +842,7 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
     double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *cc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!P || !v || !cc) { free(P); free(v); free(cc); return -1; }
-    int64_t pairs = 0, entries = 0, nflag = 0, npix_total = 0, pix_off = 0;
+    int64_t pairs = 0, entries = 0, nflag = 0, npix_total = 0, pix_off = 0, pclean = 0, eflag = 0;
     int rc = 0;
     for (int32_t p = 0; p < n_views; ++p) {
         ocam c;
@@ -812,13 +861,14 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
         if (gather(P, n, &c, cut, gather_mode, 1, &Ls)) { free_lists(&Ls); rc = -1; break; }
         int64_t npix = (int64_t)c.w * c.h;
         double score = 0.0;
-        int64_t vpairs = 0, vflag = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : score, vpairs, vflag)
+        int64_t vpairs = 0, vflag = 0, vclean = 0, veflag = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : score, vpairs, vflag, vclean, veflag)
         for (int64_t pix = 0; pix < npix; ++pix) {
             int64_t s = Ls.start[pix], e = Ls.start[pix + 1];
             double T = 1.0, w0 = 0.0, H = 0.0, sw = 0.0, swz = 0.0;
+            double Habs = 0.0;   /* sum of the magnitudes of the terms of H */
             int flag = 0;
-            int64_t last = -1, k;
+            int64_t last = -1, k, np = 0;
             for (k = s; k < e; ++k) {
                 const oentry *en = &Ls.e[k];
                 if (en->kind == 1) { flag = 1; continue; }
@@ -831,11 +881,12 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                 double w = astar * T;
                 double x = w * vg;
                 H += xlogx_neg(x) + x * cc[g];
+                Habs += fabs(xlogx_neg(x)) + fabs(x * cc[g]);
                 sw += w;
                 swz += w * en->z;
                 w0 += w * (1.0 - vg);
                 T *= (1.0 - astar);
-                vpairs++;
+                np++;
                 last = k;
                 if (fabs(T - eps_T) < ORA_TBAND * eps_T) flag = 1;
                 if (T < eps_T) break;
@@ -848,21 +899,32 @@ static int vf_query_core(int64_t n, const double *means, const double *scales, c
                 }
             }
             H += xlogx_neg(w0) + w0 * cQ0;
+            Habs += fabs(xlogx_neg(w0)) + fabs(w0 * cQ0);
             if (maps) maps[pix_off + pix] = H;
+            if (absmaps) absmaps[pix_off + pix] = Habs;
             if (depth) depth[pix_off + pix] = sw > 0.0 ? swz / sw : 0.0;
             if (pflags) pflags[pix_off + pix] = (uint8_t)flag;
+            if (pxpairs) pxpairs[pix_off + pix] = (int32_t)np;
             score += H;
             vflag += flag;
+            vpairs += np;
+            if (flag) veflag += e - s;
+            else vclean += np;
         }
         entries += Ls.start[npix];
         free_lists(&Ls);
         scores[p] = score;
         pairs += vpairs;
         nflag += vflag;
+        pclean += vclean;
+        eflag += veflag;
         npix_total += npix;
         pix_off += npix;
     }
-    if (stats) { stats[0] = pairs; stats[1] = entries; stats[2] = nflag; stats[3] = npix_total; }
+    if (stats) {
+        stats[0] = pairs; stats[1] = entries; stats[2] = nflag; stats[3] = npix_total;
+        stats[4] = pclean; stats[5] = eflag;
+    }
     free(P); free(v); free(cc);
     return rc;
 }
@@ -876,7 +938,22 @@ int ora_vf_query(int64_t n, const double *means, const double *scales, const dou
 {
     return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
                          n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
-                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
+                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats, NULL, NULL);
+}
+
+/* ora_vf_query with the per-pixel instrumentation: absmaps (sum of the
+ * magnitudes of H's terms) and pxpairs (pairs composited), both optional. */
+int ora_vf_query_instr(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                       int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
+                       int32_t n_views, const double *camR, const double *camT, const double *camK,
+                       const int32_t *camWH, double beta, double o0, double half_logdet_Q0, double half_logdet_Qc,
+                       double eps_T, double znear, double lowpass, double cut, int32_t gather_mode,
+                       double *maps, double *scores, double *vq, uint8_t *pflags, int64_t *stats,
+                       double *absmaps, int32_t *pxpairs)
+{
+    return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
+                         n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
+                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats, absmaps, pxpairs);
 }
 
 /* ora_vf_query that also writes the expected-depth maps (packed like maps). */
@@ -889,7 +966,7 @@ int ora_vf_query_depth(int64_t n, const double *means, const double *scales, con
 {
     return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, NULL, 0,
                          n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T, znear,
-                         lowpass, cut, gather_mode, maps, depth, scores, NULL, pflags, stats);
+                         lowpass, cut, gather_mode, maps, depth, scores, NULL, pflags, stats, NULL, NULL);
 }
 
 /* The same with the per-Gaussian colour covariance: color_var [3][Kc][n]
@@ -904,7 +981,7 @@ int ora_vf_query_color(int64_t n, const double *means, const double *scales, con
     if (!color_var && n > 0) return -1;
     return vf_query_core(n, means, scales, quats, opac, n_virtual, gamma, L, n_train, NULL, NULL, 0.0, color_var, Lc,
                          n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, 0.0, eps_T, znear,
-                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
+                         lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats, NULL, NULL);
 }
 
 /* The same with the exact multi-view visibility in place of the SH query:
@@ -921,7 +998,7 @@ int ora_vf_query_exact(int64_t n, const double *means, const double *scales, con
     if (n_train < 0 || (n_train > 0 && (!vtrain || !trainC))) return -1;
     return vf_query_core(n, means, scales, quats, opac, n_virtual, NULL, 0, n_train, vtrain, trainC, kappa,
                          NULL, 0, n_views, camR, camT, camK, camWH, beta, o0, half_logdet_Q0, half_logdet_Qc, eps_T,
-                         znear, lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats);
+                         znear, lowpass, cut, gather_mode, maps, NULL, scores, vq, pflags, stats, NULL, NULL);
 }
 
 /* Next-best view (eq. i_gain): index of the largest score, lowest index on
@@ -964,7 +1041,7 @@ int ora_multiview_visibility(int64_t n, const double *means, const double *scale
 #pragma omp parallel for schedule(static)
         for (int64_t g = 0; g < n; ++g)
             project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
-        if (single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v, cnt, pert, NULL, NULL)) {
+        if (single_view_visibility(P, opac, n, &c, eps_T, cut, gather_mode, v, cnt, pert, NULL, NULL, NULL)) {
             rc = -1;
             goto done;
         }
@@ -976,5 +1053,284 @@ int ora_multiview_visibility(int64_t n, const double *means, const double *scale
     for (int64_t g = 0; g < n; ++g) vis[g] = 1.0 - prod[g];
 done:
     free(P); free(v); free(pert); free(cnt); free(prod);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* A single-precision evaluation of the same loops                          */
+/* ------------------------------------------------------------------------ */
+
+/* Parity bookkeeping only.  The near-tie flags and allowances above claim to
+ * mark every pixel where a single-precision evaluation of Alg. 2 / Alg. 6 may
+ * decide an overlap or a termination differently from this FP64 one.  The
+ * functions below are such an evaluation, written independently of any GPU
+ * code: the projection is the FP64 one above, rounded to float as a tile
+ * rasteriser stores it (the centre as an integer anchor pixel plus a float
+ * fraction, the conic as its float lower Cholesky factor, the depth as a
+ * float key); per pixel, the centre is taken relative to the origin of the
+ * pixel's 16 x 16 tile, m = (l11 ex + l21 ey)^2 + (l22 ey)^2, and every
+ * quantity of the compositing recurrence (alpha, T, alpha*, w*, x, H) is a
+ * float.  Sums over pixels (per-Gaussian visibility, scores) stay double so
+ * that only the per-pixel decisions and arithmetic differ.  The test suite
+ * checks that wherever the FP64 oracle raises no flag the two agree. */
+
+typedef struct {
+    int ok;
+    int32_t ax, ay;        /* anchor pixel: the projected centre rounded to integers */
+    float fx, fy;          /* centre minus anchor */
+    float l11, l21, l22;   /* lower Cholesky factor of the conic (conic = L L^T) */
+    float zk;              /* depth key */
+    double ux, uy, sxx, syy;
+} oproj32;
+
+static void proj_to_f32(const oproj *o, oproj32 *r)
+{
+    r->ok = o->ok;
+    if (!o->ok) return;
+    double ax = rint(o->ux), ay = rint(o->uy);
+    r->ax = (int32_t)ax; r->ay = (int32_t)ay;
+    r->fx = (float)(o->ux - ax); r->fy = (float)(o->uy - ay);
+    double l11 = sqrt(o->ca), l21 = o->cb / l11;
+    double l22 = sqrt(fmax(o->cc - l21 * l21, 0.0));
+    r->l11 = (float)l11; r->l21 = (float)l21; r->l22 = (float)l22;
+    r->zk = (float)o->z;
+    r->ux = o->ux; r->uy = o->uy; r->sxx = o->sxx; r->syy = o->syy;
+}
+
+static float mahal2_f32(const oproj32 *r, int i, int j)
+{
+    int ox = i & ~15, oy = j & ~15;
+    float cx = (float)(r->ax - ox) + r->fx;
+    float cy = (float)(r->ay - oy) + r->fy;
+    float ex = cx - ((float)(i - ox) + 0.5f);
+    float ey = cy - ((float)(j - oy) + 0.5f);
+    float w1 = r->l11 * ex + r->l21 * ey;
+    float w2 = r->l22 * ey;
+    return w1 * w1 + w2 * w2;
+}
+
+typedef struct { float zk; float m; int32_t g; } oentry32;
+
+static int cmp_entry32(const void *pa, const void *pb)
+{
+    const oentry32 *a = (const oentry32 *)pa, *b = (const oentry32 *)pb;
+    if (a->zk < b->zk) return -1;
+    if (a->zk > b->zk) return 1;
+    return (a->g > b->g) - (a->g < b->g);
+}
+
+/* Per-pixel lists under the float predicate m <= cut, in (float depth, index)
+ * order.  The search box is the FP64 ellipse's box widened by 1 % and two
+ * pixels, far more than float rounding can move the boundary. */
+static int gather_f32(const oproj32 *P, int64_t n, const ocam *c, float cut, int64_t **start_out, oentry32 **e_out)
+{
+    int64_t npix = (int64_t)c->w * c->h;
+    int64_t *start = (int64_t *)calloc((size_t)npix + 1, sizeof(int64_t));
+    if (!start) return -1;
+    oentry32 *E = NULL;
+    int64_t *fill = NULL;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int64_t i = 0; i < npix; ++i) start[i + 1] += start[i];
+            E = (oentry32 *)malloc(sizeof(oentry32) * (size_t)(start[npix] > 0 ? start[npix] : 1));
+            fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+            if (!E || !fill) { free(E); free(fill); free(start); return -1; }
+            memcpy(fill, start, sizeof(int64_t) * (size_t)npix);
+        }
+        for (int64_t g = 0; g < n; ++g) {
+            const oproj32 *o = &P[g];
+            if (!o->ok) continue;
+            double rx = 1.01 * sqrt((double)cut * o->sxx) + 2.0, ry = 1.01 * sqrt((double)cut * o->syy) + 2.0;
+            double fi0 = floor(o->ux - rx - 0.5), fi1 = ceil(o->ux + rx - 0.5);
+            double fj0 = floor(o->uy - ry - 0.5), fj1 = ceil(o->uy + ry - 0.5);
+            if (fi1 < 0 || fj1 < 0 || fi0 > c->w - 1 || fj0 > c->h - 1) continue;
+            int i0 = fi0 < 0 ? 0 : (int)fi0, i1 = fi1 > c->w - 1 ? c->w - 1 : (int)fi1;
+            int j0 = fj0 < 0 ? 0 : (int)fj0, j1 = fj1 > c->h - 1 ? c->h - 1 : (int)fj1;
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) {
+                    float m = mahal2_f32(o, i, j);
+                    if (!(m <= cut)) continue;
+                    int64_t pix = (int64_t)j * c->w + i;
+                    if (pass == 0) { start[pix + 1]++; continue; }
+                    oentry32 *e = &E[fill[pix]++];
+                    e->zk = o->zk; e->m = m; e->g = (int32_t)g;
+                }
+        }
+    }
+    free(fill);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t pix = 0; pix < npix; ++pix) {
+        int64_t s = start[pix], e = start[pix + 1];
+        if (e - s > 1) qsort(&E[s], (size_t)(e - s), sizeof(oentry32), cmp_entry32);
+    }
+    *start_out = start;
+    *e_out = E;
+    return 0;
+}
+
+/* Alg. 2 for one view in single precision: v[g] = (sum of T) / count. */
+static int single_view_f32(const oproj32 *P, const double *opac, int64_t n, const ocam *c, float eps_T, float cut,
+                           double *v, int32_t *pxpairs, int64_t *pairs_out)
+{
+    int64_t *start = NULL;
+    oentry32 *E = NULL;
+    if (gather_f32(P, n, c, cut, &start, &E)) return -1;
+    int64_t npix = (int64_t)c->w * c->h;
+    int nth = ora_num_threads();
+    size_t tot = (size_t)nth * (size_t)n + 1;
+    double *sT_t = (double *)calloc(tot, sizeof(double));
+    int64_t *cc_t = (int64_t *)calloc(tot, sizeof(int64_t));
+    if (!sT_t || !cc_t) { free(sT_t); free(cc_t); free(start); free(E); return -1; }
+    int64_t npairs = 0;
+#pragma omp parallel reduction(+ : npairs)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *sT = sT_t + (size_t)tid * n;
+        int64_t *cc = cc_t + (size_t)tid * n;
+#pragma omp for schedule(static)
+        for (int64_t pix = 0; pix < npix; ++pix) {
+            float T = 1.0f;
+            int32_t np = 0;
+            for (int64_t k = start[pix]; k < start[pix + 1]; ++k) {
+                const oentry32 *en = &E[k];
+                float alpha = (float)opac[en->g] * expf(-0.5f * en->m);
+                sT[en->g] += (double)T;
+                cc[en->g] += 1;
+                np++;
+                T = T * (1.0f - alpha);
+                if (T < eps_T) break;
+            }
+            npairs += np;
+            if (pxpairs) pxpairs[pix] = np;
+        }
+    }
+    for (int64_t g = 0; g < n; ++g) {
+        double s = 0.0;
+        int64_t k = 0;
+        for (int t = 0; t < nth; ++t) { s += sT_t[(size_t)t * n + g]; k += cc_t[(size_t)t * n + g]; }
+        v[g] = k > 0 ? (double)(float)(s / (double)k) : 0.0;
+    }
+    if (pairs_out) *pairs_out += npairs;
+    free(sT_t); free(cc_t); free(start); free(E);
+    return 0;
+}
+
+/* Alg. 3 with the single-precision Alg. 2 above: gamma [n][K]; pxpairs
+ * (optional) per view and pixel, packed view after view; pairs (optional)
+ * the total. */
+int ora_vf_build_f32(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                     int32_t n_views, const double *camR, const double *camT, const double *camK, const int32_t *camWH,
+                     int32_t L, double kappa, double eps_T, double znear, double lowpass, double cut,
+                     double *gamma, int32_t *pxpairs, int64_t *pairs)
+{
+    if (n < 0 || n_views < 0 || L < 0 || L > ORA_LMAX) return -1;
+    int K = (L + 1) * (L + 1);
+    double al[ORA_LMAX + 1];
+    for (int l = 0; l <= L; ++l) al[l] = ora_a_l(l, kappa);
+    memset(gamma, 0, sizeof(double) * (size_t)n * K);
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    oproj *P = (oproj *)malloc(sizeof(oproj) * nn);
+    oproj32 *P32 = (oproj32 *)malloc(sizeof(oproj32) * nn);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    int64_t npairs = 0, off = 0;
+    int rc = 0;
+    if (!P || !P32 || !v) { rc = -1; goto done; }
+    for (int32_t p = 0; p < n_views; ++p) {
+        ocam c;
+        load_cam(&c, &camR[9 * p], &camT[3 * p], &camK[4 * p], &camWH[2 * p]);
+#pragma omp parallel for schedule(static)
+        for (int64_t g = 0; g < n; ++g) {
+            project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
+            proj_to_f32(&P[g], &P32[g]);
+        }
+        if (single_view_f32(P32, opac, n, &c, (float)eps_T, (float)cut, v, pxpairs ? pxpairs + off : NULL,
+                            &npairs)) { rc = -1; goto done; }
+        off += (int64_t)c.w * c.h;
+        for (int64_t g = 0; g < n; ++g) {
+            if (v[g] == 0.0) continue;
+            double d[3] = {means[3 * g] - c.C[0], means[3 * g + 1] - c.C[1], means[3 * g + 2] - c.C[2]};
+            double Y[(ORA_LMAX + 1) * (ORA_LMAX + 1)];
+            if (ora_sh_real(L, d, Y)) continue;
+            for (int l = 0; l <= L; ++l)
+                for (int m = -l; m <= l; ++m) gamma[(size_t)g * K + l * l + l + m] += v[g] * al[l] * Y[l * l + l + m];
+        }
+    }
+    if (pairs) *pairs = npairs;
+done:
+    free(P); free(P32); free(v);
+    return rc;
+}
+
+/* Alg. 4 + Alg. 6 with every per-pixel quantity in single precision (the
+ * per-Gaussian visibility of Alg. 4 is the FP64 one, rounded to float):
+ * maps and pxpairs (optional) packed view after view, scores [n_views]. */
+int ora_vf_query_f32(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
+                     int64_t n_virtual, const double *gamma, int32_t L, int64_t n_train,
+                     int32_t n_views, const double *camR, const double *camT, const double *camK, const int32_t *camWH,
+                     double beta, double o0, double half_logdet_Q0, double half_logdet_Qc,
+                     double eps_T, double znear, double lowpass, double cut,
+                     double *maps, int32_t *pxpairs, double *scores)
+{
+    if (n < 0 || n_views < 0 || L < 0 || L > ORA_LMAX || n_virtual < 0 || n_virtual > n) return -1;
+    int K = (L + 1) * (L + 1);
+    const double c3 = 1.5 * log(2.0 * M_PI * M_E);
+    const float cQc = (float)(half_logdet_Qc + c3), cQ0 = (float)(half_logdet_Q0 + c3);
+    const float fb = (float)beta, fo0 = (float)o0, feps = (float)eps_T, fcut = (float)cut;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    oproj *P = (oproj *)malloc(sizeof(oproj) * nn);
+    oproj32 *P32 = (oproj32 *)malloc(sizeof(oproj32) * nn);
+    float *v = (float *)malloc(sizeof(float) * nn);
+    int64_t off = 0;
+    int rc = 0;
+    if (!P || !P32 || !v) { rc = -1; goto done; }
+    for (int32_t p = 0; p < n_views; ++p) {
+        ocam c;
+        load_cam(&c, &camR[9 * p], &camT[3 * p], &camK[4 * p], &camWH[2 * p]);
+#pragma omp parallel for schedule(static)
+        for (int64_t g = 0; g < n; ++g) {
+            project_one(&means[3 * g], &scales[3 * g], &quats[4 * g], &c, lowpass, znear, &P[g]);
+            proj_to_f32(&P[g], &P32[g]);
+            double d[3] = {means[3 * g] - c.C[0], means[3 * g + 1] - c.C[1], means[3 * g + 2] - c.C[2]};
+            v[g] = g >= n - n_virtual ? 0.0f : (float)ora_query_visibility(&gamma[(size_t)g * K], L, n_train, d);
+        }
+        int64_t *start = NULL;
+        oentry32 *E = NULL;
+        if (gather_f32(P32, n, &c, fcut, &start, &E)) { rc = -1; goto done; }
+        int64_t npix = (int64_t)c.w * c.h;
+        double score = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : score)
+        for (int64_t pix = 0; pix < npix; ++pix) {
+            float T = 1.0f, w0 = 0.0f, H = 0.0f;
+            int32_t np = 0;
+            for (int64_t k = start[pix]; k < start[pix + 1]; ++k) {
+                const oentry32 *en = &E[k];
+                float vg = v[en->g];
+                float alpha = (float)opac[en->g] * expf(-0.5f * en->m);
+                float astar = (vg + fb * (1.0f - vg)) * alpha + fo0 * (1.0f - fb) * (1.0f - vg);
+                float w = astar * T;
+                float x = w * vg;
+                if (x > 0.0f) H += -x * logf(x);
+                H += x * cQc;
+                w0 += w * (1.0f - vg);
+                T = T * (1.0f - astar);
+                np++;
+                if (T < feps) break;
+            }
+            if (w0 > 0.0f) H += -w0 * logf(w0);
+            H += w0 * cQ0;
+            if (maps) maps[off + pix] = (double)H;
+            if (pxpairs) pxpairs[off + pix] = np;
+            score += (double)H;
+        }
+        free(start); free(E);
+        scores[p] = score;
+        off += npix;
+    }
+done:
+    free(P); free(P32); free(v);
     return rc;
 }

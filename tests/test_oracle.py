@@ -99,12 +99,62 @@ def test_virtual_particles_are_invisible(tiny):
     assert np.any(q["vq"][:, :-50] > 0.0)
 
 
-def test_near_tie_bookkeeping_is_small(tiny):
-    """The parity allowance touches few Gaussians and few pixels."""
-    w = tiny
-    b = oracle.vf_build(w.scene, w.train, 2)
-    g, a = b["gamma"], b["allow"]
-    big = a.max(1) > 1e-4 * np.abs(g).max(1)
-    assert big.mean() < 0.05
-    q = oracle.vf_query(w.scene, g, 2, w.train.n, w.cand)
-    assert q["stats"][2] / q["stats"][3] < 0.01
+def _fp32_cases():
+    from tests._cases import stress_scene, translucent_stack
+    w = scenes.workload("tiny")
+    yield "tiny", w.scene, w.train, w.cand, 2
+    tr = scenes.sphere_cameras(3, 7101, width=160, height=120)
+    yield "stress", stress_scene(tr), tr, scenes.sphere_cameras(3, 7102, width=160, height=120), 2
+    sc, tr, cd = translucent_stack()
+    yield "translucent stack", sc, tr, cd, 2
+    w = scenes.workload("room", scale=0.1)
+    yield "room subset", w.scene, w.train.subset([0, 3, 7]), w.cand.subset([0, 1, 2, 3]), 3
+
+
+@pytest.mark.parametrize("case", list(range(4)))
+def test_near_tie_bookkeeping_against_a_float32_evaluation(case):
+    """Pins the near-tie flags and allowances (C21) against an independent
+    single-precision evaluation of the same loops (Alg. 2, Alg. 6): wherever
+    the FP64 oracle flags no pixel, the float evaluation composites exactly
+    the same number of pairs and its entropy map agrees to 1e-4 (of the
+    pixel's term magnitudes, and of |b| + max|b| of the map); every
+    Gaussian's gamma agrees to 1e-4 ||gamma_g||_inf + 2 allow_g.  On these
+    small scenes the flags stay within the C21 bars: under 0.1 % of the
+    pixels; the Gaussians with an allowance above 1e-4 of their own scale,
+    which C21 caps at 0.5 %, stay under 2 % (a Gaussian with an allowance is
+    one any of whose ~40 boundary pixels is flagged, and these scenes have
+    few, large Gaussians)."""
+    name, sc, train, cand, L = list(_fp32_cases())[case]
+    prm = oracle.Params(eps_T=float(np.float32(1e-4)), lowpass=float(np.float32(0.3)),
+                        znear=float(np.float32(0.2)), o0=float(np.float32(0.15)))
+    b = oracle.vf_build(sc, train, L, prm)
+    b32 = oracle.vf_build_f32(sc, train, L, prm)
+    off = 0
+    for i in range(train.n):
+        _, _, _, px = oracle.single_view(sc, train, i, prm, want_pixels=True)
+        n = px["pairs"].size
+        p32 = b32["pxpairs_flat"][off:off + n].reshape(px["pairs"].shape)
+        assert np.array_equal(p32[~px["flags"]], px["pairs"][~px["flags"]]), (name, i)
+        off += n
+    st = b["stats"]
+    assert st[6] / st[7] < 1e-3, (name, st)
+    ref, allow = b["gamma"], b["allow"]
+    scale = np.abs(ref).max(1, keepdims=True)
+    tol = 1e-4 * scale + 2.0 * allow + 1e-7 * np.abs(ref).max()
+    assert np.all(np.abs(b32["gamma"] - ref) <= tol), name
+    assert (allow.max(1) > 1e-4 * scale[:, 0]).mean() < 0.02, name
+
+    g32 = ref.astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, L, train.n, cand, prm)
+    q32 = oracle.vf_query_f32(sc, g32, L, train.n, cand, prm)
+    f = q["flags_flat"]
+    assert f.mean() < 1e-3, name
+    assert np.array_equal(q32["pxpairs_flat"][~f], q["pxpairs_flat"][~f]), name
+    a, bm, ab = q32["maps_flat"], q["maps_flat"], q["absmaps_flat"]
+    off = 0
+    for m in q["maps"]:
+        sl = slice(off, off + m.size)
+        ok = np.abs(a[sl] - bm[sl]) <= 1e-4 * np.minimum(ab[sl], np.abs(bm[sl]) + np.abs(bm[sl]).max()) + 1e-12
+        assert np.all(ok | f[sl]), name
+        off += m.size
+    assert q["stats"][4] <= q["stats"][0] <= q["stats"][4] + q["stats"][5]

@@ -691,3 +691,95 @@ def test_expected_depth_empty_pixels_and_range():
         zmin, zmax = min(zmin, pr["z"][ok].min()), max(zmax, pr["z"][ok].max())
     live = D > 0
     assert live.mean() > 0.3 and D[live].min() >= zmin * (1 - 1e-12) and D[live].max() <= zmax * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- depth keys and near-tie flags
+
+def test_depth_order_is_decided_on_float32_keys():
+    """Reading of "sorted by increasing z" (Alg. 2 / Alg. 6): the order is
+    decided on z rounded to FP32 (the precision of the sort keys), equal keys
+    in index order.  Two Gaussians centred on a 1x1 image's pixel (alpha = o)
+    whose FP64 depths differ, z0 = 2 + 3 2^-25 > z1 = 2 - 2^-25, but round to
+    the same FP32 key 2: index 0 composites first, so v0 = 1 and v1 = 1 - o0,
+    although FP64 order would give v1 = 1, v0 = 1 - o1.  Moving Gaussian 0 one
+    FP32 key further (z0 = 2 + 2^-22 + 3 2^-25) restores depth order.  Neither
+    depth lies near an FP32 rounding midpoint, so no pixel is flagged."""
+    from paper_2605_30342_amd.scenes import Scene
+    tz = np.float32(3.0 * 2.0 ** -25)
+    cam = axis_camera(1, 1, 50.0, center=(0.0, 0.0, -float(tz)))
+    assert cam.t[0, 2] == tz
+    o = [0.5, 0.25]
+    for m0, first in ((2.0, 0), (2.0 + 2.0 ** -22, 1)):
+        means = np.array([[0.0, 0.0, m0], [0.0, 0.0, 2.0 - 2.0 ** -23]], np.float32)
+        assert float(means[0, 2]) == m0 and float(means[1, 2]) == 2.0 - 2.0 ** -23
+        z = means[:, 2].astype(np.float64) + float(tz)
+        assert z[0] > z[1]
+        assert (np.float32(z[0]) == np.float32(z[1])) == (first == 0)
+        sc = Scene(means, np.full((2, 3), 0.01, np.float32), np.tile(np.array([1, 0, 0, 0], np.float32), (2, 1)),
+                   np.array(o, np.float32))
+        v, c, _, px = oracle.single_view(sc, cam, 0, want_pixels=True)
+        second = 1 - first
+        assert v[first] == 1.0 and v[second] == pytest.approx(1.0 - o[first], rel=1e-15)
+        assert not px["flags"].any()
+        q = oracle.vf_query(sc, np.zeros((2, 9)), 2, 0, cam)
+        assert not q["flags_flat"].any()
+
+
+def test_termination_near_eps_flags_the_pixel():
+    """A stack of 15 Gaussians centred on a 1x1 image's pixel with equal
+    opacity o: T after the 14th is (1 - o)^14.  With o chosen so that this
+    lies within 1e-5 (relative) of eps_T, a float evaluation may stop before
+    the 15th or not, so the oracle flags the pixel and gives the 15th an
+    allowance; with (1 - o)^14 a few percent away from eps_T it does not."""
+    eps = float(np.float32(1e-4))
+    prm = Params(eps_T=eps)
+    o_exact = 1.0 - eps ** (1.0 / 14.0)
+    cands = np.float32(o_exact) + np.arange(-40, 41).astype(np.float32) * np.spacing(np.float32(o_exact))
+    rel = np.abs((1.0 - cands.astype(np.float64)) ** 14 / eps - 1.0)
+    o_near = cands[np.argmin(rel)]
+    assert rel.min() < 1e-5
+    zs = np.arange(1.0, 16.0)
+    cam = axis_camera(1, 1, 50.0)
+    for o, flagged in ((o_near, True), (np.float32(0.47), False), (np.float32(0.49), False)):
+        sc = stack_scene(zs, [float(o)] * 15, scale=0.01)
+        v, c, pert, px = oracle.single_view(sc, cam, 0, prm, want_pixels=True)
+        assert bool(px["flags"][0, 0]) == flagged, o
+        assert (pert[14] > 0) == flagged
+
+
+def _boundary_scene(x):
+    from paper_2605_30342_amd.scenes import Scene
+    return Scene(np.array([[x, 0.0, 1.0]], np.float32), np.full((1, 3), 0.2, np.float32),
+                 np.array([[1, 0, 0, 0]], np.float32), np.array([0.6], np.float32))
+
+
+def test_overlap_boundary_flags_the_pixel():
+    """One isotropic Gaussian whose 3-sigma ellipse (m = 9, C2) passes within
+    1e-5 of the centre of pixel (0, 4) of a 9x9 image: the overlap decision
+    there is a near tie, so the pixel is flagged in Alg. 2 and Alg. 6 and the
+    Gaussian gets an allowance; moved by 5e-3 (m about 0.1 away) nothing is
+    flagged."""
+    cam = axis_camera(9, 9, 10.0)
+    prm = Params()
+
+    def m_at(x):
+        p = oracle.project_view(_boundary_scene(x), cam, 0, prm)
+        dx, dy = 0.5 - p["ux"][0], 4.5 - p["uy"][0]
+        return p["ca"][0] * dx * dx + 2 * p["cb"][0] * dx * dy + p["cc"][0] * dy * dy
+    lo, hi = 0.15, 0.35                  # m(lo) < 9 < m(hi): the ellipse's edge moves off the pixel
+    assert m_at(lo) < 9.0 < m_at(hi)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if m_at(mid) < 9.0 else (lo, mid)
+    x0 = 0.5 * (lo + hi)
+    xs = np.float32(x0) + np.arange(-20, 21).astype(np.float32) * np.spacing(np.float32(x0))
+    ms = np.array([m_at(float(x)) for x in xs])
+    x_near = float(xs[np.argmin(np.abs(ms - 9.0))])
+    assert abs(m_at(x_near) - 9.0) < 1e-5
+    for x, flagged in ((x_near, True), (x_near - 5e-3, False), (x_near + 5e-3, False)):
+        sc = _boundary_scene(x)
+        v, c, pert, px = oracle.single_view(sc, cam, 0, prm, want_pixels=True)
+        assert bool(px["flags"][4, 0]) == flagged and int(px["flags"].sum()) == int(flagged)
+        assert (pert[0] > 0) == flagged
+        q = oracle.vf_query(sc, np.zeros((1, 9)), 2, 0, cam, prm)
+        assert bool(q["flags"][0][4, 0]) == flagged and int(q["flags_flat"].sum()) == int(flagged)
