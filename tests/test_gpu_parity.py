@@ -19,7 +19,9 @@ import pytest
 import oracle
 from paper_2605_30342_amd import scenes
 from paper_2605_30342_amd.scenes import Cameras, Scene
-from tests._gpu import compare_gamma, compare_maps, gpu_build, gpu_query, oracle_params, say
+from tests._cases import stress_scene, translucent_stack
+from tests._gpu import (ALLOW_BAR, check_pair_count, compare_gamma, compare_maps, flag_bar, gpu_build, gpu_query,
+                        oracle_params, say, score_slack)
 
 pytestmark = pytest.mark.gpu
 
@@ -102,8 +104,8 @@ def test_build_tiny_matches_oracle(ctx, tiny, tiny_ref):
     g = gpu_build(ctx, _dsc(tiny.scene), tiny.train, 2)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
-    assert worst <= 1.0
-    assert frac < 0.05
+    assert worst <= 1.0 and frac <= ALLOW_BAR
+    assert frac <= ALLOW_BAR
 
 
 def test_query_tiny_matches_oracle(ctx, tiny, tiny_ref):
@@ -113,7 +115,7 @@ def test_query_tiny_matches_oracle(ctx, tiny, tiny_ref):
     worst, flagged = compare_maps(mp, q)
     say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
     assert worst <= 1.0
-    assert flagged < 0.01
+    assert flagged <= flag_bar(q["stats"])
     _check_scores(s, q, mp)
     _check_argmax(ctx, s, q)
 
@@ -221,7 +223,7 @@ def test_maximum_image_sizes(ctx, tiny, tiny_ref):
     worst, flagged = compare_maps(mp, q)
     say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}, "
         f"covered px {[int((m != 0).sum()) for m in q['maps']]}")
-    assert worst <= 1.0 and flagged < 0.01
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     assert all((m != 0).sum() > 1000 for m in q["maps"])   # both views see the scene
     _check_scores(s, q, mp)
 
@@ -310,48 +312,6 @@ def room_small():
     return scenes.workload("room", scale=0.1)
 
 
-def _stress_scene(train):
-    """Object-scene Gaussians plus the geometry the binning's conservative
-    tests and the multi-batch tile lists must handle: large Gaussians that
-    cover many tiles, needle-thin ones in random orientations, fully opaque
-    (o = 1) and fully transparent (o = 0, still measured) ones, and small
-    Gaussians just in front of and just behind the near plane of the
-    training cameras (huge footprints, or culled)."""
-    rng = np.random.default_rng(7100)
-
-    def quats(n):
-        q = rng.standard_normal((n, 4))
-        return q / np.linalg.norm(q, axis=1, keepdims=True)
-    parts = []
-    n = 1500   # object-scene base
-    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n),
-                  1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, n)))))
-    n = 12     # large, faint
-    parts.append((rng.uniform(-0.8, 0.8, (n, 3)), rng.uniform(0.3, 0.8, (n, 3)), quats(n),
-                  rng.uniform(0.05, 0.3, n)))
-    n = 150    # needles
-    sc = np.stack([rng.uniform(0.2, 0.5, n), np.full(n, 0.002), np.full(n, 0.002)], axis=1)
-    parts.append((rng.uniform(-1, 1, (n, 3)), sc, quats(n), 1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, n)))))
-    n = 100    # opaque
-    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n), np.ones(n)))
-    n = 50     # transparent but not virtual
-    parts.append((rng.uniform(-1, 1, (n, 3)), np.exp(rng.normal(-3.0, 0.5, (n, 3))), quats(n), np.zeros(n)))
-    # around the near plane (0.2) of each training camera: depths 0.15 .. 0.3
-    # along the view axis, small lateral offsets
-    cen = train.centers
-    for v in range(train.n):
-        fwd = train.R[v, 2].astype(np.float64)
-        right = train.R[v, 0].astype(np.float64)
-        down = train.R[v, 1].astype(np.float64)
-        n = 10
-        d = rng.uniform(0.15, 0.3, n)
-        m = (cen[v][None] + d[:, None] * fwd[None] + rng.uniform(-0.05, 0.05, (n, 1)) * right[None]
-             + rng.uniform(-0.05, 0.05, (n, 1)) * down[None])
-        parts.append((m, np.full((n, 3), 0.01), quats(n), rng.uniform(0.1, 0.9, n)))
-    cat = [np.concatenate([p[i] for p in parts]).astype(np.float32) for i in range(4)]
-    return Scene(cat[0], cat[1], cat[2], cat[3], 0, ((-1, 1), (-1, 1), (-1, 1)))
-
-
 def test_stress_geometry_matches_oracle(ctx):
     """Build and query on the stress scene (large, needle, opaque,
     transparent and near-plane Gaussians) against the oracle, element by
@@ -359,7 +319,7 @@ def test_stress_geometry_matches_oracle(ctx):
     run over several batches."""
     train = scenes.sphere_cameras(3, 7101, width=160, height=120)
     cand = scenes.sphere_cameras(3, 7102, width=160, height=120)
-    sc = _stress_scene(train)
+    sc = stress_scene(train)
     prm = oracle_params()
     say(f"case: stress geometry build, {sc.n} Gaussians, 3 views 160x120")
     b = oracle.vf_build(sc, train, 2, prm)
@@ -367,14 +327,14 @@ def test_stress_geometry_matches_oracle(ctx):
     g = gpu_build(ctx, dsc, train, 2)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
-    assert worst <= 1.0
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     say("case: stress geometry query, 3 views 160x120")
     g32 = b["gamma"].astype(np.float32).astype(np.float64)
     q = oracle.vf_query(sc, g32, 2, train.n, cand, prm)
     s, mp, _ = gpu_query(ctx, dsc, g32, 2, train.n, cand)
     worst, flagged = compare_maps(mp, q)
     say(f"  map worst ratio {worst:.3f}, flagged px {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(s, q, mp)
     _check_argmax(ctx, s, q)
 
@@ -385,14 +345,7 @@ def test_deep_translucent_stack_matches_oracle(ctx):
     so the blends run up to about 50 batches of 64 records per tile (the VF
     CONST blend flushing each one a batch late) with few pixels terminating;
     build and query against the oracle element by element."""
-    rng = np.random.default_rng(7200)
-    n = 4000
-    q = rng.standard_normal((n, 4))
-    q /= np.linalg.norm(q, axis=1, keepdims=True)
-    sc = Scene(rng.uniform(-0.2, 0.2, (n, 3)).astype(np.float32), np.full((n, 3), 0.05, np.float32),
-               q.astype(np.float32), np.full(n, 0.003, np.float32), 0, ((-1, 1), (-1, 1), (-1, 1)))
-    train = scenes.sphere_cameras(2, 7201, width=96, height=96, fov=30.0)
-    cand = scenes.sphere_cameras(2, 7202, width=96, height=96, fov=30.0)
+    sc, train, cand = translucent_stack()
     prm = oracle_params()
     say("case: translucent stack build, 4000 Gaussians of opacity 0.003, 2 views 96x96")
     b = oracle.vf_build(sc, train, 2, prm)
@@ -400,7 +353,7 @@ def test_deep_translucent_stack_matches_oracle(ctx):
     g = gpu_build(ctx, dsc, train, 2)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst ratio {worst:.3f}, allowance fraction {frac:.4f}")
-    assert worst <= 1.0
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     say("case: translucent stack query, 2 views 96x96")
     g32 = b["gamma"].astype(np.float32).astype(np.float64)
     qo = oracle.vf_query(sc, g32, 2, train.n, cand, prm)
@@ -409,8 +362,44 @@ def test_deep_translucent_stack_matches_oracle(ctx):
     say(f"  instances {counts[1]}, map worst ratio {compare_maps(mp, qo)[0]:.3f}")
     assert counts[1] > 25000                 # tile instances of the two views
     worst, flagged = compare_maps(mp, qo)
-    assert worst <= 1.0 and flagged < 0.01
+    assert worst <= 1.0 and flagged <= flag_bar(qo["stats"])
     _check_scores(s, qo, mp)
+
+
+def _pair_count_cases():
+    w = scenes.workload("tiny")
+    yield "tiny", w.scene, w.train, w.cand, 2
+    tr = scenes.sphere_cameras(3, 7101, width=160, height=120)
+    yield "stress", stress_scene(tr), tr, scenes.sphere_cameras(3, 7102, width=160, height=120), 2
+    sc, tr, cd = translucent_stack()
+    yield "translucent stack", sc, tr, cd, 2
+    w = scenes.workload("room", scale=0.1)
+    yield "room subset", w.scene, w.train.subset([0, 3, 7]), w.cand.subset([0, 1, 2, 3]), 3
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_device_pair_counts_match_oracle(ctx, case):
+    """The composited (pixel, Gaussian) pair counts the kernels report (the
+    numerator of the blend rooflines) against the oracle's exact count
+    (Alg. 2 for the build, Alg. 6 for the query): equal on every pixel
+    without a near-tie flag; a flagged pixel may contribute anywhere
+    between none and all of its list entries."""
+    name, sc, train, cand, L = list(_pair_count_cases())[case]
+    prm = oracle_params()
+    say(f"case: pair counts, {name}: build over {train.n} views, query of {cand.n} views")
+    b = oracle.vf_build(sc, train, L, prm)
+    dsc = _dsc(sc)
+    _, counts = gpu_build(ctx, dsc, train, L, want_counts=True)
+    st = b["stats"]
+    say(f"  build: device {counts[3]}, oracle {st[0]} (clean {st[4]}, flagged entries {st[5]})")
+    check_pair_count(counts[3], st, 4, 5)
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, L, train.n, cand, prm)
+    _, _, ws = gpu_query(ctx, dsc, g32, L, train.n, cand, maps=False, count_pairs=True)
+    _, counts = ctx.check_workspace(ws)
+    st = q["stats"]
+    say(f"  query: device {counts[3]}, oracle {st[0]} (clean {st[4]}, flagged entries {st[5]})")
+    check_pair_count(counts[3], st, 4, 5)
 
 
 def test_room_subset_build_and_query(ctx, room_small):
@@ -422,14 +411,14 @@ def test_room_subset_build_and_query(ctx, room_small):
     g = gpu_build(ctx, _dsc(w.scene), train, 3)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst {worst:.3f} allowance frac {frac:.4f}")
-    assert worst <= 1.0
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     g32 = b["gamma"].astype(np.float32).astype(np.float64)
     cand = w.cand.subset([0, 1, 2, 3])
     q = oracle.vf_query(w.scene, g32, 3, train.n, cand, prm)
     s, mp, _ = gpu_query(ctx, _dsc(w.scene), g32, 3, train.n, cand)
     worst, flagged = compare_maps(mp, q)
     say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(s, q, mp)
     _check_argmax(ctx, s, q)
 
@@ -445,7 +434,9 @@ def test_room_full_size_sampled(ctx):
     b = oracle.vf_build(w.scene, train, 3, prm)
     dsc = _dsc(w.scene)
     g = gpu_build(ctx, dsc, train, 3)
-    assert compare_gamma(g, b)[0] <= 1.0
+    worst, frac = compare_gamma(g, b)
+    say(f"  gamma worst {worst:.3f} allowance frac {frac:.4f}")
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     say("case: room full size query, 64 views in one call, oracle on views 5 and 40")
     g32 = b["gamma"].astype(np.float32).astype(np.float64)
     s, mp, _ = gpu_query(ctx, dsc, g32, 3, train.n, w.cand)
@@ -453,9 +444,10 @@ def test_room_full_size_sampled(ctx):
     q = oracle.vf_query(w.scene, g32, 3, train.n, sub, prm)
     npx = 400 * 400
     mp_sub = np.concatenate([mp[5 * npx:6 * npx], mp[40 * npx:41 * npx]])
-    worst, flagged = compare_maps(mp_sub, q)
-    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    rep = {}
+    worst, flagged = compare_maps(mp_sub, q, report=rep)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f} worst pixel rel {rep['pixel_rel']:.2e}")
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(np.array([s[5], s[40]]), q, mp_sub)
 
 
@@ -475,9 +467,10 @@ def test_paper_geometry_full_size_sampled(ctx):
     q = oracle.vf_query(w.scene, g32, 3, train.n, sub, prm)
     npx = 512 * 512
     mp_sub = np.concatenate([mp[7 * npx:8 * npx], mp[51 * npx:52 * npx]])
-    worst, flagged = compare_maps(mp_sub, q)
-    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    rep = {}
+    worst, flagged = compare_maps(mp_sub, q, report=rep)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f} worst pixel rel {rep['pixel_rel']:.2e}")
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(np.array([s[7], s[51]]), q, mp_sub)
 
 
@@ -495,7 +488,7 @@ def test_batched_full_size_sampled(ctx):
     g = gpu_build(ctx, dsc, train, 3)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst {worst:.3f} allowance frac {frac:.4f}")
-    assert worst <= 1.0
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     say("case: batched full size query, 256 mixed views in one call, oracle on one view per size")
     g32 = b["gamma"].astype(np.float32).astype(np.float64)
     s, mp, _ = gpu_query(ctx, dsc, g32, 3, train.n, w.cand)
@@ -504,10 +497,28 @@ def test_batched_full_size_sampled(ctx):
     idx = [int(np.nonzero(wh[:, 0] == x)[0][0]) for x in (160, 320, 640)]
     q = oracle.vf_query(w.scene, g32, 3, train.n, w.cand.subset(idx), prm)
     mp_sub = np.concatenate([mp[starts[i]:starts[i + 1]] for i in idx])
-    worst, flagged = compare_maps(mp_sub, q)
-    say(f"  views {idx}: map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    rep = {}
+    worst, flagged = compare_maps(mp_sub, q, report=rep)
+    say(f"  views {idx}: map worst {worst:.3f} flagged {flagged:.5f} worst pixel rel {rep['pixel_rel']:.2e}")
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(s[idx], q, mp_sub)
+    say("case: batched full size query as a captured hipGraph: capture, then replays, against the oracle")
+    import torch
+    from paper_2605_30342_amd import _lib
+    gprm = _lib.default_uq_params(use_graph=1)
+    ws = ctx.query_workspace(dsc, w.cand, gprm, 3)
+    gd = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    for it in range(3):
+        sg, mg = ctx.vf_query_views(dsc, gd, 3, train.n, w.cand, gprm, ws, want_maps=True)
+        st_, _ = ctx.check_workspace(ws)
+        assert st_ == 0
+        sg, mg = sg.cpu().numpy().astype(np.float64), mg.cpu().numpy().astype(np.float64)
+        mg_sub = np.concatenate([mg[starts[i]:starts[i + 1]] for i in idx])
+        worst, _ = compare_maps(mg_sub, q)
+        say(f"  graph call {it}: map worst {worst:.3f}")
+        assert worst <= 1.0
+        _check_scores(sg[idx], q, mg_sub)
+        assert np.array_equal(sg, s) and np.array_equal(mg, mp)
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
@@ -528,7 +539,7 @@ def test_precision_full_size_sampled(ctx, dtype):
     g = gpu_build(ctx, dsc, train, 3)
     worst, frac = compare_gamma(g, b)
     say(f"  gamma worst {worst:.3f} allowance frac {frac:.4f}")
-    assert worst <= 1.0
+    assert worst <= 1.0 and frac <= ALLOW_BAR
     say(f"case: precision full size {dtype} query, 512 views in one call, oracle on views 7 and 300")
     gh = torch.from_numpy(b["gamma"].astype(np.float32)).to(
         torch.float16 if dtype == "f16" else torch.bfloat16).float().numpy().astype(np.float64)
@@ -537,9 +548,10 @@ def test_precision_full_size_sampled(ctx, dtype):
     idx = [7, 300]
     q = oracle.vf_query(deq, gh, 3, train.n, w.cand.subset(idx), prm)
     mp_sub = np.concatenate([mp[i * npx:(i + 1) * npx] for i in idx])
-    worst, flagged = compare_maps(mp_sub, q)
-    say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    rep = {}
+    worst, flagged = compare_maps(mp_sub, q, report=rep)
+    say(f"  map worst {worst:.3f} flagged {flagged:.5f} worst pixel rel {rep['pixel_rel']:.2e}")
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     _check_scores(s[idx], q, mp_sub)
 
 
@@ -677,7 +689,7 @@ def test_half_storage_matches_oracle_on_dequantised_inputs(ctx, dtype):
     s, mp, _ = gpu_query(ctx, dsc, gh, 3, train.n, cand, gamma_dtype=dtype)
     worst, flagged = compare_maps(mp, q)
     say(f"  map worst {worst:.3f} flagged {flagged:.5f}")
-    assert worst <= 1.0 and flagged < 0.02
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
     # storage error against FP64 on the original FP32 inputs: reported, sanity-bounded
     q32 = oracle.vf_query(sc, b["gamma"], 3, train.n, cand, prm)
     rel = np.abs(s - q32["scores"]) / np.abs(q32["scores"])
@@ -711,20 +723,28 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
     """Requests of three resident scenes (one stored in BF16 with a BF16
     field) with mixed view counts and resolutions, served with continuous
     batching on concurrent streams under a memory budget: every request's
-    scores equal the scores of the same request run alone."""
-    say("case: continuous-batching server, alone vs mix")
+    scores equal the scores of the same request run alone, and the first
+    request of every scene matches the FP64 oracle (fields built by the
+    oracle; the BF16 scene against the oracle on its dequantised values)."""
+    say("case: continuous-batching server, alone vs mix, and against the oracle")
     import torch
     from paper_2605_30342_amd import _lib
     from paper_2605_30342_amd.api import DeviceScene
     from paper_2605_30342_amd.serve import DONE, GpuBackend, Server
     be = GpuBackend(ctx, n_slots=3)
     rng = np.random.default_rng(5)
+    prm_o = oracle_params()
+    ora_scene, ora_gamma = {}, {}
     for k in range(3):
         sc = scenes.tiny_scene(1500 + 500 * k, seed=50 + k)
         train = scenes.sphere_cameras(6, 60 + k, width=96, height=96)
         dt = "bf16" if k == 2 else "f32"
         dsc = DeviceScene(sc, dtype=dt)
-        g = ctx.vf_build(dsc, train, 2, gamma_dtype=dt)
+        seen = _dequantised(sc, dt) if dt == "bf16" else sc
+        b = oracle.vf_build(seen, train, 2, prm_o)
+        td = torch.bfloat16 if dt == "bf16" else torch.float32
+        g = torch.from_numpy(np.ascontiguousarray(b["gamma"].T.astype(np.float32))).to(td).cuda()
+        ora_scene[k], ora_gamma[k] = seen, g.float().cpu().numpy().T.astype(np.float64)
         be.add_scene(k, dsc, g, 2, train.n)
     reqs = []
     for i in range(14):
@@ -740,6 +760,7 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
     say(f"  {st}")
     assert st["merged_requests"] > 0
     prm = _lib.default_uq_params()
+    checked = set()
     for rid, (k, c) in zip(rids, reqs):
         r = srv.requests[rid]
         assert r.status == DONE, r.error
@@ -747,6 +768,14 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
         s, _ = ctx.vf_query_views(sc.dsc, sc.gamma, 2, sc.n_train, c, prm)
         torch.cuda.synchronize()
         np.testing.assert_allclose(r.scores, s.cpu().numpy(), rtol=1e-6, atol=1e-6)
+        if k not in checked:
+            q = oracle.vf_query(ora_scene[k], ora_gamma[k], 2, sc.n_train, c, prm_o)
+            slack = score_slack(q)
+            err = np.abs(r.scores.astype(np.float64) - q["scores"])
+            say(f"  scene {k} request {rid}: served vs oracle {err.max():.3e} (slack {slack.min():.3e})")
+            assert np.all(err <= slack), (err, slack)
+            checked.add(k)
+    assert checked == {0, 1, 2}
 
 
 # ---------------------------------------------------------------- density control (Alg. 5)
