@@ -126,16 +126,45 @@ class Context:
                                              ctypes.byref(plan), _stream(stream)))
         return self._alloc(plan)
 
-    def query_workspace(self, dsc: DeviceScene, cams, params: _lib.gv_uq_params, sh_degree: int,
-                        stream=None, slack: float = 1.0) -> Workspace:
+    def query_plan_exact(self, dsc: DeviceScene, cams, params: _lib.gv_uq_params, sh_degree: int,
+                         stream=None) -> _lib.gv_workspace:
+        """The exact query workspace plan of `cams` (the library's counting
+        pass on the device; synchronises `stream`); allocates nothing."""
         plan = _lib.gv_workspace()
         cc = _lib.cameras_to_c(cams)
         check(self.L.vf_query_workspace_size(self.h, ctypes.byref(dsc.c), cc, cams.n, ctypes.byref(params),
                                              sh_degree, ctypes.byref(plan), _stream(stream)))
+        return plan
+
+    def query_workspace(self, dsc: DeviceScene, cams, params: _lib.gv_uq_params, sh_degree: int,
+                        stream=None, slack: float = 1.0) -> Workspace:
+        plan = self.query_plan_exact(dsc, cams, params, sh_degree, stream)
         if slack != 1.0:
             plan.max_records = int(plan.max_records * slack) + 1
             plan.max_instances = int(plan.max_instances * slack) + 1
             plan.bytes = self.L.gv_workspace_bytes(ctypes.byref(plan))
+        return self._alloc(plan)
+
+    def query_plan(self, dsc: DeviceScene, cams, sh_degree: int, max_records: int,
+                   max_instances: int) -> _lib.gv_workspace:
+        """A query workspace plan with caller-chosen capacities, made on the
+        host (no device pass): the view, tile and pixel counts of `cams`, and
+        the bytes those capacities need.  A call whose records or instances
+        exceed them reports GV_ERR_CAPACITY through check_workspace."""
+        plan = _lib.gv_workspace()
+        wh = np.asarray(cams.wh, dtype=np.int64)
+        plan.kind = 1
+        plan.n = dsc.n
+        plan.sh_degree = int(sh_degree)
+        plan.n_views = int(cams.n)
+        plan.total_tiles = int(np.sum(((wh[:, 0] + 15) // 16) * ((wh[:, 1] + 15) // 16)))
+        plan.total_pixels = int(np.sum(wh[:, 0] * wh[:, 1]))
+        plan.max_records = int(max_records)
+        plan.max_instances = int(max_instances)
+        plan.bytes = self.L.gv_workspace_bytes(ctypes.byref(plan))
+        return plan
+
+    def alloc_workspace(self, plan: _lib.gv_workspace) -> Workspace:
         return self._alloc(plan)
 
     # ---------------------------------------------------------------- calls

@@ -5,10 +5,10 @@ ask for the uncertainty scores of a set of candidate views of one scene.  The
 server keeps a FIFO of pending requests and a fixed number of slots (HIP
 streams).  Whenever a slot is free it forms a batch from the oldest pending
 request plus the following pending requests of the same scene (up to a view
-budget), asks the backend for the exact workspace size of that batch, and
-admits it if the bytes fit in the free memory budget; otherwise it waits for
-memory to come back (the oldest request is never bypassed, so large requests
-do not starve).  Batches of different scenes run concurrently on different
+budget), asks the backend for the workspace bytes of that batch, and admits
+it if the bytes fit in the free memory budget; otherwise it waits for memory
+to come back (the oldest request is never bypassed, so large requests do not
+starve).  Batches of different scenes run concurrently on different
 slots.  Completion is detected by polling the slot's event; each request's
 latency is completion time minus arrival time.
 
@@ -256,20 +256,49 @@ class ResidentScene:
 
 
 class GpuBackend:
-    """Runs batches through the C ABI, one HIP stream per slot."""
+    """Runs batches through the C ABI, one HIP stream per slot.
 
-    def __init__(self, ctx, n_slots: int = 4, params=None):
+    Admission needs a batch's workspace bytes before anything runs; they are
+    computed on the host.  Per resident scene and image size the backend
+    keeps the largest records and instances per view seen so far (`rates`)
+    and plans a batch as the sum over its views of those rates times `slack`
+    (Context.query_plan: no device pass, nothing allocated).  Only a batch
+    holding an image size the scene has not been seen at is sized exactly
+    by the library's counting pass (synchronous, once per scene and size).
+    The workspace is allocated when the batch is launched, after admission;
+    an allocation failure is a BackendError.  At completion every batch's
+    workspace status gives its exact record and instance counts, which
+    raise the rates; a batch that overflowed its plan (the kernels then skip
+    their writes and flag it) is planned exactly and launched again on its
+    slot, once.  Such a re-launch may hold more bytes than were admitted for
+    the batch until it completes."""
+
+    def __init__(self, ctx, n_slots: int = 4, params=None, slack: float = 1.5):
         import torch
         from . import _lib
         self.torch = torch
         self.ctx = ctx
         self.scenes: Dict[Any, ResidentScene] = {}
-        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
-        self.plan_stream = torch.cuda.Stream()
+        self.n_slots = n_slots
+        self._streams = None      # created on first use (the planning logic runs without a device)
         self.params = params if params is not None else _lib.default_uq_params()
+        self.slack = float(slack)
+        self.rates: Dict[tuple, list] = {}      # (scene, w, h) -> [records per view, instances per view]
+        self.exact_sizings = 0
+        self.relaunches = 0
 
     def add_scene(self, scene_id, dsc, gamma, sh_degree: int, n_train: int) -> None:
         self.scenes[scene_id] = ResidentScene(dsc, gamma, sh_degree, n_train)
+
+    @property
+    def streams(self):
+        if self._streams is None:
+            self._streams = [self.torch.cuda.Stream() for _ in range(self.n_slots + 1)]
+        return self._streams
+
+    @property
+    def plan_stream(self):
+        return self.streams[-1]
 
     def now(self) -> float:
         return time.perf_counter()
@@ -282,44 +311,102 @@ class GpuBackend:
         from .scenes import Cameras
         return cams_list[0] if len(cams_list) == 1 else Cameras.concat(cams_list)
 
-    def plan_bytes(self, scene_id, cams_list) -> int:
+    @staticmethod
+    def _sizes(cams):
+        return [(int(w), int(h)) for w, h in cams.wh]
+
+    def _exact(self, sc, cams):
+        """Exact capacities of `cams` by the library's counting pass."""
         from ._lib import GvError
-        sc = self.scenes[scene_id]
         try:
-            ws = self.ctx.query_workspace(sc.dsc, self._cams(cams_list), self.params, sc.sh_degree,
-                                          stream=self.plan_stream)
+            ws_plan = self.ctx.query_plan_exact(sc.dsc, cams, self.params, sc.sh_degree, stream=self.plan_stream)
         except GvError as e:
             raise BackendError(str(e))
-        self._last_plan = (scene_id, ws)
-        return ws.nbytes
+        self.exact_sizings += 1
+        return ws_plan
 
-    def launch(self, scene_id, cams_list, slot: int, nbytes: int):
+    def _learn(self, scene_id, cams, records: int, instances: int) -> None:
+        """Raises the per-view rates of the image sizes in `cams` so that
+        they cover `records` and `instances` spread over its views by the
+        current rates (evenly for sizes without one)."""
+        sizes = self._sizes(cams)
+        keys = [(scene_id,) + wh for wh in sizes]
+        est_r = sum(self.rates.get(k, [0.0, 0.0])[0] for k in keys)
+        est_m = sum(self.rates.get(k, [0.0, 0.0])[1] for k in keys)
+        n = len(keys)
+        for k in set(keys):
+            r = self.rates.setdefault(k, [0.0, 0.0])
+            r[0] = max(r[0], records / n if est_r <= 0 else r[0] * records / est_r)
+            r[1] = max(r[1], instances / n if est_m <= 0 else r[1] * instances / est_m)
+
+    def _plan(self, scene_id, cams):
+        sc = self.scenes[scene_id]
+        keys = [(scene_id,) + wh for wh in self._sizes(cams)]
+        missing = sorted({k[1:] for k in keys if k not in self.rates})
+        for wh in missing:       # first sight of an image size: one exact pass over its views
+            sub = cams.subset([i for i, k in enumerate(keys) if k[1:] == wh])
+            p = self._exact(sc, sub)
+            self._learn(scene_id, sub, int(p.max_records), int(p.max_instances))
+        rec = sum(self.rates[k][0] for k in keys) * self.slack
+        ins = sum(self.rates[k][1] for k in keys) * self.slack
+        return self.ctx.query_plan(sc.dsc, cams, sc.sh_degree, int(np.ceil(rec)) + 64, int(np.ceil(ins)) + 256)
+
+    def plan_bytes(self, scene_id, cams_list) -> int:
+        return int(self._plan(scene_id, self._cams(cams_list)).bytes)
+
+    def _alloc(self, plan):
+        torch = self.torch
+        try:
+            return self.ctx.alloc_workspace(plan)
+        except (torch.cuda.OutOfMemoryError, RuntimeError) as e:
+            raise BackendError(f"workspace allocation of {int(plan.bytes)} bytes failed: {e}")
+
+    def _run(self, h) -> None:
         from ._lib import GvError
         torch = self.torch
-        sc = self.scenes[scene_id]
-        cams = self._cams(cams_list)
-        sid, ws = getattr(self, "_last_plan", (None, None))
-        if sid != scene_id or ws is None or ws.nbytes != nbytes:
-            ws = self.ctx.query_workspace(sc.dsc, cams, self.params, sc.sh_degree, stream=self.plan_stream)
-        s = self.streams[slot]
+        sc = self.scenes[h["scene"]]
+        s = h["stream"]
         s.wait_stream(self.plan_stream)
         with torch.cuda.stream(s):
             try:
-                scores, _ = self.ctx.vf_query_views(sc.dsc, sc.gamma, sc.sh_degree, sc.n_train, cams, self.params,
-                                                    ws, stream=s)
+                self.ctx.vf_query_views(sc.dsc, sc.gamma, sc.sh_degree, sc.n_train, h["cams"], self.params,
+                                        h["ws"], scores=h["scores"], stream=s)
             except GvError as e:
                 raise BackendError(str(e))
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"ev": ev, "scores": scores, "ws": ws, "stream": s}
+        h["ev"] = ev
+
+    def launch(self, scene_id, cams_list, slot: int, nbytes: int):
+        torch = self.torch
+        cams = self._cams(cams_list)
+        plan = self._plan(scene_id, cams)
+        ws = self._alloc(plan)
+        scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        h = {"scene": scene_id, "cams": cams, "ws": ws, "scores": scores, "stream": self.streams[slot],
+             "relaunched": False}
+        self._run(h)
+        return h
 
     def done(self, h) -> bool:
-        return bool(h["ev"].query())
+        from ._lib import GV_ERR_CAPACITY
+        if not h["ev"].query():
+            return False
+        st, counts = self.ctx.check_workspace(h["ws"], stream=h["stream"])
+        self._learn(h["scene"], h["cams"], counts[0], counts[1])
+        if st == GV_ERR_CAPACITY and not h["relaunched"]:
+            sc = self.scenes[h["scene"]]
+            plan = self._exact(sc, h["cams"])
+            h["ws"] = self._alloc(plan)
+            h["relaunched"] = True
+            self.relaunches += 1
+            self._run(h)
+            return False
+        if st != 0:
+            raise BackendError(f"query failed with status {st} (records {counts[0]}, instances {counts[1]})")
+        return True
 
     def result(self, h):
-        st, counts = self.ctx.check_workspace(h["ws"], stream=h["stream"])
-        if st != 0:
-            raise BackendError(f"workspace overflow {counts}")
         return h["scores"].cpu().numpy()
 
     def release(self, h) -> None:

@@ -177,3 +177,98 @@ def test_latency_stats():
     assert st["requests_done"] == 10 and st["views_done"] == 30
     assert st["p50_latency_ms"] <= st["p99_latency_ms"]
     assert st["views_per_s"] > 0
+
+
+# ---------------------------------------------------------------- GPU backend planning, on the CPU
+
+class _Plan:
+    def __init__(self, n, rec, ins):
+        self.max_records, self.max_instances = rec, ins
+        self.bytes = 1000 + 10 * rec + 20 * ins + n
+
+
+class _StubCtx:
+    """Stands in for api.Context: exact sizing returns 100 records and 300
+    instances per view of 32x24 and twice that for 64x48; allocation
+    optionally refuses."""
+    device = 0
+
+    def __init__(self, refuse_alloc=False):
+        self.exact_calls = []
+        self.allocs = 0
+        self.refuse = refuse_alloc
+
+    def query_plan_exact(self, dsc, cams, params, sh_degree, stream=None):
+        f = np.where(cams.wh[:, 0] == 32, 1, 2)
+        self.exact_calls.append(cams.n)
+        return _Plan(dsc.n, int(100 * f.sum()), int(300 * f.sum()))
+
+    def query_plan(self, dsc, cams, sh_degree, max_records, max_instances):
+        return _Plan(dsc.n, max_records, max_instances)
+
+    def alloc_workspace(self, plan):
+        import torch
+        self.allocs += 1
+        if self.refuse:
+            raise torch.cuda.OutOfMemoryError("no memory")
+        return object()
+
+
+class _Dsc:
+    n = 1000
+
+
+def _gpu_backend(ctx):
+    from paper_2605_30342_amd.serve import GpuBackend
+    be = GpuBackend(ctx, n_slots=2, params=object(), slack=1.5)
+    be._streams = [None] * 3          # no device streams on the CPU
+    be.add_scene("A", _Dsc(), None, 2, 4)
+    return be
+
+
+def _cams_wh(n, w, h, seed):
+    return scenes.room_candidates(n, seed, ((0, 6), (0, 4), (0, 3)), w, h)
+
+
+def test_gpu_backend_plans_on_the_host_after_one_exact_pass_per_image_size():
+    """Admission sizing allocates nothing; each (scene, image size) is sized
+    exactly once, later batches from the learnt per-view rates with slack;
+    a mixed batch adds the rates of its sizes."""
+    ctx = _StubCtx()
+    be = _gpu_backend(ctx)
+    b1 = be.plan_bytes("A", [_cams_wh(4, 32, 24, 1)])
+    assert ctx.exact_calls == [4] and ctx.allocs == 0
+    b2 = be.plan_bytes("A", [_cams_wh(4, 32, 24, 2), _cams_wh(2, 32, 24, 3)])
+    assert ctx.exact_calls == [4] and ctx.allocs == 0      # known size: no device pass
+    assert be.rates[("A", 32, 24)] == [100.0, 300.0]
+    p = be._plan("A", _cams_wh(6, 32, 24, 4))
+    assert p.max_records >= 6 * 100 * 1.5 and p.max_instances >= 6 * 300 * 1.5
+    assert b2 > b1
+    from paper_2605_30342_amd.scenes import Cameras
+    mixed = Cameras.concat([_cams_wh(3, 32, 24, 5), _cams_wh(2, 64, 48, 6)])
+    p = be._plan("A", mixed)
+    assert ctx.exact_calls == [4, 2]                      # only the new size is sized exactly
+    assert p.max_records >= (3 * 100 + 2 * 200) * 1.5
+
+
+def test_gpu_backend_learns_larger_counts_from_completed_batches():
+    ctx = _StubCtx()
+    be = _gpu_backend(ctx)
+    c = _cams_wh(4, 32, 24, 1)
+    be.plan_bytes("A", [c])
+    be._learn("A", c, 4 * 150, 4 * 280)          # a batch that needed more records, fewer instances
+    assert be.rates[("A", 32, 24)] == [150.0, 300.0]
+
+
+def test_gpu_backend_turns_allocation_failure_into_a_failed_request():
+    """The workspace is allocated at launch, after admission; an allocation
+    the device refuses fails the batch's requests instead of escaping the
+    server loop."""
+    ctx = _StubCtx(refuse_alloc=True)
+    be = _gpu_backend(ctx)
+    srv = Server(be, memory_budget=1 << 40, n_slots=2, max_batch_views=16)
+    rid = srv.submit("A", _cams_wh(3, 32, 24, 1))
+    srv.step()
+    r = srv.requests[rid]
+    assert r.status == FAILED and "allocation" in r.error
+    assert srv.in_use == 0 and sorted(srv.free_slots) == [0, 1]
