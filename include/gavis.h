@@ -133,8 +133,17 @@ typedef struct {
     int32_t n_views;            /* views per pass the plan was made for */
     int32_t total_tiles;        /* largest per-pass tile count */
     int64_t total_pixels;       /* largest per-pass pixel count */
-    int32_t kind;               /* 0 build, 1 query */
+    int32_t kind;               /* 0 build, 1 query, 2 density control */
     int32_t sh_degree;
+    int32_t emit_mode;          /* how instances find their output offsets: 1 a scan of
+                                   the records' tile counts, gathered into depth order by
+                                   the depth sort; 2 a single-pass scan with decoupled
+                                   look-back inside the emission (one read of each
+                                   record's binning line); 0 chosen from the sizes (2 when
+                                   the binning lines exceed the last-level cache and
+                                   records average at most 4 tiles).  The sizing calls
+                                   fill in the choice; results do not depend on it. */
+    int32_t reserved;
 } gv_workspace;
 
 /* Context: small host state, a few bytes of device counters, cached graphs.
@@ -179,6 +188,55 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
 gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
                                   const gv_vf_params *params, float *visibility, const gv_workspace *plan,
                                   void *workspace, void *hip_stream);
+
+/* Visibility-field density control (Alg. 5): virtual particles fill the
+ * scene's box at density rho; those the training views see at most eps_v
+ * (multi-view visibility 1 - prod_p (1 - v_p), as vf_multiview_visibility)
+ * are kept as invisible space.  N_virt = floor(rho * volume of [lo, hi]);
+ * particle i sits at lo + u_i (hi - lo), formed in FP64 and stored in FP32,
+ * with isotropic scale s, (4/3) pi s^3 rho = 1 + eta, identity rotation and
+ * opacity 0 (measured, never occluding).  The paper uses rho = 100, eta = 0.5,
+ * eps_v = 0.95. */
+typedef struct {
+    float lo[3], hi[3];         /* box corners (world units) */
+    float rho;                  /* particles per unit volume */
+    float eta;                  /* overlap of the particles' 1-sigma balls */
+    float eps_v;                /* keep particles with visibility <= eps_v */
+} gv_density_params;
+
+/* Alg. 5's particle count and scale for these parameters (host arithmetic
+ * only): *n_virt = N_virt, *scale = s rounded to FP32 (either may be NULL).
+ * GV_ERR_INVALID_ARG for an empty box or parameters out of range. */
+gv_status vf_virtual_particle_count(const gv_density_params *dp, int64_t *n_virt, float *scale);
+
+/* Workspace for vf_density_control.  g (device, FP32, n_virtual = 0) holds
+ * the real Gaussians in rows 0 .. n_real - 1 and room for the particles after
+ * them: g->n must be n_real + N_virt.  u: device float [n_draw][3] uniform
+ * draws in [0, 1), n_draw >= N_virt (the random numbers Alg. 5 consumes).
+ * Writes the particles into rows n_real .. of g's arrays (the arrays must be
+ * writable), runs the counting pass on the GPU over everything (synchronises
+ * hip_stream) and fills plan; *n_virt (host, optional) receives N_virt.
+ * GV_ERR_INVALID_ARG when the counts, the box or the draws do not fit,
+ * GV_ERR_UNSUPPORTED for half-precision attributes. */
+gv_status vf_density_control_workspace_size(gv_context *ctx, const gv_gaussians *g, int64_t n_real,
+                                            const float *u, int64_t n_draw, const gv_density_params *dp,
+                                            const gv_camera *train, int32_t n_train, const gv_vf_params *params,
+                                            gv_workspace *plan, int64_t *n_virt, void *hip_stream);
+
+/* Alg. 5 on the GPU: (re)writes the particles into rows n_real .. of g as the
+ * sizing call does, measures the multi-view visibility of all g->n rows
+ * (visibility: device float [g->n]), and keeps the particles with visibility
+ * <= eps_v: kept (device int32 [N_virt]) receives their indices (0-based
+ * among the particles, ascending) and *n_kept (host) their number; their
+ * attributes are packed into rows n_real .. n_real + *n_kept - 1 of g, so the
+ * first n_real + *n_kept rows, with n_virtual = *n_kept, are the scene the
+ * query takes (its last n_virtual Gaussians have V = 0).  Synchronises
+ * hip_stream.  Errors as the sizing call, GV_ERR_CAPACITY when the workspace
+ * was too small for these inputs. */
+gv_status vf_density_control(gv_context *ctx, const gv_gaussians *g, int64_t n_real, const float *u, int64_t n_draw,
+                             const gv_density_params *dp, const gv_camera *train, int32_t n_train,
+                             const gv_vf_params *params, float *visibility, int32_t *kept, int64_t *n_kept,
+                             const gv_workspace *plan, void *workspace, void *hip_stream);
 
 /* Per-view single-view visibility, the input of the exact validation mode:
  * view_vis[p * n + g] = v_p[g] (device, float [n_train][n]), the visibility of
@@ -281,13 +339,21 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
                              int64_t out[4], void *hip_stream);
 
 /* Launch schedule of the blend kernels, chosen per workload class by the
- * autotuner: the number of depth-ordered records a tile stages into LDS per
- * batch (64, 128 or 256) for the VF CONST and VF QUERY blends.  Larger
- * batches need fewer barriers, smaller ones use less LDS (more resident
- * workgroups).  Results do not depend on the choice.  Defaults 64 / 256. */
+ * autotuner, for the VF CONST (vis_) and VF QUERY (uq_) blends:
+ *   *_batch  depth-ordered records a tile stages into LDS per batch (64, 128
+ *            or 256): larger batches need fewer barriers, smaller ones use
+ *            less LDS (more resident workgroups);
+ *   *_order  which tile each workgroup blends (0: workgroup b takes tile b;
+ *            1: the eight XCDs, which take the workgroups in turn, each take
+ *            a contiguous run of tiles, so that neighbouring tiles, which
+ *            share most of their records, share an L2 cache).
+ * Results do not depend on the choice (VF CONST's float atomics may add in
+ * another order).  Defaults 64 / 256, order 0. */
 typedef struct {
     int32_t vis_batch;
     int32_t uq_batch;
+    int32_t vis_order;
+    int32_t uq_order;
 } gv_tuning;
 gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t);
 gv_status gv_get_tuning(const gv_context *ctx, gv_tuning *t);

@@ -48,6 +48,8 @@ def lib():
         L.ora_sh_real.argtypes = [ctypes.c_int, vp, vp]
         L.ora_sh_real.restype = ctypes.c_int
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_virtual_particles.argtypes = [vp, vp, d, d, vp, i64, vp, vp]
+        L.ora_virtual_particles.restype = i64
         L.ora_project_view.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, d, d, d, vp]
         L.ora_project_view.restype = ctypes.c_int
         L.ora_vf_build.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, d, d, d, d, d, i32,
@@ -394,6 +396,57 @@ def density_control_keep(vis, n_real: int, eps_v: float = 0.95):
     when its multi-view visibility is at most eps_v."""
     vis = np.asarray(vis)
     return np.nonzero(vis[n_real:] <= eps_v)[0] + n_real
+
+
+@dataclass
+class _Gaussians:
+    """Attribute arrays of a set of Gaussians (the fields the oracle reads)."""
+    means: np.ndarray
+    scales: np.ndarray
+    quats: np.ndarray
+    opacity: np.ndarray
+    n_virtual: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+
+def virtual_particles(lo, hi, u, rho: float = 100.0, eta: float = 0.5):
+    """Alg. 5's virtual particles in the box [lo, hi]: (means [N_virt][3],
+    scale s).  N_virt = floor(rho * volume), positions lo + u (hi - lo) from
+    the uniform draws u, scale s with (4/3) pi s^3 rho = 1 + eta."""
+    lo, hi, u = _f64(np.asarray(lo)), _f64(np.asarray(hi)), _f64(np.asarray(u))
+    n_draw = u.shape[0]
+    out = np.zeros((max(n_draw, 1), 3))
+    s = np.zeros(1)
+    nv = lib().ora_virtual_particles(_p(lo), _p(hi), float(rho), float(eta), _p(u), n_draw, _p(out), _p(s))
+    if nv < 0:
+        raise ValueError("too few uniform draws for the box and density, or an empty box")
+    return out[:nv].copy(), float(s[0])
+
+
+def density_control(scene, cams, u, lo, hi, rho: float = 100.0, eta: float = 0.5, eps_v: float = 0.95,
+                    prm: Params = Params(), stored_f32: bool = True):
+    """Alg. 5 end to end: the virtual particles (transparent, identity
+    rotation) appended to the scene, the multi-view visibility of everything
+    (Alg. 2 per view, 1 - prod (1 - v_p)), and the particles kept (visibility
+    at most eps_v).  With stored_f32 the particles' means and scale are
+    rounded to FP32, the precision every Gaussian attribute is stored in,
+    before they are measured.  Returns dict: n_virt, s, means [N_virt][3],
+    vis and allow of the particles [N_virt], kept (particle indices,
+    ascending)."""
+    means, s = virtual_particles(lo, hi, u, rho, eta)
+    if stored_f32:
+        means, s = means.astype(np.float32).astype(np.float64), float(np.float32(s))
+    nv = means.shape[0]
+    allp = _Gaussians(np.concatenate([scene.means.astype(np.float64), means]),
+                      np.concatenate([scene.scales.astype(np.float64), np.full((nv, 3), s)]),
+                      np.concatenate([scene.quats.astype(np.float64), np.tile([1.0, 0.0, 0.0, 0.0], (nv, 1))]),
+                      np.concatenate([scene.opacity.astype(np.float64), np.zeros(nv)]))
+    vis, allow = multiview_visibility(allp, cams, prm)
+    keep = density_control_keep(vis, scene.n, eps_v) - scene.n
+    return {"n_virt": nv, "s": s, "means": means, "vis": vis[scene.n:], "allow": allow[scene.n:], "kept": keep}
 
 
 def vf_build_f32(scene, cams, L: int, prm: Params = Params()):

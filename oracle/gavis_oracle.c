@@ -1056,6 +1056,28 @@ done:
     return rc;
 }
 
+/* Virtual particles of the density control (Alg. 5): N_virt = floor(rho *
+ * volume of the box [lo, hi]) particles; particle i sits at lo + u_i (hi - lo)
+ * (u: the uniform draws, [n_draw][3], n_draw >= N_virt), isotropic scale s
+ * with (4/3) pi s^3 rho = 1 + eta (each particle's 1-sigma ball holds 1 + eta
+ * of the density's volume per particle), identity rotation and opacity 0.
+ * Writes means_out [N_virt][3] if given; returns N_virt, or -1 if n_draw is
+ * too small or the box is empty. */
+int64_t ora_virtual_particles(const double *lo, const double *hi, double rho, double eta, const double *u,
+                              int64_t n_draw, double *means_out, double *s_out)
+{
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= hi[k] - lo[k];
+    if (!(vol > 0.0) || !(rho > 0.0)) return -1;
+    const int64_t nv = (int64_t)floor(rho * vol);
+    if (nv > n_draw) return -1;
+    if (s_out) *s_out = cbrt(3.0 * (1.0 + eta) / (4.0 * M_PI * rho));
+    if (means_out)
+        for (int64_t i = 0; i < nv; ++i)
+            for (int k = 0; k < 3; ++k) means_out[3 * i + k] = lo[k] + u[3 * i + k] * (hi[k] - lo[k]);
+    return nv;
+}
+
 /* ------------------------------------------------------------------------ */
 /* A single-precision evaluation of the same loops                          */
 /* ------------------------------------------------------------------------ */

@@ -24,7 +24,8 @@ EXPORTS = (
     "gv_workspace_check", "gv_workspace_bytes", "select_next_view",
     "gv_profile_enable", "gv_profile_read", "gv_profile_stage_name", "vf_multiview_visibility",
     "gv_set_tuning", "gv_get_tuning", "vf_view_visibility", "vf_query_views_exact",
-    "vf_query_views_color", "vf_query_views_noalloc",
+    "vf_query_views_color", "vf_query_views_noalloc", "vf_density_control_workspace_size", "vf_density_control",
+    "vf_virtual_particle_count",
 )
 GV_PROFILE_STAGES = 9
 GV_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -55,6 +56,11 @@ class gv_vf_params(ctypes.Structure):
                 ("views_per_pass", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
 
 
+class gv_density_params(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3), ("rho", ctypes.c_float),
+                ("eta", ctypes.c_float), ("eps_v", ctypes.c_float)]
+
+
 class gv_uq_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_float), ("o0", ctypes.c_float), ("half_logdet_Q0", ctypes.c_float),
                 ("half_logdet_Qc", ctypes.c_float), ("eps_T", ctypes.c_float), ("znear", ctypes.c_float),
@@ -63,13 +69,15 @@ class gv_uq_params(ctypes.Structure):
 
 
 class gv_tuning(ctypes.Structure):
-    _fields_ = [("vis_batch", ctypes.c_int32), ("uq_batch", ctypes.c_int32)]
+    _fields_ = [("vis_batch", ctypes.c_int32), ("uq_batch", ctypes.c_int32), ("vis_order", ctypes.c_int32),
+                ("uq_order", ctypes.c_int32)]
 
 
 class gv_workspace(ctypes.Structure):
     _fields_ = [("bytes", ctypes.c_size_t), ("max_records", ctypes.c_int64), ("max_instances", ctypes.c_int64),
                 ("n", ctypes.c_int64), ("n_views", ctypes.c_int32), ("total_tiles", ctypes.c_int32),
-                ("total_pixels", ctypes.c_int64), ("kind", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
+                ("total_pixels", ctypes.c_int64), ("kind", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("emit_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -108,6 +116,14 @@ def load(path: str = LIB_PATH):
     L.vf_view_visibility.argtypes = [vp, P(gv_gaussians), P(gv_camera), i32, P(gv_vf_params), vp, vp,
                                      P(gv_workspace), vp, vp]
     L.vf_view_visibility.restype = st
+    L.vf_density_control_workspace_size.argtypes = [vp, P(gv_gaussians), i64, vp, i64, P(gv_density_params),
+                                                    P(gv_camera), i32, P(gv_vf_params), P(gv_workspace), P(i64), vp]
+    L.vf_density_control_workspace_size.restype = st
+    L.vf_density_control.argtypes = [vp, P(gv_gaussians), i64, vp, i64, P(gv_density_params), P(gv_camera), i32,
+                                     P(gv_vf_params), vp, vp, P(i64), P(gv_workspace), vp, vp]
+    L.vf_density_control.restype = st
+    L.vf_virtual_particle_count.argtypes = [P(gv_density_params), P(i64), P(ctypes.c_float)]
+    L.vf_virtual_particle_count.restype = st
     L.vf_query_views_exact.argtypes = [vp, P(gv_gaussians), vp, vp, i32, ctypes.c_float, P(gv_camera), i32,
                                        P(gv_uq_params), vp, vp, P(gv_workspace), vp, vp]
     L.vf_query_views_exact.restype = st

@@ -331,14 +331,14 @@ class Context:
         st = self.L.gv_workspace_check(self.h, ctypes.byref(ws.plan), _ptr(ws.buf), out, _stream(stream))
         return st, (int(out[0]), int(out[1]), int(out[2]), int(out[3]))
 
-    def set_tuning(self, vis_batch: int = 64, uq_batch: int = 256):
-        t = _lib.gv_tuning(vis_batch, uq_batch)
+    def set_tuning(self, vis_batch: int = 64, uq_batch: int = 256, vis_order: int = 0, uq_order: int = 0):
+        t = _lib.gv_tuning(vis_batch, uq_batch, vis_order, uq_order)
         check(self.L.gv_set_tuning(self.h, ctypes.byref(t)))
 
     def get_tuning(self):
         t = _lib.gv_tuning()
         check(self.L.gv_get_tuning(self.h, ctypes.byref(t)))
-        return {"vis_batch": t.vis_batch, "uq_batch": t.uq_batch}
+        return {"vis_batch": t.vis_batch, "uq_batch": t.uq_batch, "vis_order": t.vis_order, "uq_order": t.uq_order}
 
     def profile(self, on: bool = True):
         check(self.L.gv_profile_enable(self.h, 1 if on else 0))
@@ -359,54 +359,69 @@ class Context:
 
 # ---------------------------------------------------------------- density control (Alg. 5)
 
-def virtual_particle_count(extent, rho: float = 100.0) -> int:
-    """N_virt = floor(rho * scene volume)."""
-    vol = float(np.prod([hi - lo for lo, hi in extent]))
-    return int(np.floor(rho * vol))
-
-
-def virtual_particle_scale(rho: float = 100.0, eta: float = 0.5) -> float:
-    """Isotropic scale s with (4/3) pi s^3 rho = 1 + eta."""
-    return float((3.0 * (1.0 + eta) / (4.0 * np.pi * rho)) ** (1.0 / 3.0))
-
-
-def virtual_particles(extent, u: np.ndarray, rho: float = 100.0, eta: float = 0.5):
-    """Virtual particles at lo + u (hi - lo) (u: uniform draws in [0, 1)^3,
-    at least N_virt rows), identity rotation, scale s, opacity 0."""
+def density_control(ctx: "Context", scene, train, u: np.ndarray, lo=None, hi=None, rho: float = 100.0,
+                    eta: float = 0.5, eps_v: float = 0.95, params: Optional[_lib.gv_vf_params] = None,
+                    device: str = "cuda"):
+    """Alg. 5 through the library (vf_density_control): virtual particles in
+    the box [lo, hi] (the scene's extent by default) at density rho, from the
+    uniform draws u ([n_draw][3] in [0, 1)); the multi-view visibility of the
+    scene and the particles; the particles with visibility at most eps_v kept
+    as the scene's n_virtual tail.  This function only allocates the device
+    arrays (the real attributes copied in, room for the particles behind
+    them) and reads the results back.  Returns (augmented scene as a
+    scenes.Scene, visibility of every particle, indices of the kept
+    particles, N_virt)."""
     from .scenes import Scene
-    n = virtual_particle_count(extent, rho)
-    lo = np.array([e[0] for e in extent], dtype=np.float64)
-    hi = np.array([e[1] for e in extent], dtype=np.float64)
-    means = lo + np.asarray(u[:n], dtype=np.float64) * (hi - lo)
-    sc = virtual_particle_scale(rho, eta)
-    return Scene(means.astype(np.float32), np.full((n, 3), sc, np.float32),
-                 np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), np.zeros(n, np.float32), 0, tuple(extent))
+    if params is None:
+        params = _lib.default_vf_params()
+    ext = scene.extent
+    dp = _lib.gv_density_params()
+    for k in range(3):
+        dp.lo[k] = float(ext[k][0] if lo is None else lo[k])
+        dp.hi[k] = float(ext[k][1] if hi is None else hi[k])
+    dp.rho, dp.eta, dp.eps_v = float(rho), float(eta), float(eps_v)
+    L = load()
+    u_dev = torch.from_numpy(np.ascontiguousarray(u, dtype=np.float32)).to(device)
+    n_real = int(scene.n)
 
+    def arrays(n_total):
+        out = []
+        for a, w in ((scene.means, 3), (scene.scales, 3), (scene.quats, 4), (scene.opacity, 1)):
+            t = torch.empty((n_total, w) if w > 1 else (n_total,), dtype=torch.float32, device=device)
+            t[:n_real] = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+            out.append(t)
+        return out
 
-def append_virtual(real, virt, keep=None):
-    """Scene made of the real Gaussians followed by the (kept) virtual ones,
-    marked as the n_virtual tail."""
-    from .scenes import Scene
-    idx = np.arange(virt.n) if keep is None else np.asarray(keep)
-    return Scene(np.concatenate([real.means, virt.means[idx]]), np.concatenate([real.scales, virt.scales[idx]]),
-                 np.concatenate([real.quats, virt.quats[idx]]), np.concatenate([real.opacity, virt.opacity[idx]]),
-                 int(len(idx)), real.extent)
+    def gauss(ts, n_total):
+        g = _lib.gv_gaussians()
+        g.n, g.n_virtual, g.dtype = n_total, 0, GV_F32
+        g.means, g.scales, g.quats, g.opacity = (t.data_ptr() for t in ts)
+        g.anchors, g.anchor_block = None, 0
+        return g
 
-
-def density_control(ctx: "Context", scene, train, u: np.ndarray, rho: float = 100.0, eta: float = 0.5,
-                    eps_v: float = 0.95, params=None):
-    """Alg. 5: sample virtual particles, measure their multi-view visibility
-    against the scene (transparent, on the GPU), keep those with visibility
-    <= eps_v.  Returns (augmented scene with the kept particles as its
-    n_virtual tail, visibility of every candidate particle)."""
-    virt = virtual_particles(scene.extent, u, rho, eta)
-    allp = append_virtual(scene, virt)
-    dsc = DeviceScene(allp)
-    vis = ctx.multiview_visibility(dsc, train, params)
-    torch.cuda.synchronize()
-    v = vis[scene.n:].cpu().numpy()
-    keep = np.nonzero(v <= eps_v)[0]
-    return append_virtual(scene, virt, keep), v
+    # N_virt and s come from the library's own arithmetic
+    plan = _lib.gv_workspace()
+    nv, sc = ctypes.c_int64(0), ctypes.c_float(0.0)
+    check(L.vf_virtual_particle_count(ctypes.byref(dp), ctypes.byref(nv), ctypes.byref(sc)))
+    n_virt = int(nv.value)
+    cc = _lib.cameras_to_c(train)
+    ts = arrays(n_real + n_virt)
+    g = gauss(ts, n_real + n_virt)
+    check(L.vf_density_control_workspace_size(ctx.h, ctypes.byref(g), n_real, _ptr(u_dev), int(u_dev.shape[0]),
+                                              ctypes.byref(dp), cc, train.n, ctypes.byref(params),
+                                              ctypes.byref(plan), ctypes.byref(nv), _stream(None)))
+    ws = ctx.alloc_workspace(plan)
+    vis = torch.empty(max(n_real + n_virt, 1), dtype=torch.float32, device=device)
+    kept = torch.empty(max(n_virt, 1), dtype=torch.int32, device=device)
+    n_kept = ctypes.c_int64(0)
+    check(L.vf_density_control(ctx.h, ctypes.byref(g), n_real, _ptr(u_dev), int(u_dev.shape[0]), ctypes.byref(dp),
+                               cc, train.n, ctypes.byref(params), _ptr(vis), _ptr(kept), ctypes.byref(n_kept),
+                               ctypes.byref(ws.plan), _ptr(ws.buf), _stream(None)))
+    k = int(n_kept.value)
+    n = n_real + k
+    aug = Scene(ts[0][:n].cpu().numpy(), ts[1][:n].cpu().numpy(), ts[2][:n].cpu().numpy(), ts[3][:n].cpu().numpy(),
+                k, scene.extent)
+    return aug, vis[n_real:n_real + n_virt].cpu().numpy(), kept[:k].cpu().numpy(), n_virt
 
 
 def split_maps(maps: torch.Tensor, cams):

@@ -1,15 +1,18 @@
 """Autotuner for the blend launch schedule.
 
-The blends stage a tile's depth-ordered records through LDS in batches of
-64, 128 or 256 (`gv_tuning`): larger batches need fewer workgroup barriers,
-smaller ones leave room for more resident workgroups per CU.  Which wins
-depends on the workload (list lengths per tile, image sizes, Gaussian
-footprints), so the tuner times each candidate on the caller's actual
-workload, checks that the outputs are identical, and caches the winner per
-workload class in a JSON file.
+Two axes per blend (`gv_tuning`): the records a tile stages into LDS per
+batch (64, 128 or 256: larger batches need fewer workgroup barriers, smaller
+ones leave room for more resident workgroups per CU) and the tile order of
+the workgroups (0: workgroup b blends tile b; 1: each of the eight XCDs takes
+a contiguous run of tiles, so that neighbouring tiles share an L2).  Which
+schedule wins depends on the workload (list lengths per tile, image sizes,
+Gaussian footprints, the number of views), so the tuner times every
+candidate on the caller's actual workload, checks that the outputs agree, and
+caches the winner per workload class in a JSON file.
 """
 from __future__ import annotations
 
+import itertools
 import json
 import math
 import os
@@ -17,7 +20,9 @@ from typing import Dict, Optional
 
 import torch
 
-CANDIDATES = (64, 128, 256)
+BATCHES = (64, 128, 256)
+ORDERS = (0, 1)
+CANDIDATES = tuple(itertools.product(BATCHES, ORDERS))
 
 
 def workload_class(mode: str, n_gaussians: int, cams) -> str:
@@ -40,6 +45,10 @@ def _time(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def _label(c) -> str:
+    return f"{c[0]}/{c[1]}"
+
+
 class Autotuner:
     def __init__(self, ctx, cache_path: Optional[str] = None):
         self.ctx = ctx
@@ -54,31 +63,37 @@ class Autotuner:
             with open(self.path, "w") as f:
                 json.dump(self.table, f, indent=1, sort_keys=True)
 
+    def _set(self, mode: str, batch: int, order: int) -> None:
+        t = self.ctx.get_tuning()
+        p = "uq" if mode == "query" else "vis"
+        t[f"{p}_batch"], t[f"{p}_order"] = batch, order
+        self.ctx.set_tuning(**t)
+
     def tune_query(self, dsc, gamma, sh_degree: int, n_train: int, cams, params, ws, reps: int = 3,
                    rounds: int = 3) -> dict:
         key = workload_class("query", dsc.n, cams)
         if key in self.table:
             self.apply("query", dsc.n, cams)
             return self.table[key]
-        base = self.ctx.get_tuning()
         times, ref = {}, None
         scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         # candidates interleaved over several rounds, best time of each kept,
         # so that clock ramps and other transients do not pick the winner
         for _ in range(rounds):
-            for bsz in CANDIDATES:
-                self.ctx.set_tuning(base["vis_batch"], bsz)
+            for c in CANDIDATES:
+                self._set("query", *c)
                 t = _time(lambda: self.ctx.vf_query_views(dsc, gamma, sh_degree, n_train, cams, params, ws,
                                                           scores=scores), reps)
-                times[bsz] = min(times.get(bsz, t), t)
+                times[c] = min(times.get(c, t), t)
                 out = scores.clone()
                 if ref is None:
                     ref = out
                 elif not torch.equal(out, ref):
-                    raise RuntimeError(f"query results differ between batch sizes ({bsz})")
+                    raise RuntimeError(f"query results differ between schedules ({_label(c)})")
         best = min(times, key=times.get)
-        self.ctx.set_tuning(base["vis_batch"], best)
-        self.table[key] = {"uq_batch": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        self._set("query", *best)
+        self.table[key] = {"uq_batch": best[0], "uq_order": best[1],
+                           "ms": {_label(k): round(v, 4) for k, v in times.items()}}
         return self.table[key]
 
     def tune_build(self, dsc, cams, params, ws, gamma, reps: int = 2, rounds: int = 3) -> dict:
@@ -86,13 +101,12 @@ class Autotuner:
         if key in self.table:
             self.apply("build", dsc.n, cams)
             return self.table[key]
-        base = self.ctx.get_tuning()
         times, ref = {}, None
         for _ in range(rounds):
-            for bsz in CANDIDATES:
-                self.ctx.set_tuning(bsz, base["uq_batch"])
+            for c in CANDIDATES:
+                self._set("build", *c)
                 t = _time(lambda: self.ctx.vf_build(dsc, cams, params.sh_degree, params, ws, gamma), reps)
-                times[bsz] = min(times.get(bsz, t), t)
+                times[c] = min(times.get(c, t), t)
                 out = gamma.clone()
                 if ref is None:
                     ref = out
@@ -100,20 +114,17 @@ class Autotuner:
                     # float atomics may add in another order: compare to FP32 rounding
                     scale = ref.abs().amax(dim=0, keepdim=True) + 1e-30
                     if ((out - ref).abs() > 1e-5 * scale).any():
-                        raise RuntimeError(f"build results differ between batch sizes ({bsz})")
+                        raise RuntimeError(f"build results differ between schedules ({_label(c)})")
         best = min(times, key=times.get)
-        self.ctx.set_tuning(best, base["uq_batch"])
-        self.table[key] = {"vis_batch": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        self._set("build", *best)
+        self.table[key] = {"vis_batch": best[0], "vis_order": best[1],
+                           "ms": {_label(k): round(v, 4) for k, v in times.items()}}
         return self.table[key]
 
     def apply(self, mode: str, n_gaussians: int, cams) -> bool:
         e = self.table.get(workload_class(mode, n_gaussians, cams))
         if not e:
             return False
-        t = self.ctx.get_tuning()
-        if mode == "query":
-            t["uq_batch"] = e["uq_batch"]
-        else:
-            t["vis_batch"] = e["vis_batch"]
-        self.ctx.set_tuning(t["vis_batch"], t["uq_batch"])
+        p = "uq" if mode == "query" else "vis"
+        self._set(mode, e[f"{p}_batch"], e.get(f"{p}_order", 0))
         return True

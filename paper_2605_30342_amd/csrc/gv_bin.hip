@@ -378,7 +378,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 Bin b = {};
                 if (!Pj.ok) {
                     bin[r] = b;
-                    ntr[r] = 0u;
+                    if (ntr) ntr[r] = 0u;
                     key[r] = DEAD_KEY;
                     rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     b.l21 = R.l21;
                     b.l22 = R.l22;
                     bin[r] = b;
-                    ntr[r] = bin_ntiles(b.dims);
+                    if (ntr) ntr[r] = bin_ntiles(b.dims);
                 }
             }
             started += (uint32_t)__popcll(P);
@@ -815,22 +815,98 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
 // The key also carries the record's quadrant mask for the tile (which
 // quadrants of the tile its ellipse reaches); an instance whose ellipse
 // reaches none of them is given the tile id past the last tile.
-// Each wave takes 64 consecutive records and writes their instances as one
-// contiguous range in chunks of 64 outputs, lane j writing output J + j.
-// The record owning an output is found without a search: records starting
-// inside the chunk mark their first output in LDS, a ballot over the marks
-// gives every lane the number of records started up to its output, and the
-// compacted list of records that own tiles turns that count into a lane.
-__global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
-                                             const uint32_t *__restrict__ ioff, const Status *__restrict__ st,
-                                             float qcut, uint32_t dead_tile, uint32_t *__restrict__ ikey,
-                                             uint32_t *__restrict__ ival) {
-    __shared__ uint2 sid[WAVES][64];       // record index, first output (relative)
-    __shared__ float4 sgA[WAVES][64];      // band-test constants of each record: fx, fy, kx, 1 / a
-    __shared__ float4 sgB[WAVES][64];      // c, ey of the rightmost point, half height, anchor (bits)
-    __shared__ uint2 sgC[WAVES][64];       // first tile, rectangle dims
-    __shared__ uint8_t cl[WAVES][64];      // lanes of the records that own at least one tile, in order
-    __shared__ uint8_t mk[WAVES][64];      // 1 where a record starts at that output of the chunk
+//
+// A wave takes a chunk of 64 depth-ordered records and writes their instances
+// as one contiguous range in chunks of 64 outputs, lane j writing output
+// J + j.  The record owning an output is found without a search: records
+// starting inside the output chunk mark their first output in LDS, a ballot
+// over the marks gives every lane the number of records started up to its
+// output, and the compacted list of records that own tiles turns that count
+// into a lane.  Two kernels differ only in where a chunk's output offsets
+// come from: a scan of the records' tile counts done before (k_emit_scanned),
+// or the kernel's own single-pass scan (k_emit).
+struct EmitLds {
+    uint2 sid[WAVES][64];       // record index, first output (relative to the chunk)
+    float4 sgA[WAVES][64];      // band-test constants of each record: fx, fy, kx, 1 / a
+    float4 sgB[WAVES][64];      // c, ey of the rightmost point, half height, anchor (bits)
+    uint2 sgC[WAVES][64];       // first tile, rectangle dims
+    uint8_t cl[WAVES][64];      // lanes of the records that own at least one tile, in order
+    uint8_t mk[WAVES][64];      // 1 where a record starts at that output of the chunk
+};
+
+// This lane's record r (binning line B, nt tiles, first output rel after the
+// chunk's first output cbase); outputs at or past icap are not written.
+__device__ __forceinline__ void emit_chunk(EmitLds &S, int w, int lane, uint32_t r, const Bin &B, uint32_t nt,
+                                           uint32_t rel, unsigned long long cbase, unsigned long long icap, float qc,
+                                           float sq, uint32_t dead_tile, uint32_t *__restrict__ ikey,
+                                           uint32_t *__restrict__ ival) {
+    const bool owns = nt > 0;
+    const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
+    if (owns) S.cl[w][lanes_below(own)] = (uint8_t)lane;
+    S.sid[w][lane] = make_uint2(r, rel);
+    if (owns) {
+        const EllipseBands E = ellipse_bands(B.l11, B.l21, B.l22, sq);
+        S.sgA[w][lane] = make_float4(B.fx, B.fy, E.kx, E.ia);
+        S.sgB[w][lane] = make_float4(B.l22, E.eyR, E.hy, __int_as_float(B.uvr));
+        S.sgC[w][lane] = make_uint2(B.tile0, B.dims);
+    }
+    // outputs of the chunk = end of the last record that owns tiles
+    uint32_t total = 0;
+    if (own) {
+        const int last = 63 - __builtin_clzll(own);
+        total = __shfl(rel + nt, last);
+    }
+    uint32_t started = 0;   // records (owning tiles) that start before the output chunk
+    for (uint32_t J = 0; J < total; J += 64) {
+        S.mk[w][lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (owns && rel >= J && rel < J + 64) S.mk[w][rel - J] = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned long long P = __builtin_amdgcn_ballot_w64(S.mk[w][lane] != 0);
+        const uint32_t upto = started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull);
+        const uint32_t jo = J + lane;
+        const unsigned long long o = cbase + jo;
+        if (jo < total && o < icap) {
+            const int q = S.cl[w][upto - 1];
+            const uint2 id = S.sid[w][q];
+            const uint2 C = S.sgC[w][q];
+            const uint32_t k = jo - id.y;
+            const uint32_t wx = bin_wx(C.y);
+            // k / wx in floating point (k < 2^24), corrected to the exact quotient
+            uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)wx));
+            int32_t rem = (int32_t)(k - ty * wx);
+            if (rem < 0) { --ty; rem += (int32_t)wx; }
+            else if (rem >= (int32_t)wx) { ++ty; rem -= (int32_t)wx; }
+            // quadrants of the tile the ellipse reaches; none: the instance is dead
+            const float4 A = S.sgA[w][q], Bq = S.sgB[w][q];
+            const int uvr = __float_as_int(Bq.w);
+            const float ux = (float)((int)(int16_t)(uvr & 0xFFFF) - rem * TILE) + A.x;
+            const float uy = (float)((uvr >> 16) - (int)ty * TILE) + A.y;
+            const uint32_t qm = quadrant_mask_bands(ux, uy, A.z, A.w, Bq.x, Bq.y, Bq.z, qc);
+            const uint32_t tile = qm ? C.x + ty * bin_tiles_x(C.y) + (uint32_t)rem : dead_tile;
+            ikey[o] = tile | (qm << QMASK_SHIFT);
+            ival[o] = id.x;
+        }
+        started += (uint32_t)__popcll(P);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Offsets from a scan done before (ioff[i]: first output of depth-ordered
+// record i; the scan has set the instance totals and the overflow flag, and
+// nothing is emitted on overflow).  Waves take chunks of 64 records in turn.
+__global__ __launch_bounds__(WG) void k_emit_scanned(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
+                                                     const uint32_t *__restrict__ ioff,
+                                                     const Status *__restrict__ st, float qcut, uint32_t dead_tile,
+                                                     uint32_t *__restrict__ ikey, uint32_t *__restrict__ ival) {
+    __shared__ EmitLds S;
     if (st->overflow) return;
     const uint64_t n = st->R_eff;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -838,73 +914,147 @@ __global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, 
     const float qc = band_threshold(qcut), sq = sqrtf(qc);
     for (uint64_t c = (uint64_t)blockIdx.x * WAVES + w; c * 64 < n; c += nwaves) {
         const uint64_t i = c * 64 + lane;
-        const bool valid = i < n;
         uint32_t r = 0, o = 0, nt = 0;
         Bin B = {};
-        if (valid) {
+        if (i < n) {
             r = sval[i];
             B = bin[r];
             o = ioff[i];
             nt = bin_ntiles(B.dims);
         }
         const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
-        const uint32_t rel = o - o0;
-        const bool owns = valid && nt > 0;
-        const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
-        if (owns) cl[w][lanes_below(own)] = (uint8_t)lane;
-        sid[w][lane] = make_uint2(r, rel);
-        if (owns) {
-            const EllipseBands E = ellipse_bands(B.l11, B.l21, B.l22, sq);
-            sgA[w][lane] = make_float4(B.fx, B.fy, E.kx, E.ia);
-            sgB[w][lane] = make_float4(B.l22, E.eyR, E.hy, __int_as_float(B.uvr));
-            sgC[w][lane] = make_uint2(B.tile0, B.dims);
+        emit_chunk(S, w, lane, r, B, nt, o - o0, o0, ~0ull, qc, sq, dead_tile, ikey, ival);
+    }
+}
+
+// Offsets found by the kernel itself.  A block starts by taking a ticket (the
+// order in which blocks begin) and with it the next EMIT_RPB records in depth
+// order; it reads their binning lines, sums their tile counts, posts that sum
+// and then the sum of all earlier blocks, which it learns by looking back
+// over what the blocks with smaller tickets posted: a single-pass scan with
+// decoupled look-back (Merrill and Garland, "Single-pass parallel prefix scan
+// with decoupled look-back", NVIDIA technical report NVR-2016-002).  A block
+// with a smaller ticket started earlier, so it is running or done, and it
+// posts its own sum before it waits for anything: every wait ends.
+// Post words: bits 62-63 the kind (0 nothing yet, 1 the block's own sum,
+// 2 the sum of it and every earlier block), bits 0-61 the value.  Within a
+// block, wave w owns chunks 4w .. 4w + 3.  The block holding the last record
+// sets the instance totals and the overflow flag; outputs past the capacity
+// are not written.
+constexpr int EMIT_CHUNKS = 4;                       // chunks of 64 records per wave
+constexpr int EMIT_RPB = WG * EMIT_CHUNKS;           // records per block
+constexpr unsigned long long LB_AGG = 1ull << 62, LB_INCL = 2ull << 62, LB_VALUE = (1ull << 62) - 1ull;
+
+// A post word carries everything its reader needs (kind and value in one
+// 64-bit atomic), and nothing else is published through it, so the posts
+// and reads are relaxed atomics at device scope: coherent across the XCDs'
+// L2 caches without the L2 write-back / invalidate that release and acquire
+// ordering would add to every post and every read of the spin.
+__device__ __forceinline__ void lb_post(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long lb_read(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(WG) void k_emit(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
+                                             unsigned long long *__restrict__ lb, Status *__restrict__ st,
+                                             uint64_t icap, float qcut, uint32_t dead_tile,
+                                             uint32_t *__restrict__ ikey, uint32_t *__restrict__ ival) {
+    __shared__ EmitLds S;
+    __shared__ uint32_t wsum[WAVES];       // tile counts of each wave's records
+    __shared__ uint32_t sticket;
+    __shared__ unsigned long long sbase;   // instances of all earlier blocks
+    if (st->overflow) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) sticket = atomicAdd(&st->emit_ticket, 1u);
+    __syncthreads();
+    const uint32_t blk = sticket;
+    const uint64_t n = st->R_eff;
+    const uint64_t first = (uint64_t)blk * EMIT_RPB;
+    if (first >= n) return;                // the whole block: no record left for this ticket
+    // this lane's records, their binning lines and tile counts
+    uint32_t r[EMIT_CHUNKS], nt[EMIT_CHUNKS], pre[EMIT_CHUNKS];
+    Bin B[EMIT_CHUNKS];
+    uint32_t wtot = 0;
+#pragma unroll
+    for (int j = 0; j < EMIT_CHUNKS; ++j) {
+        const uint64_t i = first + (uint64_t)(w * EMIT_CHUNKS + j) * 64 + lane;
+        r[j] = 0;
+        nt[j] = 0;
+        B[j] = Bin{};
+        if (i < n) {
+            r[j] = sval[i];
+            B[j] = bin[r[j]];
+            nt[j] = bin_ntiles(B[j].dims);
         }
-        // total outputs of the wave = end of the last record that owns tiles
-        uint32_t total = 0;
-        if (own) {
-            const int last = 63 - __builtin_clzll(own);
-            total = __shfl(rel + nt, last);
+        // inclusive scan over the wave's lanes, then exclusive with the
+        // chunk's offset inside the wave
+        uint32_t inc = nt[j];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
         }
-        uint32_t started = 0;   // records (owning tiles) that start before the chunk
-        for (uint32_t J = 0; J < total; J += 64) {
-            mk[w][lane] = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (owns && rel >= J && rel < J + 64) mk[w][rel - J] = 1;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const unsigned long long P = __builtin_amdgcn_ballot_w64(mk[w][lane] != 0);
-            const uint32_t upto = started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull);
-            const uint32_t j = J + lane;
-            if (j < total) {
-                const int q = cl[w][upto - 1];
-                const uint2 id = sid[w][q];
-                const uint2 C = sgC[w][q];
-                const uint32_t k = j - id.y;
-                const uint32_t wx = bin_wx(C.y);
-                // k / wx in floating point (k < 2^24), corrected to the exact quotient
-                uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)wx));
-                int32_t rem = (int32_t)(k - ty * wx);
-                if (rem < 0) { --ty; rem += (int32_t)wx; }
-                else if (rem >= (int32_t)wx) { ++ty; rem -= (int32_t)wx; }
-                // quadrants of the tile the ellipse reaches; none: the instance is dead
-                const float4 A = sgA[w][q], Bq = sgB[w][q];
-                const int uvr = __float_as_int(Bq.w);
-                const float ux = (float)((int)(int16_t)(uvr & 0xFFFF) - rem * TILE) + A.x;
-                const float uy = (float)((uvr >> 16) - (int)ty * TILE) + A.y;
-                const uint32_t qm = quadrant_mask_bands(ux, uy, A.z, A.w, Bq.x, Bq.y, Bq.z, qc);
-                const uint32_t tile = qm ? C.x + ty * bin_tiles_x(C.y) + (uint32_t)rem : dead_tile;
-                ikey[o0 + j] = tile | (qm << QMASK_SHIFT);
-                ival[o0 + j] = id.x;
+        pre[j] = wtot + inc - nt[j];
+        wtot += __shfl(inc, 63);
+    }
+    if (lane == 0) wsum[w] = wtot;
+    __syncthreads();
+    uint32_t wbase = 0, btot = 0;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) {
+        wbase += q < w ? wsum[q] : 0u;
+        btot += wsum[q];
+    }
+    // post this block's sum; learn the sum of all earlier blocks
+    if (w == 0) {
+        if (blk == 0) {
+            if (lane == 0) {
+                lb_post(&lb[0], LB_INCL | (unsigned long long)btot);
+                sbase = 0;
             }
-            started += (uint32_t)__popcll(P);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        } else {
+            if (lane == 0) lb_post(&lb[blk], LB_AGG | (unsigned long long)btot);
+            unsigned long long acc = 0;
+            int64_t j = (int64_t)blk - 1;      // the newest earlier block not yet added
+            while (true) {
+                const int64_t jj = j - lane;
+                unsigned long long word = jj >= 0 ? lb_read(&lb[jj]) : LB_INCL;
+                const unsigned long long incl = __builtin_amdgcn_ballot_w64((word >> 62) == 2ull);
+                const unsigned long long empty = __builtin_amdgcn_ballot_w64((word >> 62) == 0ull);
+                // lanes up to the first inclusive one (all lanes if none)
+                const int stop = incl ? __builtin_ctzll(incl) : 63;
+                const unsigned long long need = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
+                if (empty & need) continue;    // an earlier block has not posted yet: read again
+                unsigned long long v = lane <= stop ? (word & LB_VALUE) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                acc += v;
+                if (incl) break;
+                j -= 64;
+            }
+            if (lane == 0) {
+                lb_post(&lb[blk], LB_INCL | ((acc + btot) & LB_VALUE));
+                sbase = acc;
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const unsigned long long base = sbase;
+    if (threadIdx.x == 0 && first + EMIT_RPB >= n) {   // the block holding the last record: the totals
+        const unsigned long long tot = base + btot;
+        st->M_total = tot;
+        st->M_eff = (uint32_t)(tot < icap ? tot : icap);
+        if (tot > icap) st->overflow |= 2u;
+    }
+    const float qc = band_threshold(qcut), sq = sqrtf(qc);
+#pragma unroll
+    for (int j = 0; j < EMIT_CHUNKS; ++j) {
+        const uint32_t p0 = __shfl(pre[j], 0);
+        emit_chunk(S, w, lane, r[j], B[j], nt[j], pre[j] - p0, base + wbase + p0, icap, qc, sq, dead_tile, ikey,
+                   ival);
     }
 }
 
@@ -1111,9 +1261,21 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
 }
 
 
-void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
-                 uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
+size_t emit_post_words(uint64_t rcap) { return (size_t)((rcap + EMIT_RPB - 1) / EMIT_RPB) + 1; }
+
+void launch_emit_scanned(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
+                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit_scanned, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
+}
+
+void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, Status *st, uint64_t rcap,
+                 uint64_t icap, float qcut, uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
+    // the post words start empty (a fill kernel, not a memset: the sequence
+    // may be captured in a graph); st->emit_ticket was cleared with the status
+    const size_t words = emit_post_words(rcap);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(lb), 2 * (uint64_t)words, 0u, s);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)words), dim3(WG), 0, s, sval, bin, lb, st, icap, qcut, dead_tile,
+                       ikey, ival);
 }
 
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s) {

@@ -104,9 +104,26 @@ bool finite_cam(const gv_camera &c) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t status, views, cnt, vmask, offs, blk, rec, bin, ntr, key0, val0, key1, val1, icnt, ioff;
-    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, rz, total;
+    size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, ntr, icnt, ioff, post;
+    size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, rz;
+    size_t dc_flags, dc_offs, dc_tmp, dc_misc;   // density control (kind 2)
+    size_t total;
 };
+
+// Which emission a plan runs.  The scanned one gathers each depth-ordered
+// record's tile count in the last depth-sort pass and scans the counts before
+// it emits: two random 32-byte reads per record, cheap while the records'
+// binning lines stay in the 256 MB last-level cache, and its waves take
+// chunks of records in turn, which balances records with many tiles.  The
+// look-back one reads each binning line once and finds its offsets itself:
+// it pays off where the binning lines (32 bytes per record) far exceed that
+// cache and records have few tiles each.
+int emit_mode_for(const gv_workspace &p) {
+    return (uint64_t)p.max_records * sizeof(Bin) > ((uint64_t)256 << 20) && p.max_instances <= 4 * p.max_records
+               ? 2 : 1;
+}
+
+bool emit_lookback(const gv_workspace &p) { return (p.emit_mode == 0 ? emit_mode_for(p) : p.emit_mode) == 2; }
 
 Layout make_layout(const gv_workspace &p) {
     Layout L{};
@@ -124,16 +141,21 @@ Layout make_layout(const gv_workspace &p) {
     L.cnt = take(N * PROJ_SPLIT * 4);
     L.vmask = take(N * PROJ_SPLIT * (uint64_t)mask_words((int)V) * 4);
     L.offs = take((N * PROJ_SPLIT + 1) * 4);
-    L.blk = take(scan_blk_count(std::max(N * PROJ_SPLIT, R)) * 8);
+    const bool lookback = emit_lookback(p);
+    L.blk = take(scan_blk_count(lookback ? N * PROJ_SPLIT : std::max(N * PROJ_SPLIT, R)) * 8);
     L.rec = take(R * sizeof(Rec));
     L.bin = take(R * sizeof(Bin));
-    L.ntr = take(R * 4);
     L.key0 = take(R * 4);
     L.val0 = take(R * 4);
     L.key1 = take(R * 4);
     L.val1 = take(R * 4);
-    L.icnt = take(R * 4);
-    L.ioff = take((R + 1) * 4);
+    if (lookback) {
+        L.post = take(emit_post_words(R) * 8);
+    } else {
+        L.ntr = take(R * 4);
+        L.icnt = take(R * 4);
+        L.ioff = take((R + 1) * 4);
+    }
     L.ikey0 = take(M * 4);
     L.ival0 = take(M * 4);
     L.ikey1 = take(M * 4);
@@ -141,10 +163,16 @@ Layout make_layout(const gv_workspace &p) {
     L.ranges = take(T * 8);
     L.hist = take((size_t)RADIX * RADIX_BLOCKS * 4);
     L.dtot = take((size_t)RADIX * 4);
-    if (p.kind == 0) {
+    if (p.kind == 0 || p.kind == 2) {
         L.accT = take(R * 4);
         L.accC = take(R * 4);
         L.gam32 = take(N * (uint64_t)K * 4);
+        if (p.kind == 2) {   // the pruning of the virtual particles (at most n of them)
+            L.dc_flags = take((N + 1) * 4);
+            L.dc_offs = take((N + 1) * 4);
+            L.dc_tmp = take(N * 11 * 4);
+            L.dc_misc = take(64);
+        }
     } else {
         L.tpart = take(T * 4);
         L.rcc = take(R * 4);
@@ -229,7 +257,7 @@ struct gv_context {
     unsigned char *scratch = nullptr;
     std::string scratch_err;
     bool capturing = false;
-    gv_tuning tuning = {64, 256};
+    gv_tuning tuning = {64, 256, 0, 0};
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     // stage timing
     bool prof_on = false;
@@ -369,7 +397,9 @@ static gv_status measure(gv_context *ctx, const gv_gaussians *g, const std::vect
 static gv_status plan_check(const gv_workspace *plan, const void *ws, int kind, int64_t n, int32_t nv,
                             int64_t tiles, int64_t pixels) {
     if (!plan || !ws) return fail(GV_ERR_INVALID_ARG, "NULL workspace or plan");
-    if (plan->kind != kind) return fail(GV_ERR_INVALID_ARG, "workspace plan made for the other call");
+    // a density-control plan (kind 2) holds the build layout and more
+    if (plan->kind != kind && !(kind == 0 && plan->kind == 2))
+        return fail(GV_ERR_INVALID_ARG, "workspace plan made for another call");
     if (plan->n != n) return fail(GV_ERR_INVALID_ARG, "workspace plan made for n=%lld, got %lld",
                                   (long long)plan->n, (long long)n);
     if (nv > plan->n_views || tiles > plan->total_tiles || pixels > plan->total_pixels)
@@ -379,6 +409,7 @@ static gv_status plan_check(const gv_workspace *plan, const void *ws, int kind, 
     if (plan->max_records < 0 || plan->max_instances < 0 || plan->max_records > 0x7fffffffLL ||
         plan->max_instances > 0x7fffffffLL)
         return fail(GV_ERR_INVALID_ARG, "workspace capacities out of range");
+    if (plan->emit_mode < 0 || plan->emit_mode > 2) return fail(GV_ERR_INVALID_ARG, "emit_mode must be 0, 1 or 2");
     if (plan->bytes < make_layout(*plan).total) return fail(GV_ERR_CAPACITY, "workspace plan bytes too small");
     return GV_OK;
 }
@@ -398,10 +429,12 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     unsigned long long *blk = at<unsigned long long>(ws, L.blk);
     Rec *rec = at<Rec>(ws, L.rec);
     Bin *bin = at<Bin>(ws, L.bin);
-    uint32_t *ntr = at<uint32_t>(ws, L.ntr);
     uint32_t *k0 = at<uint32_t>(ws, L.key0), *v0 = at<uint32_t>(ws, L.val0);
     uint32_t *k1 = at<uint32_t>(ws, L.key1), *v1 = at<uint32_t>(ws, L.val1);
-    uint32_t *icnt = at<uint32_t>(ws, L.icnt), *ioff = at<uint32_t>(ws, L.ioff);
+    const bool lookback = emit_lookback(p);
+    unsigned long long *post = lookback ? at<unsigned long long>(ws, L.post) : nullptr;
+    uint32_t *ntr = lookback ? nullptr : at<uint32_t>(ws, L.ntr);
+    uint32_t *icnt = lookback ? nullptr : at<uint32_t>(ws, L.icnt), *ioff = lookback ? nullptr : at<uint32_t>(ws, L.ioff);
     uint32_t *ik0 = at<uint32_t>(ws, L.ikey0), *iv0 = at<uint32_t>(ws, L.ival0);
     uint32_t *ik1 = at<uint32_t>(ws, L.ikey1), *iv1 = at<uint32_t>(ws, L.ival1);
     uint2 *ranges = at<uint2>(ws, L.ranges);
@@ -422,16 +455,22 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     int dres;
     {
         StageScope sc(ctx, ST_SORT_DEPTH, s);
-        // the last pass also gathers each record's tile count into depth order
+        // scanned emission: the last pass also gathers each record's tile
+        // count into depth order
         dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R, ntr,
                                  icnt);
     }
     const uint32_t *sval = dres ? v1 : v0;
     {
         StageScope sc(ctx, ST_EMIT, s);
-        launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
+        const float qc = (float)(0.5 * geo.cut / std::log(2.0));
         launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
-        launch_emit(sval, bin, ioff, st, (float)(0.5 * geo.cut / std::log(2.0)), (uint32_t)tiles, ik0, iv0, s);
+        if (lookback) {
+            launch_emit(sval, bin, post, st, R, M, qc, (uint32_t)tiles, ik0, iv0, s);
+        } else {
+            launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
+            launch_emit_scanned(sval, bin, ioff, st, qc, (uint32_t)tiles, ik0, iv0, s);
+        }
     }
     int tres;
     {
@@ -541,8 +580,16 @@ size_t gv_workspace_bytes(const gv_workspace *plan) {
     return make_layout(*plan).total;
 }
 
+static gv_status build_plan(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                            const gv_vf_params *prm, gv_workspace *plan, void *hip_stream);
+
 gv_status vf_build_workspace_size(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
                                   const gv_vf_params *prm, gv_workspace *plan, void *hip_stream) {
+    return build_plan(ctx, g, train, n_train, prm, plan, hip_stream);
+}
+
+static gv_status build_plan(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
+                            const gv_vf_params *prm, gv_workspace *plan, void *hip_stream) {
     if (!ctx || !prm || !plan) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     GV_TRY(check_gauss(g));
     if (n_train < 0 || (n_train > 0 && !train)) return fail(GV_ERR_INVALID_ARG, "bad training views");
@@ -572,6 +619,7 @@ gv_status vf_build_workspace_size(gv_context *ctx, const gv_gaussians *g, const 
     }
     if (plan->max_records > 0x7fffffffLL || plan->max_instances > 0x7fffffffLL)
         return fail(GV_ERR_CAPACITY, "one pass needs more than 2^31 records or instances; lower views_per_pass");
+    plan->emit_mode = emit_mode_for(*plan);
     plan->bytes = make_layout(*plan).total;
     return GV_OK;
 }
@@ -602,6 +650,7 @@ gv_status vf_query_workspace_size(gv_context *ctx, const gv_gaussians *g, const 
     plan->total_pixels = pixels;
     if (plan->max_records > 0x7fffffffLL || plan->max_instances > 0x7fffffffLL)
         return fail(GV_ERR_CAPACITY, "more than 2^31 records or instances in one call; split the views");
+    plan->emit_mode = emit_mode_for(*plan);
     plan->bytes = make_layout(*plan).total;
     return GV_OK;
 }
@@ -672,7 +721,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -743,7 +792,7 @@ static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const g
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -777,6 +826,118 @@ gv_status vf_multiview_visibility(gv_context *ctx, const gv_gaussians *g, const 
                                   const gv_vf_params *prm, float *visibility, const gv_workspace *plan,
                                   void *workspace, void *hip_stream) {
     return view_visibility(ctx, g, train, n_train, prm, visibility, true, plan, workspace, hip_stream);
+}
+
+// Alg. 5's particle count and scale from the box and density: N_virt =
+// floor(rho * volume), (4/3) pi s^3 rho = 1 + eta.
+static gv_status virtual_count(const gv_density_params *dp, int64_t *nv, double *s) {
+    if (!dp) return fail(GV_ERR_INVALID_ARG, "NULL density parameters");
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (!(std::isfinite(dp->lo[k]) && std::isfinite(dp->hi[k]) && dp->hi[k] > dp->lo[k]))
+            return fail(GV_ERR_INVALID_ARG, "empty or non-finite box along axis %d", k);
+        vol *= (double)dp->hi[k] - (double)dp->lo[k];
+    }
+    if (!(std::isfinite(dp->rho) && dp->rho > 0.f && std::isfinite(dp->eta) && dp->eta > -1.f &&
+          std::isfinite(dp->eps_v)))
+        return fail(GV_ERR_INVALID_ARG, "density parameters out of range");
+    const double cnt = std::floor((double)dp->rho * vol);
+    if (cnt > (double)(((int64_t)1 << 31) - 2)) return fail(GV_ERR_CAPACITY, "too many virtual particles");
+    *nv = (int64_t)cnt;
+    *s = std::cbrt(3.0 * (1.0 + (double)dp->eta) / (4.0 * M_PI * (double)dp->rho));
+    return GV_OK;
+}
+
+// Checks of the density-control arguments shared by the sizing call and the
+// call itself; writes the virtual particles into rows n_real.. of g.
+static gv_status place_virtual(const gv_gaussians *g, int64_t n_real, const float *u, int64_t n_draw,
+                               const gv_density_params *dp, int64_t *nv_out, hipStream_t s) {
+    GV_TRY(check_gauss(g));
+    if (g->dtype != GV_F32) return fail(GV_ERR_UNSUPPORTED, "density control takes FP32 attribute arrays");
+    if (g->n_virtual != 0) return fail(GV_ERR_INVALID_ARG, "every Gaussian is measured: n_virtual must be 0");
+    int64_t nv;
+    double sc;
+    GV_TRY(virtual_count(dp, &nv, &sc));
+    if (n_real < 0 || g->n != n_real + nv)
+        return fail(GV_ERR_INVALID_ARG, "the arrays must hold n_real + N_virt = %lld + %lld rows, n = %lld",
+                    (long long)n_real, (long long)nv, (long long)g->n);
+    if (n_draw < nv || (nv > 0 && !u)) return fail(GV_ERR_INVALID_ARG, "%lld uniform draws for %lld particles",
+                                                   (long long)n_draw, (long long)nv);
+    VirtArgs va;
+    for (int k = 0; k < 3; ++k) {
+        va.lo[k] = (double)dp->lo[k];
+        va.span[k] = (double)dp->hi[k] - (double)dp->lo[k];
+    }
+    va.s = (float)sc;
+    launch_place_virtual((float *)g->means, (float *)g->scales, (float *)g->quats, (float *)g->opacity, u, n_real, nv,
+                         va, s);
+    GV_HIP(hipGetLastError());
+    *nv_out = nv;
+    return GV_OK;
+}
+
+gv_status vf_virtual_particle_count(const gv_density_params *dp, int64_t *n_virt, float *scale) {
+    int64_t nv;
+    double sc;
+    GV_TRY(virtual_count(dp, &nv, &sc));
+    if (n_virt) *n_virt = nv;
+    if (scale) *scale = (float)sc;
+    return GV_OK;
+}
+
+gv_status vf_density_control_workspace_size(gv_context *ctx, const gv_gaussians *g, int64_t n_real, const float *u,
+                                            int64_t n_draw, const gv_density_params *dp, const gv_camera *train,
+                                            int32_t n_train, const gv_vf_params *prm, gv_workspace *plan,
+                                            int64_t *n_virt, void *hip_stream) {
+    if (!ctx || !prm || !plan) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    int64_t nv;
+    GV_TRY(place_virtual(g, n_real, u, n_draw, dp, &nv, (hipStream_t)hip_stream));
+    GV_TRY(build_plan(ctx, g, train, n_train, prm, plan, hip_stream));
+    plan->kind = 2;
+    plan->bytes = make_layout(*plan).total;
+    if (n_virt) *n_virt = nv;
+    return GV_OK;
+}
+
+gv_status vf_density_control(gv_context *ctx, const gv_gaussians *g, int64_t n_real, const float *u, int64_t n_draw,
+                             const gv_density_params *dp, const gv_camera *train, int32_t n_train,
+                             const gv_vf_params *prm, float *visibility, int32_t *kept, int64_t *n_kept,
+                             const gv_workspace *plan, void *workspace, void *hip_stream) {
+    if (!ctx || !prm || !n_kept) return fail(GV_ERR_INVALID_ARG, "NULL argument");
+    if (!plan || plan->kind != 2 || !workspace) return fail(GV_ERR_INVALID_ARG, "needs a density-control plan");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    *n_kept = 0;
+    int64_t nv;
+    GV_TRY(place_virtual(g, n_real, u, n_draw, dp, &nv, s));
+    if (g->n > 0 && !visibility) return fail(GV_ERR_INVALID_ARG, "visibility is NULL");
+    if (nv > 0 && !kept) return fail(GV_ERR_INVALID_ARG, "kept is NULL");
+    if (g->n > plan->n) return fail(GV_ERR_INVALID_ARG, "plan made for fewer Gaussians");
+    GV_TRY(view_visibility(ctx, g, train, n_train, prm, visibility, true, plan, workspace, hip_stream));
+    if (nv == 0) return GV_OK;
+    const Layout Lay = make_layout(*plan);
+    uint32_t *flags = at<uint32_t>(workspace, Lay.dc_flags), *offs = at<uint32_t>(workspace, Lay.dc_offs);
+    float *tmp = at<float>(workspace, Lay.dc_tmp);
+    unsigned long long *tot = at<unsigned long long>(workspace, Lay.dc_misc);
+    uint32_t *eff = reinterpret_cast<uint32_t *>(tot + 1), *ovf = eff + 1;
+    float *means = (float *)g->means, *scales = (float *)g->scales, *quats = (float *)g->quats,
+          *opac = (float *)g->opacity;
+    launch_fill_u32(ovf, 1, 0u, s);
+    launch_virtual_flags(visibility, n_real, nv, dp->eps_v, flags, s);
+    launch_scan(flags, offs, nullptr, (uint64_t)nv, (uint64_t)nv, at<unsigned long long>(workspace, Lay.blk), tot, eff,
+                (uint64_t)nv, ovf, 1u, s);
+    launch_virtual_pack(flags, offs, n_real, nv, means, scales, quats, opac, kept, tmp, s);
+    unsigned long long h = 0;
+    Status hs;
+    GV_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    GV_HIP(hipMemcpyAsync(&hs, at<Status>(workspace, Lay.status), sizeof(hs), hipMemcpyDeviceToHost, s));
+    GV_HIP(hipStreamSynchronize(s));
+    if (hs.overflow) return fail(GV_ERR_CAPACITY, "workspace too small for the density control's views");
+    launch_virtual_store(tmp, n_real, (int64_t)h, means, scales, quats, opac, s);
+    GV_HIP(hipGetLastError());
+    *n_kept = (int64_t)h;
+    return GV_OK;
 }
 
 gv_status vf_view_visibility(gv_context *ctx, const gv_gaussians *g, const gv_camera *train, int32_t n_train,
@@ -849,7 +1010,7 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
                              bz.ival, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
-                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, s);
+                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, ctx->tuning.uq_order, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
         return GV_OK;
@@ -869,7 +1030,7 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
         const void *ws, *gamma, *vtrain, *tc, *cvar, *scores, *maps, *means, *scales, *quats, *opac, *anchors;
         int64_t n, n_virtual, tiles, pixels;
         gv_workspace plan;
-        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, ntv, csh, depth;
+        int32_t mode, n_cand, sh, gdt, dtype, anchor_block, count, uq_batch, uq_order, ntv, csh, depth;
         float f[10];
     } key;
     std::memset(&key, 0, sizeof(key));
@@ -880,7 +1041,8 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     key.n = g->n; key.n_virtual = g->n_virtual; key.tiles = tiles; key.pixels = pixels;
     key.plan = *plan;
     key.mode = q.mode; key.n_cand = n_cand; key.sh = q.sh_degree; key.gdt = q.gamma_dtype; key.dtype = (int)g->dtype;
-    key.anchor_block = g->anchor_block; key.count = prm->count_pairs; key.uq_batch = ctx->tuning.uq_batch;
+    key.anchor_block = g->anchor_block; key.count = prm->count_pairs;
+    key.uq_batch = ctx->tuning.uq_batch; key.uq_order = ctx->tuning.uq_order;
     key.ntv = q.n_train_views;
     const float fv[10] = {prm->beta, prm->o0, prm->half_logdet_Q0, prm->half_logdet_Qc, prm->eps_T, prm->znear,
                           prm->lowpass, prm->cut, q.n_train, q.kappa};
@@ -1097,6 +1259,8 @@ gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t) {
     if (!ctx || !t) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
     if (!ok(t->vis_batch) || !ok(t->uq_batch)) return fail(GV_ERR_INVALID_ARG, "batch sizes must be 64, 128 or 256");
+    if (t->vis_order < 0 || t->vis_order > 1 || t->uq_order < 0 || t->uq_order > 1)
+        return fail(GV_ERR_INVALID_ARG, "tile orders must be 0 or 1");
     ctx->tuning = *t;
     return GV_OK;
 }

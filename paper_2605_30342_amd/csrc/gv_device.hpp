@@ -93,7 +93,7 @@ struct Status {
     uint32_t overflow;            // bit 0 records, bit 1 instances
     int32_t best;                 // argmax scratch
     uint32_t M_live;              // instances left after the tile sort drops dead ones
-    uint32_t pad0;
+    uint32_t emit_ticket;         // next record block of the instance emission
     unsigned long long measure[4];
 };
 

@@ -80,25 +80,49 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
                       uint64_t n_cap, const uint32_t *gather_src = nullptr, uint32_t *gather_dst = nullptr);
 void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
+// Density control (Alg. 5): box corner and sides in FP64, particle scale.
+struct VirtArgs {
+    double lo[3], span[3];
+    float s;
+};
+void launch_place_virtual(float *means, float *scales, float *quats, float *opac, const float *u, int64_t n_real,
+                          int64_t nv, const VirtArgs &v, hipStream_t s);
+void launch_virtual_flags(const float *vis, int64_t n_real, int64_t nv, float eps_v, uint32_t *flags, hipStream_t s);
+void launch_virtual_pack(const uint32_t *flags, const uint32_t *offs, int64_t n_real, int64_t nv, const float *means,
+                         const float *scales, const float *quats, const float *opac, int32_t *kept, float *tmp,
+                         hipStream_t s);
+void launch_virtual_store(const float *tmp, int64_t n_real, int64_t n_kept, float *means, float *scales, float *quats,
+                          float *opac, hipStream_t s);
 void launch_vis_logsum(int64_t n, const uint32_t *offs, const float *acc_T, const uint32_t *acc_c, const Status *st,
                        float *out, bool accumulate, unsigned long long *pairs, hipStream_t s);
 void launch_vis_finish(int64_t n, float *out, hipStream_t s);
 void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *vmask, int mw, const float *acc_T,
                      const uint32_t *acc_c, const Status *st, float *out, unsigned long long *pairs, hipStream_t s);
-void launch_emit(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
-                 uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
+// Instances of the first st->R_eff depth-ordered records (sval) at the output
+// offsets ioff of a scan done before (nothing on overflow).
+void launch_emit_scanned(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
+                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
+// Post words the instance emission needs for rcap records (its look-back).
+size_t emit_post_words(uint64_t rcap);
+// Instances of the first st->R_eff depth-ordered records (sval) into
+// (ikey, ival), at most icap of them; sets st->M_total, M_eff and the
+// instance overflow bit.  lb: emit_post_words(rcap) words of workspace.
+void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, Status *st, uint64_t rcap,
+                 uint64_t icap, float qcut, uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s);
 
+// order: tile schedule of the blend's workgroups (0 linear, 1 contiguous runs
+// of tiles per XCD); batch: records staged per LDS batch (64, 128, 256)
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                       int batch, hipStream_t s);
+                       int batch, int order, hipStream_t s);
 // rcc: per-record colour constants c_c (NULL: the uniform u.cQc); rz and
 // dmaps: per-record depths and the expected-depth maps (both NULL: none;
 // depth maps need maps)
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
-                      hipStream_t s);
+                      int order, hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);

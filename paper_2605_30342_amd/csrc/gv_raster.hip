@@ -139,6 +139,22 @@ __device__ __forceinline__ int pad_slot(int n) {
     return k < ((n + LPAD - 1) / LPAD) * LPAD ? k : -1;
 }
 
+// ---------------------------------------------------------------- tile schedule
+
+// Tile blended by workgroup b of a grid of T.  The workgroups of a launch are
+// dealt to the eight XCDs in turn (b mod 8), and each XCD has its own L2.
+// order 0: workgroup b takes tile b, so neighbouring tiles, which share most
+// of their records, run on different XCDs and every XCD's L2 fetches them;
+// order 1: XCD x takes a contiguous run of the tile ids (row-major tiles of
+// one view after another), so neighbours share an L2.  A bijection of
+// [0, T): XCD x holds the ceil((T - x) / 8) workgroups x, x + 8, ...
+__device__ __forceinline__ int tile_of_block(int b, int T, int order) {
+    if (order == 0) return b;
+    const int x = b & 7, k = b >> 3;
+    const int per = T >> 3, rem = T & 7;
+    return x * per + min(x, rem) + k;
+}
+
 // ---------------------------------------------------------------- VF CONST raster (Alg. 2)
 
 // Contributions of LGROUP consecutive list entries are kept per lane (acc[])
@@ -151,7 +167,7 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
                                                    const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
                                                    const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
-                                                   uint32_t *__restrict__ acc_c) {
+                                                   uint32_t *__restrict__ acc_c, int order) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
@@ -162,7 +178,7 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
     __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
     __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
 
-    const int gt = blockIdx.x;
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, order);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -388,7 +404,8 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                                                   const Rec *__restrict__ rec, const float *__restrict__ rcc,
                                                   const float *__restrict__ rz,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
-                                                  float *__restrict__ dmaps, unsigned long long *__restrict__ pairs) {
+                                                  float *__restrict__ dmaps, unsigned long long *__restrict__ pairs,
+                                                  int order) {
     constexpr int NL = 4 * WAVES;          // sub-block lists per tile
     __shared__ float4 wA[RB + 1];          // ux, uy, l11, l21 per batch slot (slot RB: never hit)
     __shared__ float4 wB[RB + 1];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     __shared__ BatchCounts<NL> bc;         // per sub-block list: counts of the four waves
     __shared__ float red[WAVES];
 
-    const int gt = blockIdx.x;
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, order);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -774,6 +791,111 @@ void launch_vis_finish(int64_t n, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_vis_finish, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, n, out);
 }
 
+// ---------------------------------------------------------------- density control (Alg. 5)
+
+// Virtual particle i of nv at lo + u_i (hi - lo), formed in FP64 (the product
+// of the FP32 draw and the FP32 box side is exact there) and stored in FP32
+// like every Gaussian attribute; isotropic scale s, identity rotation,
+// opacity 0: rows n_real + i of the FP32 attribute arrays.
+__global__ __launch_bounds__(WG) void k_place_virtual(float *__restrict__ means, float *__restrict__ scales,
+                                                      float *__restrict__ quats, float *__restrict__ opac,
+                                                      const float *__restrict__ u, int64_t n_real, int64_t nv,
+                                                      VirtArgs v) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= nv) return;
+    const int64_t g = n_real + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        means[3 * g + k] = (float)fma((double)u[3 * i + k], v.span[k], v.lo[k]);
+        scales[3 * g + k] = v.s;
+    }
+    quats[4 * g] = 1.0f;
+    quats[4 * g + 1] = 0.0f;
+    quats[4 * g + 2] = 0.0f;
+    quats[4 * g + 3] = 0.0f;
+    opac[g] = 0.0f;
+}
+
+// flags[i] = 1 where particle i is kept: its multi-view visibility is at most
+// eps_v (Alg. 5's pruning rule).
+__global__ __launch_bounds__(WG) void k_virtual_flags(const float *__restrict__ vis, int64_t n_real, int64_t nv,
+                                                      float eps_v, uint32_t *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < nv) flags[i] = vis[n_real + i] <= eps_v ? 1u : 0u;
+}
+
+// The kept particles in draw order: kept[offs[i]] = i, and their attributes
+// packed into rows offs[i] of tmp (11 floats: mean, scale, quaternion,
+// opacity).
+__global__ __launch_bounds__(WG) void k_virtual_pack(const uint32_t *__restrict__ flags,
+                                                     const uint32_t *__restrict__ offs, int64_t n_real, int64_t nv,
+                                                     const float *__restrict__ means, const float *__restrict__ scales,
+                                                     const float *__restrict__ quats, const float *__restrict__ opac,
+                                                     int32_t *__restrict__ kept, float *__restrict__ tmp) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= nv || !flags[i]) return;
+    const uint32_t j = offs[i];
+    const int64_t g = n_real + i;
+    kept[j] = (int32_t)i;
+    float *t = tmp + (int64_t)j * 11;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t[k] = means[3 * g + k];
+        t[3 + k] = scales[3 * g + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[6 + k] = quats[4 * g + k];
+    t[10] = opac[g];
+}
+
+// Rows n_real .. n_real + n_kept - 1 of the attribute arrays <- the packed
+// kept particles.
+__global__ __launch_bounds__(WG) void k_virtual_store(const float *__restrict__ tmp, int64_t n_real, int64_t n_kept,
+                                                      float *__restrict__ means, float *__restrict__ scales,
+                                                      float *__restrict__ quats, float *__restrict__ opac) {
+    const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (j >= n_kept) return;
+    const int64_t g = n_real + j;
+    const float *t = tmp + j * 11;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        means[3 * g + k] = t[k];
+        scales[3 * g + k] = t[3 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) quats[4 * g + k] = t[6 + k];
+    opac[g] = t[10];
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+void launch_place_virtual(float *means, float *scales, float *quats, float *opac, const float *u, int64_t n_real,
+                          int64_t nv, const VirtArgs &v, hipStream_t s) {
+    if (nv <= 0) return;
+    hipLaunchKernelGGL(k_place_virtual, dim3(blocks_for(nv)), dim3(WG), 0, s, means, scales, quats, opac, u, n_real,
+                       nv, v);
+}
+
+void launch_virtual_flags(const float *vis, int64_t n_real, int64_t nv, float eps_v, uint32_t *flags, hipStream_t s) {
+    if (nv <= 0) return;
+    hipLaunchKernelGGL(k_virtual_flags, dim3(blocks_for(nv)), dim3(WG), 0, s, vis, n_real, nv, eps_v, flags);
+}
+
+void launch_virtual_pack(const uint32_t *flags, const uint32_t *offs, int64_t n_real, int64_t nv, const float *means,
+                         const float *scales, const float *quats, const float *opac, int32_t *kept, float *tmp,
+                         hipStream_t s) {
+    if (nv <= 0) return;
+    hipLaunchKernelGGL(k_virtual_pack, dim3(blocks_for(nv)), dim3(WG), 0, s, flags, offs, n_real, nv, means, scales,
+                       quats, opac, kept, tmp);
+}
+
+void launch_virtual_store(const float *tmp, int64_t n_real, int64_t n_kept, float *means, float *scales, float *quats,
+                          float *opac, hipStream_t s) {
+    if (n_kept <= 0) return;
+    hipLaunchKernelGGL(k_virtual_store, dim3(blocks_for(n_kept)), dim3(WG), 0, s, tmp, n_real, n_kept, means, scales,
+                       quats, opac);
+}
+
 // ---------------------------------------------------------------- dtype conversion
 
 template <typename TS, typename TD>
@@ -805,28 +927,30 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 
 template <int RB>
 static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
-                          const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, hipStream_t s) {
+                          const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
+                          int order, hipStream_t s) {
     hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, ikey, rec, eps_T, qcut,
-                       acc_T, acc_c);
+                       acc_T, acc_c, order);
 }
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
-                       hipStream_t s) {
+                       int order, hipStream_t s) {
     if (total_tiles <= 0) return;
     switch (batch) {
-    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
-    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
-    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, s); break;
+    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
+    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
+    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
     }
 }
 
 template <int RB, bool CC, bool DEPTH>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                          const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
-                         float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
+                         float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
+                         hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
-#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs
+#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order
     if constexpr (DEPTH) {   // depth maps come with the entropy maps
         if (pairs)
             hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true>), g, b, 0, s, GV_UQ_ARGS);
@@ -848,8 +972,9 @@ static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const ui
 template <int RB>
 static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                           const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
-                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, hipStream_t s) {
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
+                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
+                          hipStream_t s) {
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, s
     const bool depth = dmaps && maps && rz;
     if (rcc && depth) raster_uq_rb<RB, true, true>(GV_UQ_ARGS);
     else if (rcc) raster_uq_rb<RB, true, false>(GV_UQ_ARGS);
@@ -861,9 +986,9 @@ static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const u
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
-                      hipStream_t s) {
+                      int order, hipStream_t s) {
     if (total_tiles <= 0) return;
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, s
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, s
     switch (batch) {
     case 64: raster_uq_var<64>(GV_UQ_ARGS); break;
     case 256: raster_uq_var<256>(GV_UQ_ARGS); break;

@@ -109,18 +109,20 @@ class Server:
     def _admit(self) -> None:
         while self.free_slots and self.pending:
             batch = self._form_batch()
+            free = self.budget - self.in_use
             try:
                 nbytes = self.be.plan_bytes(batch[0].scene_id, [r.cams for r in batch])
+                if nbytes > free and len(batch) > 1:
+                    batch = batch[:1]
+                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams])
+                if nbytes > free:
+                    # a request alone whose estimate does not fit may still fit
+                    # at its exact size (asked once per request: the backend
+                    # keeps it while the request waits)
+                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams], limit=free)
             except BackendError as e:
                 self._fail(batch, str(e))
                 continue
-            if nbytes > self.budget - self.in_use and len(batch) > 1:
-                batch = batch[:1]
-                try:
-                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams])
-                except BackendError as e:
-                    self._fail(batch, str(e))
-                    continue
             if nbytes > self.budget:
                 for r in batch:
                     r.status, r.error = REJECTED, f"needs {nbytes} bytes, budget {self.budget}"
@@ -262,9 +264,10 @@ class GpuBackend:
     computed on the host.  Per resident scene and image size the backend
     keeps the largest records and instances per view seen so far (`rates`)
     and plans a batch as the sum over its views of those rates times `slack`
-    (Context.query_plan: no device pass, nothing allocated).  Only a batch
-    holding an image size the scene has not been seen at is sized exactly
-    by the library's counting pass (synchronous, once per scene and size).
+    (Context.query_plan: no device pass, nothing allocated).  A batch holding
+    an image size the scene has not been seen at, or whose estimate exceeds
+    the free budget, is sized exactly by the library's counting pass
+    (synchronous; once per scene and size, once per waiting batch).
     The workspace is allocated when the batch is launched, after admission;
     an allocation failure is a BackendError.  At completion every batch's
     workspace status gives its exact record and instance counts, which
@@ -286,6 +289,7 @@ class GpuBackend:
         self.rates: Dict[tuple, list] = {}      # (scene, w, h) -> [records per view, instances per view]
         self.exact_sizings = 0
         self.relaunches = 0
+        self._exact_plans: Dict[tuple, Any] = {}   # exact plans of batches whose estimate did not fit
 
     def add_scene(self, scene_id, dsc, gamma, sh_degree: int, n_train: int) -> None:
         self.scenes[scene_id] = ResidentScene(dsc, gamma, sh_degree, n_train)
@@ -351,8 +355,22 @@ class GpuBackend:
         ins = sum(self.rates[k][1] for k in keys) * self.slack
         return self.ctx.query_plan(sc.dsc, cams, sc.sh_degree, int(np.ceil(rec)) + 64, int(np.ceil(ins)) + 256)
 
-    def plan_bytes(self, scene_id, cams_list) -> int:
-        return int(self._plan(scene_id, self._cams(cams_list)).bytes)
+    def plan_bytes(self, scene_id, cams_list, limit: Optional[int] = None) -> int:
+        """Workspace bytes of a batch from the learnt rates; when that
+        estimate exceeds `limit` (the free budget), the exact bytes instead
+        (one counting pass, kept for the batch's launch and for later asks
+        while it waits for memory)."""
+        key = (scene_id, tuple(id(c) for c in cams_list))
+        if key in self._exact_plans:
+            return int(self._exact_plans[key].bytes)
+        cams = self._cams(cams_list)
+        plan = self._plan(scene_id, cams)
+        if limit is not None and plan.bytes > limit:
+            plan = self._exact(self.scenes[scene_id], cams)
+            if len(self._exact_plans) >= 64:
+                self._exact_plans.pop(next(iter(self._exact_plans)))
+            self._exact_plans[key] = plan
+        return int(plan.bytes)
 
     def _alloc(self, plan):
         torch = self.torch
@@ -380,7 +398,9 @@ class GpuBackend:
     def launch(self, scene_id, cams_list, slot: int, nbytes: int):
         torch = self.torch
         cams = self._cams(cams_list)
-        plan = self._plan(scene_id, cams)
+        plan = self._exact_plans.pop((scene_id, tuple(id(c) for c in cams_list)), None)
+        if plan is None:
+            plan = self._plan(scene_id, cams)
         ws = self._alloc(plan)
         scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         h = {"scene": scene_id, "cams": cams, "ws": ws, "scores": scores, "stream": self.streams[slot],

@@ -47,13 +47,46 @@ def test_source_hash_covers_every_kernel_source(tmp_path):
 def test_traffic_is_reported_only_for_matching_sources(tmp_path):
     b = _bench_module()
     (tmp_path / "profiles").mkdir()
-    doc = {"raster_vis": {"source_hash": "0123456789abcdef", "bytes_per_launch": 123456}}
+    doc = {"source_hash": "0123456789abcdef",
+           "workloads": {"room": {"build": {"raster_vis": {"read": 100000, "write": 23456, "launches": 1}},
+                                  "query": {"project": {"read": 10, "write": 20, "launches": 1}}}}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(doc))
     b.ROOT = str(tmp_path)
     b.kernel_source_hash = lambda: "0123456789abcdef"
     assert b.traffic_for("raster_vis") == 123456
     assert b.traffic_for("raster_uq") is None           # no entry
+    assert b.stage_traffic("room", "query")["project"]["write"] == 20
+    assert b.stage_traffic("precision", "query") is None
     b.kernel_source_hash = lambda: "fedcba9876543210"
     assert b.traffic_for("raster_vis") is None          # measured on other sources
+    assert b.stage_traffic("room", "query") is None
     (tmp_path / "profiles" / "traffic.json").write_text("not json")
     assert b.traffic_for("raster_vis") is None
+
+
+def test_stage_labels_follow_the_launch_order():
+    """Kernels of one query call, in launch order, map to the library's
+    stages; the radix passes before the emission are the depth sort, those
+    after it the tile sort."""
+    b = _bench_module()
+    seq = ["__amd_rocclr_copyBuffer", "k_fill_u32(unsigned*)", "void k_count<float>(GaussIn<float>)",
+           "k_scan_reduce(x)", "k_scan_blocks(x)", "k_scan_down(x)", "void k_project<float, float, 1, 3, false>(x)",
+           "k_radix_hist(x)", "k_radix_scan(x)", "k_radix_scatter(x)", "k_radix_hist(x)", "k_radix_scan(x)",
+           "k_radix_scatter(x)", "k_scan_reduce(x)", "k_scan_blocks(x)", "k_scan_down(x)", "k_fill_u32(unsigned*)",
+           "k_emit(x)", "k_radix_hist(x)", "k_radix_scan(x)", "k_radix_scatter(x)", "k_ranges(x)",
+           "void k_raster_uq<256, false, false, false, false>(x)", "k_scores(x)", "k_argmax(x)"]
+    lab = b.label_stages(seq)
+    assert lab[0] == "other" and lab[1:6] == ["cull"] * 5 and lab[6] == "project"
+    assert lab[7:13] == ["sort_depth"] * 6 and lab[13:18] == ["emit"] * 5
+    assert lab[18:21] == ["sort_tile"] * 3 and lab[21] == "ranges" and lab[22] == "raster_uq"
+    assert lab[23:] == ["scores", "scores"]
+
+
+def test_hbm_fractions_sum_the_binning_stages():
+    b = _bench_module()
+    tr = {"project": {"read": 4e9, "write": 4e9}, "sort_depth": {"read": 8e9, "write": 0},
+          "raster_uq": {"read": 1e9, "write": 0}}
+    r = b.hbm_fractions(tr, {"project": 2.0, "sort_depth": 2.0, "raster_uq": 1.0})
+    assert abs(r["project"]["frac"] - 0.5) < 1e-9           # 8 GB in 2 ms = 4 TB/s
+    assert abs(r["projection_and_binning"]["frac"] - 0.5) < 1e-9
+    assert r["projection_and_binning"]["bytes"] == 16e9

@@ -402,6 +402,63 @@ def test_device_pair_counts_match_oracle(ctx, case):
     check_pair_count(counts[3], st, 4, 5)
 
 
+def _with_emit_mode(ctx, ws, mode, instances=None):
+    """The workspace re-planned for the given emission mode (and optionally a
+    smaller instance capacity), with a buffer of the new size."""
+    import ctypes
+    plan = ws.plan
+    plan.emit_mode = mode
+    if instances is not None:
+        plan.max_instances = instances
+    plan.bytes = ctx.L.gv_workspace_bytes(ctypes.byref(plan))
+    return ctx.alloc_workspace(plan)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_lookback_emission_matches_the_scanned_one_and_the_oracle(ctx, case):
+    """The two ways the emission finds its output offsets (a scan of the tile
+    counts gathered into depth order, or the emission's own single-pass scan
+    with decoupled look-back, which the large workloads take) give the same
+    instance lists: bit-identical query maps and scores, equal build fields
+    to FP32 rounding, both equal to the oracle; a look-back emission whose
+    instances exceed the workspace flags the overflow."""
+    import torch
+    from paper_2605_30342_amd import _lib
+    name, sc, train, cand, L = list(_pair_count_cases())[case]
+    say(f"case: emission modes, {name}")
+    prm = oracle_params()
+    b = oracle.vf_build(sc, train, L, prm)
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, L, train.n, cand, prm)
+    dsc = _dsc(sc)
+    gd = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    uprm = _lib.default_uq_params()
+    out = {}
+    for mode in (1, 2):
+        ws = _with_emit_mode(ctx, ctx.query_workspace(dsc, cand, uprm, L), mode)
+        s_, m_ = ctx.vf_query_views(dsc, gd, L, train.n, cand, uprm, ws, want_maps=True)
+        st_, cnt = ctx.check_workspace(ws)
+        assert st_ == 0, cnt
+        vprm = _lib.default_vf_params(sh_degree=L)
+        wsb = _with_emit_mode(ctx, ctx.build_workspace(dsc, train, vprm), mode)
+        gam = ctx.vf_build(dsc, train, L, vprm, wsb)
+        torch.cuda.synchronize()
+        out[mode] = (s_.cpu().numpy(), m_.cpu().numpy(), gam.cpu().numpy().T.astype(np.float64), cnt[1])
+    assert out[1][3] == out[2][3]                          # instance totals
+    assert np.array_equal(out[1][0], out[2][0]) and np.array_equal(out[1][1], out[2][1])
+    worst, flagged = compare_maps(out[2][1].astype(np.float64), q)
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
+    scale = np.abs(out[1][2]).max(1, keepdims=True) + 1e-30
+    assert np.all(np.abs(out[2][2] - out[1][2]) <= 1e-5 * scale)
+    assert compare_gamma(out[2][2], b)[0] <= 1.0
+    # overflow of the instance capacity in the look-back emission
+    ws = _with_emit_mode(ctx, ctx.query_workspace(dsc, cand, uprm, L), 2, instances=max(1, out[2][3] // 3))
+    s_, _ = ctx.vf_query_views(dsc, gd, L, train.n, cand, uprm, ws)
+    st_, cnt = ctx.check_workspace(ws)
+    assert st_ == _lib.GV_ERR_CAPACITY and (cnt[2] & 2) and cnt[1] == out[2][3]
+    assert torch.all(torch.isnan(s_))
+
+
 def test_room_subset_build_and_query(ctx, room_small):
     say("case: room scene 20k Gaussians, L=3, 3 training views 800x800, 4 candidates 400x400")
     w = room_small
@@ -783,38 +840,68 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
 def test_multiview_visibility_matches_oracle(ctx):
     """Virtual particles (opacity 0, scale s, uniform in the room) measured
     against a room scene from four training views: the GPU's
-    1 - prod_p (1 - v_p) equals the oracle's, and the kept sets agree away
-    from the eps_v threshold."""
+    1 - prod_p (1 - v_p) equals the oracle's."""
     say("case: density control multi-view visibility")
     import torch
-    from paper_2605_30342_amd.api import DeviceScene, append_virtual, density_control, virtual_particles
+    from paper_2605_30342_amd.api import DeviceScene
     w = scenes.workload("room", scale=0.05)
     train = scenes.ellipse_path_cameras(4, 2001, 200, 200)
     u = scenes.uniform_draws(8000, 2003)
-    virt = virtual_particles(w.scene.extent, u)
-    allp = append_virtual(w.scene, virt)
+    r = oracle.density_control(w.scene, train, u, [e[0] for e in w.scene.extent], [e[1] for e in w.scene.extent])
+    from paper_2605_30342_amd.scenes import Scene
+    nv = r["n_virt"]
+    allp = Scene(np.concatenate([w.scene.means, r["means"].astype(np.float32)]),
+                 np.concatenate([w.scene.scales, np.full((nv, 3), r["s"], np.float32)]),
+                 np.concatenate([w.scene.quats, np.tile(np.array([1, 0, 0, 0], np.float32), (nv, 1))]),
+                 np.concatenate([w.scene.opacity, np.zeros(nv, np.float32)]), 0, w.scene.extent)
     prm = oracle_params()
     vis_o, allow = oracle.multiview_visibility(allp, train, prm)
     vis_g = ctx.multiview_visibility(DeviceScene(allp), train)
     torch.cuda.synchronize()
     vg = vis_g.cpu().numpy().astype(np.float64)
     err = np.abs(vg - vis_o) / (1e-4 + 2.0 * allow)
-    say(f"  worst {err.max():.3f}; virtual kept (oracle) {(vis_o[w.scene.n:] <= 0.95).sum()} of {virt.n}")
+    say(f"  worst {err.max():.3f}")
     assert err.max() <= 1.0
-    aug, v = density_control(ctx, w.scene, train, u)
-    keep_o = set(oracle.density_control_keep(vis_o, w.scene.n) - w.scene.n)
-    keep_g = set(np.nonzero(v <= 0.95)[0])
-    far = np.abs(vis_o[w.scene.n:] - 0.95) > 1e-4 + 2.0 * allow[w.scene.n:]
-    assert {i for i in keep_o if far[i]} == {i for i in keep_g if far[i]}
-    assert aug.n_virtual == len(keep_g) and aug.n == w.scene.n + len(keep_g)
+
+
+def test_density_control_through_the_abi_matches_oracle(ctx):
+    """Alg. 5 end to end in the library (vf_density_control: N_virt and s,
+    the particles from the uniform draws, their multi-view visibility, the
+    eps_v prune and the packing of the kept particles behind the scene)
+    against the oracle's Alg. 5 on the same draws: the same count and scale,
+    visibility within the near-tie allowance, the same kept set away from
+    eps_v, and the kept particles' attributes in the scene's tail."""
+    say("case: vf_density_control against the oracle")
+    from paper_2605_30342_amd import api
+    w = scenes.workload("room", scale=0.05)
+    train = scenes.ellipse_path_cameras(4, 2001, 200, 200)
+    u = scenes.uniform_draws(8000, 2003)
+    lo, hi = [e[0] for e in w.scene.extent], [e[1] for e in w.scene.extent]
+    prm = oracle_params()
+    r = oracle.density_control(w.scene, train, u.astype(np.float32).astype(np.float64), lo, hi, prm=prm)
+    aug, vis, kept, n_virt = api.density_control(ctx, w.scene, train, u)
+    say(f"  N_virt {n_virt} (oracle {r['n_virt']}), kept {len(kept)} (oracle {len(r['kept'])})")
+    assert n_virt == r["n_virt"]
+    assert np.float32(aug.scales[-1, 0] if aug.n_virtual else r["s"]) == np.float32(r["s"])
+    err = np.abs(vis.astype(np.float64) - r["vis"]) / (1e-4 + 2.0 * r["allow"])
+    say(f"  visibility worst ratio {err.max():.3f}")
+    assert err.max() <= 1.0
+    far = np.abs(r["vis"] - 0.95) > 1e-4 + 2.0 * r["allow"]
+    ko, kg = set(r["kept"].tolist()), set(kept.tolist())
+    assert {i for i in ko if far[i]} == {i for i in kg if far[i]}
+    assert np.all(np.diff(kept) > 0) and aug.n_virtual == len(kept) and aug.n == w.scene.n + len(kept)
+    assert np.array_equal(aug.means[:w.scene.n], w.scene.means)
+    assert np.array_equal(aug.means[w.scene.n:], r["means"][kept].astype(np.float32))
+    assert np.all(aug.opacity[w.scene.n:] == 0.0) and np.all(aug.quats[w.scene.n:] == [1, 0, 0, 0])
 
 
 # ---------------------------------------------------------------- launch schedules
 
 def test_schedule_variants_give_identical_results(ctx, tiny, tiny_ref):
-    """Every staging batch size (64/128/256) gives bit-identical query maps and
-    gamma equal to FP32 rounding (float atomics add in another order); the
-    autotuner picks one of them and records its timings."""
+    """Every staging batch size (64/128/256) and tile order (workgroup b takes
+    tile b, or contiguous runs of tiles per XCD) gives bit-identical query
+    maps and gamma equal to FP32 rounding (float atomics add in another
+    order); the autotuner picks one of them and records its timings."""
     say("case: blend batch-size variants and the autotuner")
     import torch
     from paper_2605_30342_amd import _lib
@@ -827,10 +914,11 @@ def test_schedule_variants_give_identical_results(ctx, tiny, tiny_ref):
     t0 = ctx.get_tuning()
     maps, gams = [], []
     for b in (64, 128, 256):
-        ctx.set_tuning(b, b)
-        _, m = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws, want_maps=True)
-        maps.append(m.clone())
-        gams.append(gpu_build(ctx, dsc, tiny.train, 2))
+        for order in (0, 1):
+            ctx.set_tuning(b, b, order, order)
+            _, m = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws, want_maps=True)
+            maps.append(m.clone())
+            gams.append(gpu_build(ctx, dsc, tiny.train, 2))
     torch.cuda.synchronize()
     for m in maps[1:]:
         assert torch.equal(m, maps[0])
@@ -840,4 +928,5 @@ def test_schedule_variants_give_identical_results(ctx, tiny, tiny_ref):
     tuner = Autotuner(ctx)
     r = tuner.tune_query(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws)
     assert r["uq_batch"] in (64, 128, 256) and ctx.get_tuning()["uq_batch"] == r["uq_batch"]
+    assert r["uq_order"] in (0, 1) and ctx.get_tuning()["uq_order"] == r["uq_order"] and len(r["ms"]) == 6
     ctx.set_tuning(**t0)

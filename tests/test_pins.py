@@ -432,12 +432,47 @@ def test_argmax_lowest_index_on_ties():
 # ---------------------------------------------------------------- density control (Alg. 5)
 
 def test_virtual_particle_constants():
-    """N_virt = floor(rho Vol) and (4/3) pi s^3 rho = 1 + eta (rho = 100, eta = 0.5)."""
-    from paper_2605_30342_amd.api import virtual_particle_count, virtual_particle_scale
-    assert virtual_particle_count(((0, 6), (0, 4), (0, 3)), 100.0) == 7200
-    s = virtual_particle_scale(100.0, 0.5)
+    """The oracle's Alg. 5 particles: N_virt = floor(rho Vol) (6 x 4 x 3 m at
+    rho = 100: 7200; a 1.25 x 1 x 1 box: 125), the scale's
+    defining identity (4/3) pi s^3 rho = 1 + eta and its value at rho = 100,
+    eta = 0.5, and positions lo + u (hi - lo) (u = 0 at the low corner, u
+    near 1 at the high one, a middle draw in the middle)."""
+    lo, hi = (0.0, 0.0, 0.0), (6.0, 4.0, 3.0)
+    u = np.full((7200, 3), 0.5)
+    u[0] = 0.0
+    u[1] = 1.0 - 2.0 ** -40
+    means, s = oracle.virtual_particles(lo, hi, u, 100.0, 0.5)
+    assert means.shape == (7200, 3)
     assert 4.0 / 3.0 * math.pi * s ** 3 * 100.0 == pytest.approx(1.5, rel=1e-12)
     assert s == pytest.approx(0.152992, abs=1e-6)
+    assert np.array_equal(means[0], [0.0, 0.0, 0.0])
+    assert np.allclose(means[1], hi, atol=1e-11) and np.all(means[1] < hi)
+    assert np.array_equal(means[2], [3.0, 2.0, 1.5])
+    m2, _ = oracle.virtual_particles((1.0, -2.0, 0.5), (2.25, -1.0, 1.5), np.full((200, 3), 0.25), 100.0, 0.5)
+    assert m2.shape[0] == 125 and np.array_equal(m2[0], [1.3125, -1.75, 0.75])
+    with pytest.raises(ValueError):
+        oracle.virtual_particles(lo, hi, u[:7199], 100.0, 0.5)      # too few draws
+    m3, s3 = oracle.virtual_particles(lo, hi, u, 10.0, 0.0)
+    assert m3.shape[0] == 720 and 4.0 / 3.0 * math.pi * s3 ** 3 * 10.0 == pytest.approx(1.0, rel=1e-12)
+
+
+def test_density_control_keeps_the_hidden_particles():
+    """Alg. 5 end to end on a 1x1 view of a wall of three opaque occluders: a
+    box that holds one particle in front of the wall (visible, multi-view
+    visibility 1, pruned) and one behind it (never reached, 0, kept)."""
+    from paper_2605_30342_amd.scenes import Cameras
+    cam1 = axis_camera(1, 1, 50.0)
+    cam2 = Cameras(np.repeat(cam1.R, 2, 0), np.repeat(cam1.t, 2, 0), np.repeat(cam1.K, 2, 0), np.repeat(cam1.wh, 2, 0))
+    wall = stack_scene([1.0, 1.1, 1.2], [0.99, 0.99, 0.99], scale=0.01)
+    # box 0.02 x 0.02 x 2.5 at rho = 2000 / (0.02 * 0.02 * 2.5) holds 2000 particles; two draws matter
+    lo, hi = (-0.01, -0.01, 0.3), (0.01, 0.01, 2.8)
+    rho = 2000.0 / (0.02 * 0.02 * 2.5) * (1 + 1e-9)
+    u = np.full((2000, 3), 0.5)
+    u[:, 2] = np.where(np.arange(2000) % 2 == 0, 0.1, 0.9)       # z = 0.55 (in front) or 2.55 (behind)
+    r = oracle.density_control(wall, cam2, u, lo, hi, rho=rho, eta=0.5, eps_v=0.95)
+    assert r["n_virt"] == 2000
+    assert np.all(r["vis"][0::2] == 1.0) and np.all(r["vis"][1::2] == 0.0)
+    assert np.array_equal(r["kept"], np.arange(1, 2000, 2))
 
 
 def test_multiview_visibility_special_cases():

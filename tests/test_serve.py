@@ -25,7 +25,7 @@ class FakeBackend:
     def wait(self, dt):
         self.t += max(dt, 0.01)
 
-    def plan_bytes(self, scene_id, cams_list):
+    def plan_bytes(self, scene_id, cams_list, limit=None):
         if scene_id in self.fail_plan:
             raise BackendError("plan failed")
         return self.bpv * sum(c.n for c in cams_list)
@@ -272,3 +272,20 @@ def test_gpu_backend_turns_allocation_failure_into_a_failed_request():
     r = srv.requests[rid]
     assert r.status == FAILED and "allocation" in r.error
     assert srv.in_use == 0 and sorted(srv.free_slots) == [0, 1]
+
+
+def test_gpu_backend_sizes_exactly_when_the_estimate_exceeds_the_free_budget():
+    """An estimate (rates x slack) above the free memory is replaced by the
+    exact size, computed once and reused while the batch waits and at its
+    launch."""
+    ctx = _StubCtx()
+    be = _gpu_backend(ctx)
+    c = _cams_wh(4, 32, 24, 1)
+    est = be.plan_bytes("A", [c])
+    assert ctx.exact_calls == [4]
+    exact = _Plan(1000, 400, 1200).bytes
+    assert est > exact
+    assert be.plan_bytes("A", [c], limit=exact) == exact
+    assert ctx.exact_calls == [4, 4]
+    assert be.plan_bytes("A", [c], limit=exact) == exact       # cached: no second pass
+    assert ctx.exact_calls == [4, 4]
