@@ -346,7 +346,9 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
  *   *_order  which tile each workgroup blends (0: workgroup b takes tile b;
  *            1: the eight XCDs, which take the workgroups in turn, each take
  *            a contiguous run of tiles, so that neighbouring tiles, which
- *            share most of their records, share an L2 cache).
+ *            share most of their records, share an L2 cache; 2: the tiles of
+ *            all views by decreasing list length, sorted on the device before
+ *            the blend, so that the longest tiles start first).
  * Results do not depend on the choice (VF CONST's float atomics may add in
  * another order).  Defaults 64 / 256, order 0. */
 typedef struct {

@@ -4,7 +4,9 @@ Two axes per blend (`gv_tuning`): the records a tile stages into LDS per
 batch (64, 128 or 256: larger batches need fewer workgroup barriers, smaller
 ones leave room for more resident workgroups per CU) and the tile order of
 the workgroups (0: workgroup b blends tile b; 1: each of the eight XCDs takes
-a contiguous run of tiles, so that neighbouring tiles share an L2).  Which
+a contiguous run of tiles, so that neighbouring tiles share an L2; 2: the
+tiles of all views longest list first, a cost-ordered queue that the
+workgroup dispatcher drains in order).  Which
 schedule wins depends on the workload (list lengths per tile, image sizes,
 Gaussian footprints, the number of views), so the tuner times every
 candidate on the caller's actual workload, checks that the outputs agree, and
@@ -21,7 +23,7 @@ from typing import Dict, Optional
 import torch
 
 BATCHES = (64, 128, 256)
-ORDERS = (0, 1)
+ORDERS = (0, 1, 2)
 CANDIDATES = tuple(itertools.product(BATCHES, ORDERS))
 
 

@@ -105,6 +105,26 @@ __device__ __forceinline__ bool cons_visible(const float m[3], float smax, const
            (uy - ry - sly <= (float)V.h);
 }
 
+// FP64 reciprocal and square root of positive arguments, about 1e-16
+// relative: the hardware estimates refined by two Newton steps each (the
+// results are rounded to FP32 or padded by conservative margins, so correct
+// rounding is not needed).  sqrt_pos(0) = 0.
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+__device__ __forceinline__ double sqrt_pos(double x) {
+    if (!(x > 0.0)) return 0.0;
+    double y = __builtin_amdgcn_rsq(x);          // 1 / sqrt(x)
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    const double r = x * y;
+    return fma(fma(-r, r, x), 0.5 * y, r);       // one more step on the root itself
+}
+
 // 3D covariance (R_q S)(R_q S)^T of one Gaussian in FP64: s00 s01 s02 s11 s12 s22.
 __device__ __forceinline__ void cov3d(const float s[3], const float q[4], double S[6]) {
     double w = q[0], x = q[1], y = q[2], z = q[3];
@@ -137,7 +157,9 @@ struct Proj {
 // and the tiles whose pixel centres can lie inside the m <= cut ellipse.
 __device__ __forceinline__ void project_exact(const float m[3], const double S[6], const ViewDev &V, float znear,
                                            float lowpass, float cut, Proj &P) {
-#pragma clang fp contract(off)
+    // multiply-adds fused within an expression only (decided per expression,
+    // so the sizing and the projection kernels compute the same values)
+#pragma clang fp contract(on)
     P.ok = false;
     const double mx = m[0], my = m[1], mz = m[2];
     const double px = (double)V.R[0] * mx + (double)V.R[1] * my + (double)V.R[2] * mz + (double)V.t[0];
@@ -145,7 +167,7 @@ __device__ __forceinline__ void project_exact(const float m[3], const double S[6
     const double pz = (double)V.R[6] * mx + (double)V.R[7] * my + (double)V.R[8] * mz + (double)V.t[2];
     P.z = pz;
     if (!(pz > (double)znear)) return;
-    const double iz = 1.0 / pz;
+    const double iz = rcp_pos(pz);
     const double fx = V.fx, fy = V.fy;
     const double jx0 = fx * iz, jx2 = -fx * px * iz * iz;
     const double jy1 = fy * iz, jy2 = -fy * py * iz * iz;
@@ -163,14 +185,14 @@ __device__ __forceinline__ void project_exact(const float m[3], const double S[6
     const double c = w10 * u0 + w11 * u1 + w12 * u2 + (double)lowpass;
     const double det = a * c - b * b;
     if (!(det > 1e-12)) return;
-    const double idet = 1.0 / det;
+    const double idet = rcp_pos(det);
     P.ca = c * idet;
     P.cb = -b * idet;
     P.cc = a * idet;
     P.ux = fx * px * iz + (double)V.cx;
     P.uy = fy * py * iz + (double)V.cy;
-    const double rx = sqrt((double)cut * a) * (1.0 + 1e-6) + 1e-4;
-    const double ry = sqrt((double)cut * c) * (1.0 + 1e-6) + 1e-4;
+    const double rx = sqrt_pos((double)cut * a) * (1.0 + 1e-6) + 1e-4;
+    const double ry = sqrt_pos((double)cut * c) * (1.0 + 1e-6) + 1e-4;
     double i0 = ceil(P.ux - rx - 0.5), i1 = floor(P.ux + rx - 0.5);
     double j0 = ceil(P.uy - ry - 0.5), j1 = floor(P.uy + ry - 0.5);
     i0 = fmax(i0, 0.0); j0 = fmax(j0, 0.0);
@@ -314,6 +336,8 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
     __shared__ uint32_t srel[WAVES][64];   // first record of each entry (relative)
     __shared__ uint8_t cl[WAVES][64];      // lanes of the entries that own records, in order
     __shared__ uint8_t mk[WAVES][64];      // 1 where an entry starts at that record of the chunk
+    __shared__ float4 sgm[WAVES][64];      // each entry's Gaussian: mean, opacity
+    __shared__ double sgS[WAVES][6][64];   // its 3D covariance (six terms, one row per term)
     if (st->overflow & 1u) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t ne = (uint64_t)G.n * PROJ_SPLIT;
@@ -333,6 +357,20 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
         const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
         if (owns) cl[w][lanes_below(own)] = (uint8_t)lane;
         srel[w][lane] = rel;
+        if (owns) {
+            // the Gaussian's attributes and 3D covariance, once per entry
+            // for all of its records
+            const int64_t g = (int64_t)(e / PROJ_SPLIT);
+            float m[3], sc3[3], qt[4];
+            G.mean(g, m);
+            G.scale(g, sc3);
+            G.quat(g, qt);
+            double S[6];
+            cov3d(sc3, qt, S);
+            sgm[w][lane] = make_float4(m[0], m[1], m[2], G.opacity(g));
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sgS[w][k][lane] = S[k];
+        }
         uint32_t total = 0;
         if (own) {
             const int last = 63 - __builtin_clzll(own);
@@ -367,12 +405,11 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 }
                 const int v = sub + PROJ_SPLIT * (32 * wi + kth_set_bit(word, k));
                 const ViewDev &V = views[v];
-                float m[3], s[3], qt[4];
-                G.mean(g, m);
-                G.scale(g, s);
-                G.quat(g, qt);
+                const float4 gm = sgm[w][q];
+                const float m[3] = {gm.x, gm.y, gm.z};
                 double S[6];
-                cov3d(s, qt, S);
+#pragma unroll
+                for (int kk = 0; kk < 6; ++kk) S[kk] = sgS[w][kk][q];
                 Proj Pj;
                 project_exact(m, S, V, znear, lowpass, cut, Pj);
                 Bin b = {};
@@ -388,13 +425,13 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     R.uv = (int32_t)(((uint32_t)(int)ax & 0xFFFFu) | ((uint32_t)(int)ay << 16));
                     R.fx = (float)(Pj.ux - ax);
                     R.fy = (float)(Pj.uy - ay);
-                    const double l11 = sqrt(Pj.ca);
-                    const double l21 = Pj.cb / l11;
-                    const double l22 = sqrt(fmax(Pj.cc - l21 * l21, 0.0));
+                    const double l11 = sqrt_pos(Pj.ca);          // ca > 0: det > 0
+                    const double l21 = Pj.cb * rcp_pos(l11);
+                    const double l22 = sqrt_pos(Pj.cc - l21 * l21);
                     R.l11 = (float)(sc * l11);
                     R.l21 = (float)(sc * l21);
                     R.l22 = (float)(sc * l22);
-                    R.o = G.opacity(g);
+                    R.o = gm.w;
                     float vis = 0.0f;
                     if constexpr (MODE == 2) {
                         const bool virt = g >= G.n - G.n_virtual;
@@ -1089,6 +1126,20 @@ __global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key,
     }
 }
 
+// Sort keys of the cost-ordered tile schedule: tile t's list length,
+// complemented so that an ascending sort puts the longest first; values the
+// tile ids; *count = T for the sort.
+__global__ __launch_bounds__(WG) void k_tile_cost(const uint2 *__restrict__ ranges, uint32_t T,
+                                                  uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                                                  uint32_t *__restrict__ count) {
+    const uint32_t t = blockIdx.x * WG + threadIdx.x;
+    if (t == 0) *count = T;
+    if (t >= T) return;
+    const uint2 r = ranges[t];
+    key[t] = ~(r.y - r.x);
+    val[t] = t;
+}
+
 // ---------------------------------------------------------------- host launchers
 
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u * 4u) {
@@ -1276,6 +1327,14 @@ void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, S
     launch_fill_u32(reinterpret_cast<uint32_t *>(lb), 2 * (uint64_t)words, 0u, s);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)words), dim3(WG), 0, s, sval, bin, lb, st, icap, qcut, dead_tile,
                        ikey, ival);
+}
+
+const uint32_t *launch_tile_order(const uint2 *ranges, uint32_t T, uint32_t *buf, uint32_t *count, uint32_t *hist,
+                                  uint32_t *dtot, hipStream_t s) {
+    uint32_t *k0 = buf, *v0 = buf + T, *k1 = buf + 2 * (uint64_t)T, *v1 = buf + 3 * (uint64_t)T;
+    hipLaunchKernelGGL(k_tile_cost, dim3((T + WG - 1) / WG), dim3(WG), 0, s, ranges, T, k0, v0, count);
+    const int r = launch_radix_sort(k0, v0, k1, v1, count, 32, false, hist, dtot, s, DEAD_KEY, nullptr, T);
+    return r ? v1 : v0;
 }
 
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s) {

@@ -104,7 +104,7 @@ bool finite_cam(const gv_camera &c) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, ntr, icnt, ioff, post;
+    size_t status, views, cnt, vmask, offs, blk, rec, bin, key0, val0, key1, val1, ntr, icnt, ioff, post, torder;
     size_t ikey0, ival0, ikey1, ival1, ranges, hist, dtot, accT, accC, gam32, tpart, rcc, rz;
     size_t dc_flags, dc_offs, dc_tmp, dc_misc;   // density control (kind 2)
     size_t total;
@@ -161,6 +161,7 @@ Layout make_layout(const gv_workspace &p) {
     L.ikey1 = take(M * 4);
     L.ival1 = take(M * 4);
     L.ranges = take(T * 8);
+    L.torder = take((4 * T + 64) * 4);   // cost-ordered tile schedule: sort buffers and a count
     L.hist = take((size_t)RADIX * RADIX_BLOCKS * 4);
     L.dtot = take((size_t)RADIX * 4);
     if (p.kind == 0 || p.kind == 2) {
@@ -419,10 +420,12 @@ struct Binned {
     const uint32_t *sval;   // record ids in depth order
     const uint32_t *ival;   // record ids in (tile, depth) order
     const uint32_t *ikey;   // their instance keys (tile id, quadrant mask)
+    const uint32_t *torder; // tiles by decreasing list length (schedule 2), else NULL
 };
 
 static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
-                             int64_t tiles, const GeomArgs &geo, const QueryArgs *query, hipStream_t s, Binned &out) {
+                             int64_t tiles, const GeomArgs &geo, const QueryArgs *query, hipStream_t s, Binned &out,
+                             int order) {
     Status *st = at<Status>(ws, L.status);
     ViewDev *views = at<ViewDev>(ws, L.views);
     uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs), *vmask = at<uint32_t>(ws, L.vmask);
@@ -481,9 +484,13 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
                                  (uint32_t)tiles, &st->M_live, M);
     }
     const uint32_t *skey = tres ? ik1 : ik0;
+    out.torder = nullptr;
     {
         StageScope sc(ctx, ST_RANGES, s);
         launch_ranges(skey, st, (uint32_t)tiles, ranges, s);
+        if (order == 2)
+            out.torder = launch_tile_order(ranges, (uint32_t)tiles, at<uint32_t>(ws, L.torder),
+                                           at<uint32_t>(ws, L.torder) + 4 * (uint64_t)tiles, hist, dtot, s);
     }
     out.sval = sval;
     out.ival = tres ? iv1 : iv0;
@@ -711,7 +718,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
@@ -721,7 +728,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, ctx->tuning.vis_order, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -782,7 +789,7 @@ static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const g
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
@@ -792,7 +799,7 @@ static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const g
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, ctx->tuning.vis_order, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -1003,14 +1010,14 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
     qa.rz = dmp ? at<float>(workspace, Lay.rz) : nullptr;
     auto enqueue = [&]() -> gv_status {
         Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &qa, s, bz));
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, n_cand, tiles, geo, &qa, s, bz, ctx->tuning.uq_order));
         float *tpart = at<float>(workspace, Lay.tpart);
         {
             StageScope sc(ctx, ST_RASTER_UQ, s);
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
                              bz.ival, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
-                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, ctx->tuning.uq_order, s);
+                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, ctx->tuning.uq_order, bz.torder, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
         return GV_OK;
@@ -1259,8 +1266,8 @@ gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t) {
     if (!ctx || !t) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
     if (!ok(t->vis_batch) || !ok(t->uq_batch)) return fail(GV_ERR_INVALID_ARG, "batch sizes must be 64, 128 or 256");
-    if (t->vis_order < 0 || t->vis_order > 1 || t->uq_order < 0 || t->uq_order > 1)
-        return fail(GV_ERR_INVALID_ARG, "tile orders must be 0 or 1");
+    if (t->vis_order < 0 || t->vis_order > 2 || t->uq_order < 0 || t->uq_order > 2)
+        return fail(GV_ERR_INVALID_ARG, "tile orders must be 0, 1 or 2");
     ctx->tuning = *t;
     return GV_OK;
 }

@@ -148,7 +148,11 @@ __device__ __forceinline__ int pad_slot(int n) {
 // order 1: XCD x takes a contiguous run of the tile ids (row-major tiles of
 // one view after another), so neighbours share an L2.  A bijection of
 // [0, T): XCD x holds the ceil((T - x) / 8) workgroups x, x + 8, ...
-__device__ __forceinline__ int tile_of_block(int b, int T, int order) {
+// order 2: torder[b], the tiles of all views by decreasing list length (the
+// dispatcher hands workgroups to free slots in launch order, so the longest
+// tiles start first and the short ones fill the end: no straggler tail).
+__device__ __forceinline__ int tile_of_block(int b, int T, int order, const uint32_t *torder) {
+    if (order == 2) return (int)torder[b];
     if (order == 0) return b;
     const int x = b & 7, k = b >> 3;
     const int per = T >> 3, rem = T & 7;
@@ -167,7 +171,8 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
                                                    const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
                                                    const Rec *__restrict__ rec,
                                                    float eps_T, float qcut, float *__restrict__ acc_T,
-                                                   uint32_t *__restrict__ acc_c, int order) {
+                                                   uint32_t *__restrict__ acc_c, int order,
+                                                   const uint32_t *__restrict__ torder) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
     __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
     __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
 
-    const int gt = tile_of_block(blockIdx.x, gridDim.x, order);
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, order, torder);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -405,7 +410,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
                                                   const float *__restrict__ rz,
                                                   UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
                                                   float *__restrict__ dmaps, unsigned long long *__restrict__ pairs,
-                                                  int order) {
+                                                  int order, const uint32_t *__restrict__ torder) {
     constexpr int NL = 4 * WAVES;          // sub-block lists per tile
     __shared__ float4 wA[RB + 1];          // ux, uy, l11, l21 per batch slot (slot RB: never hit)
     __shared__ float4 wB[RB + 1];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
@@ -415,7 +420,7 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     __shared__ BatchCounts<NL> bc;         // per sub-block list: counts of the four waves
     __shared__ float red[WAVES];
 
-    const int gt = tile_of_block(blockIdx.x, gridDim.x, order);
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, order, torder);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -928,29 +933,31 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 template <int RB>
 static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                           const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                          int order, hipStream_t s) {
+                          int order, const uint32_t *torder, hipStream_t s) {
     hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, ikey, rec, eps_T, qcut,
-                       acc_T, acc_c, order);
+                       acc_T, acc_c, order, torder);
 }
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
-                       int order, hipStream_t s) {
+                       int order, const uint32_t *torder, hipStream_t s) {
     if (total_tiles <= 0) return;
+#define GV_VIS_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, torder, s
     switch (batch) {
-    case 64: raster_vis_rb<64>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
-    case 256: raster_vis_rb<256>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
-    default: raster_vis_rb<128>(views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, s); break;
+    case 64: raster_vis_rb<64>(GV_VIS_ARGS); break;
+    case 256: raster_vis_rb<256>(GV_VIS_ARGS); break;
+    default: raster_vis_rb<128>(GV_VIS_ARGS); break;
     }
+#undef GV_VIS_ARGS
 }
 
 template <int RB, bool CC, bool DEPTH>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                          const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
-                         hipStream_t s) {
+                         const uint32_t *torder, hipStream_t s) {
     const dim3 g(total_tiles), b(WG);
-#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order
+#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder
     if constexpr (DEPTH) {   // depth maps come with the entropy maps
         if (pairs)
             hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true>), g, b, 0, s, GV_UQ_ARGS);
@@ -973,8 +980,8 @@ template <int RB>
 static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                           const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                           float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
-                          hipStream_t s) {
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, s
+                          const uint32_t *torder, hipStream_t s) {
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, s
     const bool depth = dmaps && maps && rz;
     if (rcc && depth) raster_uq_rb<RB, true, true>(GV_UQ_ARGS);
     else if (rcc) raster_uq_rb<RB, true, false>(GV_UQ_ARGS);
@@ -986,9 +993,9 @@ static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const u
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
-                      int order, hipStream_t s) {
+                      int order, const uint32_t *torder, hipStream_t s) {
     if (total_tiles <= 0) return;
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, s
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, s
     switch (batch) {
     case 64: raster_uq_var<64>(GV_UQ_ARGS); break;
     case 256: raster_uq_var<256>(GV_UQ_ARGS); break;

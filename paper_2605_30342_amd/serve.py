@@ -97,31 +97,37 @@ class Server:
         return True
 
     # ---------------------------------------------------------------- scheduling
-    def _form_batch(self) -> List[Request]:
+    def _form_batch(self):
+        """The oldest request plus the following requests of its scene, while
+        the batch stays within the view budget and its workspace within a
+        slot's share of the memory budget (so that the slots can overlap);
+        returns (batch, its workspace bytes)."""
         head = self.pending[0]
         batch, views = [head], head.n_views
+        nbytes = self.be.plan_bytes(head.scene_id, [head.cams])
+        share = self.budget // max(self.n_slots, 1)
         for r in list(self.pending)[1:]:
-            if r.scene_id == head.scene_id and views + r.n_views <= self.max_batch_views:
+            if r.scene_id != head.scene_id or views + r.n_views > self.max_batch_views or nbytes >= share:
+                continue
+            b = self.be.plan_bytes(head.scene_id, [x.cams for x in batch] + [r.cams])
+            if b <= share:
                 batch.append(r)
                 views += r.n_views
-        return batch
+                nbytes = b
+        return batch, nbytes
 
     def _admit(self) -> None:
         while self.free_slots and self.pending:
-            batch = self._form_batch()
             free = self.budget - self.in_use
             try:
-                nbytes = self.be.plan_bytes(batch[0].scene_id, [r.cams for r in batch])
-                if nbytes > free and len(batch) > 1:
-                    batch = batch[:1]
-                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams])
-                if nbytes > free:
-                    # a request alone whose estimate does not fit may still fit
-                    # at its exact size (asked once per request: the backend
-                    # keeps it while the request waits)
-                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams], limit=free)
+                batch, nbytes = self._form_batch()
+                if nbytes > self.budget:
+                    # a request whose estimate exceeds the whole budget may
+                    # still fit at its exact size (asked once per request:
+                    # the backend keeps it while the request waits)
+                    nbytes = self.be.plan_bytes(batch[0].scene_id, [batch[0].cams], limit=self.budget)
             except BackendError as e:
-                self._fail(batch, str(e))
+                self._fail([self.pending[0]], str(e))
                 continue
             if nbytes > self.budget:
                 for r in batch:
@@ -265,9 +271,9 @@ class GpuBackend:
     keeps the largest records and instances per view seen so far (`rates`)
     and plans a batch as the sum over its views of those rates times `slack`
     (Context.query_plan: no device pass, nothing allocated).  A batch holding
-    an image size the scene has not been seen at, or whose estimate exceeds
-    the free budget, is sized exactly by the library's counting pass
-    (synchronous; once per scene and size, once per waiting batch).
+    an image size the scene has not been seen at, or a request whose estimate
+    exceeds the whole budget, is sized exactly by the library's counting pass
+    (synchronous; once per scene and size, once per such request).
     The workspace is allocated when the batch is launched, after admission;
     an allocation failure is a BackendError.  At completion every batch's
     workspace status gives its exact record and instance counts, which
@@ -276,7 +282,7 @@ class GpuBackend:
     slot, once.  Such a re-launch may hold more bytes than were admitted for
     the batch until it completes."""
 
-    def __init__(self, ctx, n_slots: int = 4, params=None, slack: float = 1.5):
+    def __init__(self, ctx, n_slots: int = 4, params=None, slack: float = 1.25):
         import torch
         from . import _lib
         self.torch = torch

@@ -289,3 +289,18 @@ def test_gpu_backend_sizes_exactly_when_the_estimate_exceeds_the_free_budget():
     assert ctx.exact_calls == [4, 4]
     assert be.plan_bytes("A", [c], limit=exact) == exact       # cached: no second pass
     assert ctx.exact_calls == [4, 4]
+
+
+def test_merged_batches_keep_to_a_slots_share_of_memory():
+    """Followers join the head's batch only while the batch's workspace stays
+    within budget / slots, so that the slots can run batches side by side."""
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=10_000, n_slots=2, max_batch_views=512)
+    for i in range(10):
+        srv.submit("A", cams(8, i))
+    srv.step()
+    assert len(be.launches) == 2                        # both slots busy
+    assert all(nv * 100 <= 5_000 for _, nv, _ in be.launches)
+    assert be.launches[0][1] == 48                       # six requests of 8 views
+    srv.run_until_idle(timeout=1e4)
+    assert all(r.status == DONE for r in srv.requests.values())
