@@ -151,14 +151,36 @@ def _read_csv(path, counter=None):
 
 
 def _last_calls(rows):
-    """(build, query) dispatch slices of the last step: the last query ends at
-    the argmax that follows it; the build is the call before it."""
-    starts = [i for i, r in enumerate(rows) if _kernel_base(r[1]) == "k_count"] + [len(rows)]
-    steps = [j for j in range(len(starts) - 1)
-             if any(_kernel_base(rows[i][1]) == "k_argmax" for i in range(starts[j], starts[j + 1]))]
-    q = steps[-1]
-    end = next(i for i in range(starts[q], len(rows)) if _kernel_base(rows[i][1]) == "k_argmax") + 1
-    return rows[starts[q - 1] - 1:starts[q] - 1], rows[starts[q] - 1:end]
+    """(build, query) dispatch slices: the last one-pass call that blends with
+    k_raster_vis and the last that blends with k_raster_uq.  A call runs from
+    the upload of its view table (the copy before its k_count) to the kernel
+    before the next call's upload; a query's argmax, if any, belongs to it."""
+    starts = []
+    for i, r in enumerate(rows):
+        if _kernel_base(r[1]) != "k_count":
+            continue
+        if i > 0 and _kernel_base(rows[i - 1][1]) == "k_fill_u32":     # the status words' clear
+            i -= 1
+        if i > 0 and "copyBuffer" in rows[i - 1][1]:                      # the view table's upload
+            i -= 1
+        starts.append(i)
+    starts.append(len(rows))
+    last = {}
+    for j in range(len(starts) - 1):
+        seg = rows[starts[j]:starts[j + 1]]
+        while seg and not _kernel_base(seg[-1][1]).startswith("k_"):      # other work after the call
+            seg = seg[:-1]
+        names = {_kernel_base(r[1]) for r in seg}
+        if "k_raster_vis" in names:
+            last["build"] = seg
+        elif "k_raster_uq" in names:
+            # the timed form: not the variant that counts composited pairs
+            # (k_raster_uq<batch, maps, count, ...>)
+            uq = next(r[1] for r in seg if _kernel_base(r[1]) == "k_raster_uq")
+            targs = uq.split("<", 1)[1].split(">", 1)[0].split(",") if "<" in uq else []
+            if len(targs) < 3 or targs[2].strip() != "true":
+                last["query"] = seg
+    return last["build"], last["query"]
 
 
 def summarize_counters(d: str, workload: str, copy_mib: int):
@@ -391,13 +413,18 @@ def batched_bench(ctx, uprm, timed, log):
     t0 = time.time()
     w = scenes.workload("batched")
     L = w.sh_degree
+    from paper_2605_30342_amd.autotune import Autotuner
+    saved = ctx.get_tuning()
+    tuner = Autotuner(ctx)
     d = DeviceScene(w.scene)
     vp = _lib.default_vf_params(sh_degree=L, kappa=w.kappa, views_per_pass=50)
     wsb = ctx.build_workspace(d, w.train, vp)
     g = torch.empty(((L + 1) ** 2, w.scene.n), dtype=torch.float32, device="cuda")
+    tuner.tune_build(d, w.train, vp, wsb, g, reps=1, rounds=2)
     build_ms = timed(lambda: ctx.vf_build(d, w.train, L, vp, wsb, g), reps=2)
     wsq = ctx.query_workspace(d, w.cand, uprm, L)
     sc = torch.empty(w.cand.n, dtype=torch.float32, device="cuda")
+    tuner.tune_query(d, g, L, w.train.n, w.cand, uprm, wsq)
     q_ms = timed(lambda: ctx.vf_query_views(d, g, L, w.train.n, w.cand, uprm, wsq, scores=sc))
     gprm = _lib.default_uq_params(use_graph=1)
     side = torch.cuda.Stream()
@@ -432,7 +459,9 @@ def batched_bench(ctx, uprm, timed, log):
            "speedup_batched_vs_plain": round(p_ms / q_ms, 3), "speedup_graph_vs_plain": round(p_ms / g_ms, 3),
            "query_stages_ms": {k: round(v, 4) for k, v in stages.items()},
            "raster_uq_roofline": query_valu(cnt[3], stages, q_ms),
-           "hbm": hbm_fractions(stage_traffic("batched", "query"), stages)}
+           "hbm": hbm_fractions(stage_traffic("batched", "query"), stages),
+           "schedules": {"tuning": ctx.get_tuning(), "table": tuner.table}}
+    ctx.set_tuning(**saved)
     log(f"batched workload {out} (setup and runs {time.time() - t0:.1f}s)")
     del wsb, wsq, g, d
     torch.cuda.empty_cache()
@@ -460,6 +489,10 @@ def precision_bench(ctx, uprm, timed, log):
                        f"candidates 320x240 ({px} px), SH degree {L}"}
     ws = ctx.query_workspace(d32, w.cand, uprm, L)
     s32 = torch.empty(w.cand.n, dtype=torch.float32, device="cuda")
+    from paper_2605_30342_amd.autotune import Autotuner
+    saved = ctx.get_tuning()
+    tuner = Autotuner(ctx)
+    tuner.tune_query(d32, g32, L, w.train.n, w.cand, uprm, ws, reps=1, rounds=2)
     t32 = timed(lambda: ctx.vf_query_views(d32, g32, L, w.train.n, w.cand, uprm, ws, scores=s32))
     stages = stage_times(ctx, lambda: ctx.vf_query_views(d32, g32, L, w.train.n, w.cand, uprm, ws, scores=s32), 3,
                          torch)
@@ -503,6 +536,8 @@ def precision_bench(ctx, uprm, timed, log):
                                  "map_rel_l1_diff_field_only": l1(mg), "map_rel_l1_diff_attributes_only": l1(ma),
                                  "sum_abs_H_over_abs_score": float((m32.abs().sum() / m32.sum().abs()).item())}
         del dh, gh, wsh, ws1, ws1h, m32, mh, mg, ma
+    out["schedules"] = {"tuning": ctx.get_tuning(), "table": tuner.table}
+    ctx.set_tuning(**saved)
     out["per_map_error_vs_fp64"] = precision_subset_errors(ctx, w, L, log)
     log(f"precision workload {out} (setup and runs {time.time() - t0:.1f}s)")
     del ws, g32, d32

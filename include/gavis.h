@@ -350,7 +350,8 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
  *            all views by decreasing list length, sorted on the device before
  *            the blend, so that the longest tiles start first).
  * Results do not depend on the choice (VF CONST's float atomics may add in
- * another order).  Defaults 64 / 256, order 0. */
+ * another order).  Defaults: VF CONST 64 records, order 2; VF QUERY 256
+ * records, order 0. */
 typedef struct {
     int32_t vis_batch;
     int32_t uq_batch;

@@ -331,7 +331,7 @@ class Context:
         st = self.L.gv_workspace_check(self.h, ctypes.byref(ws.plan), _ptr(ws.buf), out, _stream(stream))
         return st, (int(out[0]), int(out[1]), int(out[2]), int(out[3]))
 
-    def set_tuning(self, vis_batch: int = 64, uq_batch: int = 256, vis_order: int = 0, uq_order: int = 0):
+    def set_tuning(self, vis_batch: int = 64, uq_batch: int = 256, vis_order: int = 2, uq_order: int = 0):
         t = _lib.gv_tuning(vis_batch, uq_batch, vis_order, uq_order)
         check(self.L.gv_set_tuning(self.h, ctypes.byref(t)))
 

@@ -1126,9 +1126,11 @@ __global__ __launch_bounds__(WG) void k_ranges(const uint32_t *__restrict__ key,
     }
 }
 
-// Sort keys of the cost-ordered tile schedule: tile t's list length,
-// complemented so that an ascending sort puts the longest first; values the
-// tile ids; *count = T for the sort.
+// Sort keys of the cost-ordered tile schedule: tile t's list length, capped
+// at 2^16 - 1 and complemented in 16 bits so that an ascending two-pass sort
+// puts the longest first (lists past the cap, rare, keep tile order among
+// themselves); values the tile ids; *count = T for the sort.
+constexpr int TILE_COST_BITS = 16;
 __global__ __launch_bounds__(WG) void k_tile_cost(const uint2 *__restrict__ ranges, uint32_t T,
                                                   uint32_t *__restrict__ key, uint32_t *__restrict__ val,
                                                   uint32_t *__restrict__ count) {
@@ -1136,7 +1138,8 @@ __global__ __launch_bounds__(WG) void k_tile_cost(const uint2 *__restrict__ rang
     if (t == 0) *count = T;
     if (t >= T) return;
     const uint2 r = ranges[t];
-    key[t] = ~(r.y - r.x);
+    constexpr uint32_t cap = (1u << TILE_COST_BITS) - 1u;
+    key[t] = cap - min(r.y - r.x, cap);
     val[t] = t;
 }
 
@@ -1333,7 +1336,7 @@ const uint32_t *launch_tile_order(const uint2 *ranges, uint32_t T, uint32_t *buf
                                   uint32_t *dtot, hipStream_t s) {
     uint32_t *k0 = buf, *v0 = buf + T, *k1 = buf + 2 * (uint64_t)T, *v1 = buf + 3 * (uint64_t)T;
     hipLaunchKernelGGL(k_tile_cost, dim3((T + WG - 1) / WG), dim3(WG), 0, s, ranges, T, k0, v0, count);
-    const int r = launch_radix_sort(k0, v0, k1, v1, count, 32, false, hist, dtot, s, DEAD_KEY, nullptr, T);
+    const int r = launch_radix_sort(k0, v0, k1, v1, count, TILE_COST_BITS, false, hist, dtot, s, DEAD_KEY, nullptr, T);
     return r ? v1 : v0;
 }
 

@@ -258,7 +258,7 @@ struct gv_context {
     unsigned char *scratch = nullptr;
     std::string scratch_err;
     bool capturing = false;
-    gv_tuning tuning = {64, 256, 0, 0};
+    gv_tuning tuning = {64, 256, 2, 0};   // the autotuned choice on the room workload
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     // stage timing
     bool prof_on = false;

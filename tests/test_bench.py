@@ -90,3 +90,21 @@ def test_hbm_fractions_sum_the_binning_stages():
     assert abs(r["project"]["frac"] - 0.5) < 1e-9           # 8 GB in 2 ms = 4 TB/s
     assert abs(r["projection_and_binning"]["frac"] - 0.5) < 1e-9
     assert r["projection_and_binning"]["bytes"] == 16e9
+
+
+def test_last_calls_pick_one_build_and_the_timed_query():
+    """The counter summary takes the last one-pass build and the last query
+    that does not count pairs, each from its view-table upload to its last
+    kernel (trailing copies of other work left out)."""
+    b = _bench_module()
+    call = ["__amd_rocclr_copyBuffer", "k_fill_u32(x)", "void k_count<float>(x)", "k_project(x)"]
+    rows = []
+    seqs = [call + ["void k_raster_vis<64>(x)", "k_vf_accum(x)"],
+            call + ["void k_raster_uq<256, false, false, false, false>(x)", "k_scores(x)", "k_argmax(x)"],
+            call + ["void k_raster_uq<256, false, true, false, false>(x)", "k_scores(x)"],
+            ["__amd_rocclr_copyBuffer", "void at::vectorized_elementwise_kernel<4>(x)"]]
+    for seq in seqs:
+        rows += [(len(rows) + i, n, 0.0, 0, 1) for i, n in enumerate(seq)]
+    bld, qry = b._last_calls(rows)
+    assert [b._kernel_base(r[1]) for r in bld][-2:] == ["k_raster_vis", "k_vf_accum"] and len(bld) == 6
+    assert "false, false, false, false" in qry[4][1] and b._kernel_base(qry[-1][1]) == "k_argmax"
