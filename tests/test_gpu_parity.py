@@ -835,6 +835,38 @@ def test_serving_results_alone_equal_results_in_the_mix(ctx):
     assert checked == {0, 1, 2}
 
 
+def test_serving_relaunches_batches_whose_estimate_was_too_small(ctx):
+    """With the backend's capacity estimates shrunk below the truth (slack
+    0.3 of the learnt per-view rates), batches overflow their workspaces; the
+    backend plans them exactly and launches them again on their slot, and
+    every request still gets the scores of the same request run alone."""
+    say("case: serving with estimates too small: overflow, exact re-plan, relaunch")
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd.api import DeviceScene
+    from paper_2605_30342_amd.serve import DONE, GpuBackend, Server
+    be = GpuBackend(ctx, n_slots=2, slack=0.3)
+    sc = scenes.tiny_scene(2000, seed=70)
+    train = scenes.sphere_cameras(6, 71, width=96, height=96)
+    dsc = DeviceScene(sc)
+    g = ctx.vf_build(dsc, train, 2)
+    be.add_scene("s", dsc, g, 2, train.n)
+    reqs = [scenes.sphere_cameras(3 + i % 3, 300 + i, width=64, height=48) for i in range(8)]
+    srv = Server(be, memory_budget=1 << 30, n_slots=2, max_batch_views=8)
+    rids = [srv.submit("s", c) for c in reqs]
+    srv.run_until_idle(timeout=120.0)
+    torch.cuda.synchronize()
+    say(f"  relaunches {be.relaunches}, exact sizings {be.exact_sizings}, {srv.stats()}")
+    assert be.relaunches > 0
+    prm = _lib.default_uq_params()
+    for rid, c in zip(rids, reqs):
+        r = srv.requests[rid]
+        assert r.status == DONE, r.error
+        s_, _ = ctx.vf_query_views(dsc, g, 2, train.n, c, prm)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(r.scores, s_.cpu().numpy(), rtol=1e-6, atol=1e-6)
+
+
 # ---------------------------------------------------------------- density control (Alg. 5)
 
 def test_multiview_visibility_matches_oracle(ctx):
