@@ -8,7 +8,10 @@ request plus the following pending requests of the same scene (up to a view
 budget), asks the backend for the workspace bytes of that batch, and admits
 it if the bytes fit in the free memory budget; otherwise it waits for memory
 to come back (the oldest request is never bypassed, so large requests do not
-starve).  Batches of different scenes run concurrently on different
+starve).  A request whose exact bytes exceed the whole budget is served in
+chunks of its views (halved until each fits; a view's score does not depend
+on the other views of its call), and only a single view that does not fit
+is rejected.  Batches of different scenes run concurrently on different
 slots.  Completion is detected by polling the slot's event; each request's
 latency is completion time minus arrival time.
 
@@ -28,7 +31,7 @@ import numpy as np
 PENDING, RUNNING, DONE, FAILED, CANCELLED, REJECTED = "pending", "running", "done", "failed", "cancelled", "rejected"
 
 
-@dataclass
+@dataclass(eq=False)                      # compared by identity (chunks share their request's id)
 class Request:
     rid: int
     scene_id: Any
@@ -39,6 +42,9 @@ class Request:
     t_done: Optional[float] = None
     scores: Optional[np.ndarray] = None
     error: Optional[str] = None
+    parent: Optional["Request"] = None   # set on a chunk of a request too large for the budget
+    offset: int = 0                      # a chunk's first view within its request
+    parts_left: int = 0                  # on a split request: chunks not yet done
 
     @property
     def n_views(self) -> int:
@@ -49,7 +55,7 @@ class Request:
         return None if self.t_done is None else self.t_done - self.t_arrival
 
 
-@dataclass
+@dataclass(eq=False)
 class Batch:
     reqs: List[Request]
     slot: int
@@ -78,6 +84,7 @@ class Server:
         self._next = 0
         self.batches_launched = 0
         self.merged_requests = 0
+        self.split_requests = 0
 
     # ---------------------------------------------------------------- client side
     def submit(self, scene_id, cams, t_arrival: Optional[float] = None) -> int:
@@ -89,12 +96,17 @@ class Server:
         return rid
 
     def cancel(self, rid: int) -> bool:
+        """Cancels a request none of whose views has started."""
         r = self.requests.get(rid)
         if r is None or r.status != PENDING:
             return False
         r.status = CANCELLED
-        self.pending = deque(x for x in self.pending if x.rid != rid)
+        self._drop_pending(r)
         return True
+
+    def _drop_pending(self, root: Request) -> None:
+        """Removes a request and every pending chunk of it from the queue."""
+        self.pending = deque(x for x in self.pending if x is not root and x.parent is not root)
 
     # ---------------------------------------------------------------- scheduling
     def _form_batch(self):
@@ -130,9 +142,11 @@ class Server:
                 self._fail([self.pending[0]], str(e))
                 continue
             if nbytes > self.budget:
-                for r in batch:
-                    r.status, r.error = REJECTED, f"needs {nbytes} bytes, budget {self.budget}"
-                    self.pending.remove(r)
+                head = batch[0]                          # never merged: it alone exceeds a share
+                if head.n_views > 1:
+                    self._split(head)
+                else:
+                    self._end(head, REJECTED, self.be.now(), msg=f"a view needs {nbytes} bytes, budget {self.budget}")
                 continue
             if nbytes > self.budget - self.in_use:
                 return                                   # wait for memory (FIFO head is not bypassed)
@@ -147,33 +161,75 @@ class Server:
             for r in batch:
                 self.pending.remove(r)
                 r.status, r.t_start = RUNNING, t
+                if r.parent is not None and r.parent.status == PENDING:
+                    r.parent.status, r.parent.t_start = RUNNING, t
             self.in_use += nbytes
             self.running.append(Batch(batch, slot, handle, nbytes, t))
             self.batches_launched += 1
             self.merged_requests += len(batch) - 1
 
+    def _split(self, r: Request) -> None:
+        """Replaces the pending head r (a request or a chunk of one) by two
+        chunks holding the first and the second half of its views."""
+        root = r.parent or r
+        h = r.n_views // 2
+        parts = [Request(root.rid, r.scene_id, r.cams.subset(np.arange(lo, hi)), r.t_arrival,
+                         parent=root, offset=r.offset + lo) for lo, hi in ((0, h), (h, r.n_views))]
+        if r.parent is None:
+            root.scores = np.zeros(root.n_views)
+            root.parts_left = 2
+            self.split_requests += 1
+        else:
+            root.parts_left += 1
+        assert self.pending[0] is r
+        self.pending.popleft()
+        self.pending.appendleft(parts[1])
+        self.pending.appendleft(parts[0])
+
+    def _end(self, r: Request, status: str, t: float, scores=None, msg=None) -> None:
+        """Settles a request or a chunk: a chunk writes its scores into its
+        request, which is done when its last chunk is; a chunk that fails or
+        is rejected ends its request so, and the request's pending chunks are
+        dropped."""
+        if r.status in (PENDING, RUNNING):
+            r.status, r.t_done, r.error = status, t, msg
+            if scores is not None and r.parent is None:
+                r.scores = np.asarray(scores)
+        if r in self.pending:
+            self.pending.remove(r)
+        root = r.parent
+        if root is None:
+            return
+        if root.status not in (PENDING, RUNNING):
+            return                                   # the request already ended (a chunk failed)
+        if status != DONE:
+            root.status, root.t_done, root.error = status, t, msg
+            self._drop_pending(root)
+            return
+        root.scores[r.offset:r.offset + r.n_views] = scores
+        root.parts_left -= 1
+        if root.parts_left == 0:
+            root.status, root.t_done = DONE, t
+
     def _fail(self, batch: List[Request], msg: str) -> None:
+        t = self.be.now()
         for r in batch:
-            r.status, r.error = FAILED, msg
-            if r in self.pending:
-                self.pending.remove(r)
+            self._end(r, FAILED, t, msg=msg)
 
     def _retire(self, b: Batch, status: str, scores=None, msg=None) -> None:
         t = self.be.now()
         off = 0
         for r in b.reqs:
             if r.status == RUNNING:          # requests already failed by a time-out stay failed
-                r.t_done = t
-                r.status = status
-                r.error = msg
-                if scores is not None:
-                    r.scores = np.asarray(scores[off:off + r.n_views])
+                self._end(r, status, t, scores=None if scores is None else scores[off:off + r.n_views], msg=msg)
             off += r.n_views
         self.in_use -= b.nbytes
         self.free_slots.append(b.slot)
         self.be.release(b.handle)
 
     def _poll(self) -> List[Request]:
+        """Retires the batches that completed; returns the requests that
+        ended (a split request once its last chunk has)."""
         finished = []
         for b in list(self.running):
             try:
@@ -195,11 +251,15 @@ class Server:
                 # slot and memory stay reserved until the backend reports done
                 for r in b.reqs:
                     if r.status == RUNNING:
-                        r.status, r.error, r.t_done = FAILED, "timed out", self.be.now()
+                        self._end(r, FAILED, self.be.now(), msg="timed out")
         return finished
 
     def step(self) -> List[Request]:
-        done = self._poll()
+        done = []
+        for r in self._poll():
+            root = r.parent or r
+            if root.status not in (PENDING, RUNNING) and all(x is not root for x in done):
+                done.append(root)
         self._admit()
         return done
 
@@ -228,6 +288,7 @@ class Server:
                 "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if done else None,
                 "views_per_s": views / span if span > 0 else None,
                 "batches": self.batches_launched, "merged_requests": self.merged_requests,
+                "split_requests": self.split_requests,
                 "failed": sum(r.status == FAILED for r in self.requests.values()),
                 "rejected": sum(r.status == REJECTED for r in self.requests.values())}
 
@@ -367,15 +428,15 @@ class GpuBackend:
         (one counting pass, kept for the batch's launch and for later asks
         while it waits for memory)."""
         key = (scene_id, tuple(id(c) for c in cams_list))
-        if key in self._exact_plans:
-            return int(self._exact_plans[key].bytes)
+        if key in self._exact_plans:          # the entry holds the cameras, so their ids stay theirs
+            return int(self._exact_plans[key][1].bytes)
         cams = self._cams(cams_list)
         plan = self._plan(scene_id, cams)
         if limit is not None and plan.bytes > limit:
             plan = self._exact(self.scenes[scene_id], cams)
             if len(self._exact_plans) >= 64:
                 self._exact_plans.pop(next(iter(self._exact_plans)))
-            self._exact_plans[key] = plan
+            self._exact_plans[key] = (list(cams_list), plan)
         return int(plan.bytes)
 
     def _alloc(self, plan):
@@ -404,9 +465,8 @@ class GpuBackend:
     def launch(self, scene_id, cams_list, slot: int, nbytes: int):
         torch = self.torch
         cams = self._cams(cams_list)
-        plan = self._exact_plans.pop((scene_id, tuple(id(c) for c in cams_list)), None)
-        if plan is None:
-            plan = self._plan(scene_id, cams)
+        ent = self._exact_plans.pop((scene_id, tuple(id(c) for c in cams_list)), None)
+        plan = ent[1] if ent is not None else self._plan(scene_id, cams)
         ws = self._alloc(plan)
         scores = torch.empty(cams.n, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         h = {"scene": scene_id, "cams": cams, "ws": ws, "scores": scores, "stream": self.streams[slot],

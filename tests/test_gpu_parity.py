@@ -867,6 +867,41 @@ def test_serving_relaunches_batches_whose_estimate_was_too_small(ctx):
         np.testing.assert_allclose(r.scores, s_.cpu().numpy(), rtol=1e-6, atol=1e-6)
 
 
+def test_serving_splits_a_request_larger_than_the_budget(ctx):
+    """A request whose exact workspace exceeds the whole memory budget is
+    served in chunks of its views; its scores equal the request run alone
+    in one call, and a second request behind it is served too."""
+    say("case: serving a request larger than the memory budget, in chunks")
+    import torch
+    from paper_2605_30342_amd import _lib
+    from paper_2605_30342_amd.api import DeviceScene
+    from paper_2605_30342_amd.serve import DONE, GpuBackend, Server
+    be = GpuBackend(ctx, n_slots=2)
+    sc = scenes.tiny_scene(2000, seed=80)
+    train = scenes.sphere_cameras(6, 81, width=96, height=96)
+    dsc = DeviceScene(sc)
+    g = ctx.vf_build(dsc, train, 2)
+    be.add_scene("s", dsc, g, 2, train.n)
+    big = scenes.sphere_cameras(10, 82, width=96, height=96)
+    small = scenes.sphere_cameras(2, 83, width=64, height=48)
+    prm = _lib.default_uq_params()
+    full = int(ctx.query_plan_exact(dsc, big, prm, 2).bytes)
+    budget = int(0.6 * full)
+    srv = Server(be, memory_budget=budget, n_slots=2, max_batch_views=16)
+    rb, rs = srv.submit("s", big), srv.submit("s", small)
+    srv.run_until_idle(timeout=120.0)
+    torch.cuda.synchronize()
+    st = srv.stats()
+    say(f"  full request {full} bytes, budget {budget}: {st}")
+    assert st["split_requests"] == 1 and st["requests_done"] == 2
+    for rid, c in ((rb, big), (rs, small)):
+        r = srv.requests[rid]
+        assert r.status == DONE, r.error
+        s_, _ = ctx.vf_query_views(dsc, g, 2, train.n, c, prm)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(r.scores, s_.cpu().numpy(), rtol=1e-6, atol=1e-6)
+
+
 # ---------------------------------------------------------------- density control (Alg. 5)
 
 def test_multiview_visibility_matches_oracle(ctx):

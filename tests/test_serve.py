@@ -11,9 +11,12 @@ class FakeBackend:
     """Batch duration = fixed + per-view time; workspace = per-view bytes.
     Scores are deterministic per (scene, camera) so mixing can be checked."""
 
-    def __init__(self, bytes_per_view=100, t_fixed=1.0, t_view=0.1, fail_plan=(), fail_launch=(), stuck=()):
+    def __init__(self, bytes_per_view=100, t_fixed=1.0, t_view=0.1, fail_plan=(), fail_launch=(), stuck=(),
+                 scene_bytes_per_view=None, fail_after=None):
         self.t = 0.0
         self.bpv = bytes_per_view
+        self.scene_bpv = dict(scene_bytes_per_view or {})
+        self.fail_after = fail_after          # (scene, n): launches of that scene after the n-th fail
         self.t_fixed, self.t_view = t_fixed, t_view
         self.fail_plan, self.fail_launch, self.stuck = set(fail_plan), set(fail_launch), set(stuck)
         self.launches = []
@@ -28,13 +31,16 @@ class FakeBackend:
     def plan_bytes(self, scene_id, cams_list, limit=None):
         if scene_id in self.fail_plan:
             raise BackendError("plan failed")
-        return self.bpv * sum(c.n for c in cams_list)
+        return self.scene_bpv.get(scene_id, self.bpv) * sum(c.n for c in cams_list)
 
     def launch(self, scene_id, cams_list, slot, nbytes):
         if scene_id in self.fail_launch:
             raise BackendError("out of memory")
         assert slot not in self.live, "slot reused while busy"
         nv = sum(c.n for c in cams_list)
+        if self.fail_after is not None and scene_id == self.fail_after[0]:
+            if sum(s == scene_id for s, _, _ in self.launches) >= self.fail_after[1]:
+                raise BackendError("out of memory")
         h = {"slot": slot, "end": self.t + self.t_fixed + self.t_view * nv,
              "scores": np.concatenate([self.score(scene_id, c) for c in cams_list]), "scene": scene_id}
         self.live[slot] = h
@@ -118,14 +124,80 @@ def test_large_head_request_is_not_starved():
     assert srv.requests[1].status == DONE
 
 
-def test_too_large_request_is_rejected_and_others_proceed():
-    be = FakeBackend(bytes_per_view=100)
+def test_request_whose_single_view_exceeds_the_budget_is_rejected_and_others_proceed():
+    be = FakeBackend(bytes_per_view=100, scene_bytes_per_view={"x": 600})
     srv = Server(be, memory_budget=500, n_slots=2)
     big = srv.submit("x", cams(8, 0))
     ok = srv.submit("y", cams(2, 1))
     srv.run_until_idle(timeout=1e4)
     assert srv.requests[big].status == REJECTED
     assert srv.requests[ok].status == DONE
+    assert not any(s == "x" for s, _, _ in be.launches)
+    assert srv.in_use == 0 and not srv.pending
+
+
+def test_request_above_the_budget_is_served_in_chunks_of_its_views():
+    """8 views of 100 bytes against a 500-byte budget: halved into two
+    chunks of 4 views, run one after the other; the request gets the scores
+    of all its views in order, and counts once in the statistics."""
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=500, n_slots=2)
+    c = cams(8, 0)
+    big = srv.submit("x", c)
+    ok = srv.submit("y", cams(2, 1))
+    srv.run_until_idle(timeout=1e4)
+    r = srv.requests[big]
+    assert r.status == DONE and r.latency > 0
+    np.testing.assert_array_equal(r.scores, FakeBackend.score("x", c))
+    assert [nv for s, nv, _ in be.launches if s == "x"] == [4, 4]
+    assert srv.requests[ok].status == DONE
+    st = srv.stats()
+    assert st["requests_done"] == 2 and st["views_done"] == 10 and st["split_requests"] == 1
+    assert srv.in_use == 0 and not srv.pending
+
+
+def test_uneven_request_is_halved_until_every_chunk_fits():
+    """13 views of 100 bytes against a 300-byte budget: 13 is halved into 6
+    and 7, those into chunks of 3, 3, 3 and 4, the 4 into 2 and 2; the
+    scores land at their views' positions, and the request is running from
+    its first chunk on."""
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=300, n_slots=3)
+    c = cams(13, 3)
+    rid = srv.submit("x", c)
+    srv.step()
+    assert srv.requests[rid].status == "running"
+    srv.run_until_idle(timeout=1e4)
+    r = srv.requests[rid]
+    assert r.status == DONE
+    np.testing.assert_array_equal(r.scores, FakeBackend.score("x", c))
+    sizes = [nv for _, nv, _ in be.launches]
+    assert sum(sizes) == 13 and max(sizes) <= 3
+    assert srv.in_use <= 300
+
+
+def test_failed_chunk_fails_its_request_and_drops_its_other_chunks():
+    """The second chunk's launch fails: the request fails, no further chunk
+    of it runs, and other requests proceed."""
+    be = FakeBackend(bytes_per_view=100, fail_after=("x", 1))
+    srv = Server(be, memory_budget=400, n_slots=1)
+    big = srv.submit("x", cams(12, 0))                # chunks 3, 3, 3, 3
+    ok = srv.submit("y", cams(2, 1))
+    srv.run_until_idle(timeout=1e4)
+    assert srv.requests[big].status == FAILED
+    assert [nv for s, nv, _ in be.launches if s == "x"] == [3]
+    assert srv.requests[ok].status == DONE
+    assert srv.in_use == 0 and not srv.pending and sorted(srv.free_slots) == [0]
+
+
+def test_split_request_cannot_be_cancelled_once_a_chunk_runs():
+    be = FakeBackend(bytes_per_view=100)
+    srv = Server(be, memory_budget=400, n_slots=1)
+    big = srv.submit("x", cams(8, 0))
+    srv.step()
+    assert not srv.cancel(big)
+    srv.run_until_idle(timeout=1e4)
+    assert srv.requests[big].status == DONE
 
 
 def test_backend_failures_fail_only_their_requests():
