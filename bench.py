@@ -458,6 +458,7 @@ def batched_bench(ctx, uprm, timed, log):
            "plain_per_view_graph_replay_ms": round(pg_ms, 4),
            "speedup_batched_vs_plain": round(p_ms / q_ms, 3), "speedup_graph_vs_plain": round(p_ms / g_ms, 3),
            "query_stages_ms": {k: round(v, 4) for k, v in stages.items()},
+           "query_records": cnt[0], "query_instances": cnt[1],
            "raster_uq_roofline": query_valu(cnt[3], stages, q_ms),
            "hbm": hbm_fractions(stage_traffic("batched", "query"), stages),
            "schedules": {"tuning": ctx.get_tuning(), "table": tuner.table}}
@@ -502,6 +503,7 @@ def precision_bench(ctx, uprm, timed, log):
     out["f32"] = {"query_ms": round(t32, 4), "mpix_s": round(px / (t32 / 1e3) / 1e6, 3),
                   "scene_bytes": d32.nbytes() + g32.numel() * 4,
                   "query_stages_ms": {k: round(v, 4) for k, v in stages.items()},
+                  "query_records": cnt[0], "query_instances": cnt[1],
                   "raster_uq_roofline": query_valu(cnt[3], stages, t32),
                   "hbm": hbm_fractions(stage_traffic("precision", "query"), stages)}
     for dt in ("f16", "bf16"):
@@ -936,6 +938,8 @@ def main():
         "query_stages_ms": {k: round(v, 4) for k, v in stages_q.items()},
         "hbm": hbm,
         "pairs": {"raster_vis": int(pairs_vis), "raster_uq": int(pairs_uq)},
+        "records": {"build": cnt_b[0], "query": cnt_q[0]},
+        "instances": {"build": cnt_b[1], "query": cnt_q[1]},
         "roofline": roof,
         "raster_uq_roofline": uq_frac,
         "batching": batching,

@@ -885,8 +885,13 @@ def test_serving_splits_a_request_larger_than_the_budget(ctx):
     big = scenes.sphere_cameras(10, 82, width=96, height=96)
     small = scenes.sphere_cameras(2, 83, width=64, height=48)
     prm = _lib.default_uq_params()
-    full = int(ctx.query_plan_exact(dsc, big, prm, 2).bytes)
-    budget = int(0.6 * full)
+    def exact(c):
+        return int(ctx.query_plan_exact(dsc, c, prm, 2).bytes)
+    full = exact(big)
+    # the workspace has a part independent of the view count, so the budget
+    # is set to what each half of the request needs
+    budget = max(exact(big.subset(range(5))), exact(big.subset(range(5, 10))), exact(small))
+    assert budget < full
     srv = Server(be, memory_budget=budget, n_slots=2, max_batch_views=16)
     rb, rs = srv.submit("s", big), srv.submit("s", small)
     srv.run_until_idle(timeout=120.0)
