@@ -672,11 +672,25 @@ __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ 
             const uint64_t e = s + (uint64_t)i * WG + t;
             k[i] = e < end ? keys[e] : 0u;
         }
+        // runs of equal digits among a thread's items are counted before
+        // one atomic each: where most keys share a digit (the high digit of
+        // depths, the view bits of tile ids) this avoids 64-way conflicts
+        // on one LDS counter per item
+        uint32_t dprev = 0, run = 0;
 #pragma unroll
         for (int i = 0; i < RITEMS; ++i) {
             const uint64_t e = s + (uint64_t)i * WG + t;
-            if (e < end && (k[i] & TILE_KEY_MASK) != drop) atomicAdd(&h[w][(k[i] >> shift) & mask], 1u);
+            if (e < end && (k[i] & TILE_KEY_MASK) != drop) {
+                const uint32_t d = (k[i] >> shift) & mask;
+                if (run != 0 && d != dprev) {
+                    atomicAdd(&h[w][dprev], run);
+                    run = 0;
+                }
+                dprev = d;
+                ++run;
+            }
         }
+        if (run != 0) atomicAdd(&h[w][dprev], run);
     }
     __syncthreads();
     hist[(size_t)t * gridDim.x + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
