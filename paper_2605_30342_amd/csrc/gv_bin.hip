@@ -744,6 +744,8 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) 
     return base + inc - x;
 }
 
+// kout NULL: only the values are written (the last pass of a sort whose
+// sorted keys are not needed).
 // With drop (see k_radix_hist) the kept pairs are written compacted and their
 // total goes to *n_kept (by one thread of block 0), the count the following
 // passes take.  With gdst set, gdst[o] = gsrc[value] is also written for
@@ -842,10 +844,12 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
             for (uint32_t j = t; j < cnt; j += WG) {
                 const uint32_t key = sk[j], val = sv[j];
                 const uint32_t o = goff[(key >> shift) & mask] + j;
-                kout[o] = key;
+                if (kout) kout[o] = key;
                 vout[o] = val;
                 gdst[o] = gsrc[val];
             }
+        } else if (!kout) {
+            for (uint32_t j = t; j < cnt; j += WG) vout[goff[(sk[j] >> shift) & mask] + j] = sv[j];
         } else {
             for (uint32_t j = t; j < cnt; j += WG) {
                 const uint32_t key = sk[j];
@@ -1299,7 +1303,7 @@ size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / S
 // the indices 0..n-1 and v0 is only used as a buffer.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
-                      uint64_t n_cap, const uint32_t *gather_src, uint32_t *gather_dst) {
+                      uint64_t n_cap, const uint32_t *gather_src, uint32_t *gather_dst, bool keys_out) {
     int cur = 0;
     // about one tile of pairs per block at the capacity: fewer, fuller blocks
     // than a fixed grid when the sort is short
@@ -1318,7 +1322,8 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(WG), 0, s, ki, n_dev, shift, nb, dk, hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(WG), 0, s, hist, dtot, nblk);
         const bool last = p == passes - 1;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(WG), 0, s, ki, vin, ko, vo, n_dev, shift, nb, dk,
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(WG), 0, s, ki, vin, last && !keys_out ? nullptr : ko, vo,
+                           n_dev, shift, nb, dk,
                            hist, dtot, kept, last ? gather_src : nullptr, last ? gather_dst : nullptr);
         if (kept) n_dev = kept;
         cur ^= 1;

@@ -460,8 +460,9 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
         StageScope sc(ctx, ST_SORT_DEPTH, s);
         // scanned emission: the last pass also gathers each record's tile
         // count into depth order
+        // (only the depth order of the records is used, not their sorted keys)
         dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R, ntr,
-                                 icnt);
+                                 icnt, false);
     }
     const uint32_t *sval = dres ? v1 : v0;
     {

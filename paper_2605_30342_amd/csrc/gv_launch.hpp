@@ -76,9 +76,12 @@ void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint6
 // *n_kept for the rest of the sort.  n_cap: the most pairs *n_dev can hold
 // (sizes the grid).  gather_dst (optional): the last pass also writes
 // gather_dst[i] = gather_src[sorted value i] for every output position i.
+// keys_out false: the sorted keys are not written (only the values are
+// sorted into the result buffer).
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
-                      uint64_t n_cap, const uint32_t *gather_src = nullptr, uint32_t *gather_dst = nullptr);
+                      uint64_t n_cap, const uint32_t *gather_src = nullptr, uint32_t *gather_dst = nullptr,
+                      bool keys_out = true);
 void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
 // Density control (Alg. 5): box corner and sides in FP64, particle scale.
 struct VirtArgs {
