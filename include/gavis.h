@@ -377,7 +377,8 @@ size_t gv_workspace_bytes(const gv_workspace *plan);
 
 /* Next-best view (eq. i_gain): index of the largest of the n device scores,
  * lowest index on exact ties, NaN never wins (-1 if all are NaN).  Runs a
- * device argmax, copies one int32 to `*best` (host) and synchronises. */
+ * device argmax that writes the index into pinned host memory of the
+ * context, synchronises the stream and stores it in `*best` (host). */
 gv_status select_next_view(gv_context *ctx, const float *scores, int32_t n, int32_t *best, void *hip_stream);
 
 #ifdef __cplusplus

@@ -595,34 +595,61 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(unsigned long long *__rest
     }
 }
 
+// Slot of element i of a scan block in LDS: one pad word per 32, so that a
+// thread reading its SCAN_ITEMS consecutive elements and a wave reading 64
+// consecutive ones both spread over the banks.
+__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                   const uint32_t *n_dev, uint64_t n_host,
                                                   const unsigned long long *__restrict__ blk) {
     const uint64_t n = scan_n(n_dev, n_host);
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
     if (base > n) return;
+    __shared__ uint32_t tile[SCAN_BLOCK + SCAN_BLOCK / 32];
+    __shared__ unsigned long long wsum[WAVES];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // the block's elements, read with consecutive lanes on consecutive
+    // elements (zero past n)
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int i = k * WG + t;
+        const uint64_t e = base + (uint64_t)i;
+        tile[scan_slot(i)] = e < n ? in[e] : 0u;
+    }
+    __syncthreads();
     // each thread owns SCAN_ITEMS consecutive elements
-    const uint64_t my = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     unsigned long long s = 0;
+#pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = (my + k < n) ? in[my + k] : 0u;
+        v[k] = tile[scan_slot(t * SCAN_ITEMS + k)];
         s += v[k];
     }
-    __shared__ unsigned long long buf[WG];
-    buf[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < WG; off <<= 1) {
-        const unsigned long long y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0ull;
-        __syncthreads();
-        buf[threadIdx.x] += y;
-        __syncthreads();
+    // exclusive scan of the threads' sums: within the wave, then over waves
+    unsigned long long inc = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
     }
-    unsigned long long run = blk[blockIdx.x] + buf[threadIdx.x] - s;
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    unsigned long long run = blk[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) run += q < w ? wsum[q] : 0ull;
+#pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (my + k < n) out[my + k] = (uint32_t)run;
-        else if (my + k == n) out[n] = (uint32_t)run;
+        tile[scan_slot(t * SCAN_ITEMS + k)] = (uint32_t)run;
         run += v[k];
+    }
+    __syncthreads();
+    // out[e] for e <= n (out[n]: the total), consecutive lanes again
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int i = k * WG + t;
+        const uint64_t e = base + (uint64_t)i;
+        if (e <= n) out[e] = tile[scan_slot(i)];
     }
 }
 

@@ -241,7 +241,8 @@ struct ProfEvent {
 struct gv_context {
     int device = 0;
     unsigned long long *dev_counters = nullptr;   // sizing counters
-    int32_t *dev_best = nullptr;
+    int32_t *host_best = nullptr;       // pinned host word the device argmax writes
+    int32_t *host_best_dev = nullptr;   // its device address
     ViewDev *dev_views = nullptr;                 // view table for sizing passes
     size_t dev_views_cap = 0;
     std::vector<ViewDev> host_views;
@@ -543,8 +544,11 @@ gv_status gv_create(int device, gv_context **out) {
     gv_context *c = new gv_context();
     c->device = device;
     if (hipMalloc((void **)&c->dev_counters, 8 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void **)&c->dev_best, 64) != hipSuccess) {
+        hipHostMalloc((void **)&c->host_best, 64, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->host_best_dev, c->host_best, 0) != hipSuccess) {
         if (c->dev_counters) (void)hipFree(c->dev_counters);
+        if (c->host_best) (void)hipHostFree(c->host_best);
+        (void)hipGetLastError();
         delete c;
         return fail(GV_ERR_OUT_OF_MEMORY, "cannot allocate context counters");
     }
@@ -568,7 +572,7 @@ void gv_destroy(gv_context *ctx) {
     if (!ctx) return;
     DeviceGuard dg(ctx->device);
     if (ctx->dev_counters) (void)hipFree(ctx->dev_counters);
-    if (ctx->dev_best) (void)hipFree(ctx->dev_best);
+    if (ctx->host_best) (void)hipHostFree(ctx->host_best);
     if (ctx->dev_views) (void)hipFree(ctx->dev_views);
     for (const ProfEvent &e : ctx->prof_pending) {
         (void)hipEventDestroy(e.a);
@@ -1289,12 +1293,12 @@ gv_status select_next_view(gv_context *ctx, const float *scores, int32_t n, int3
     if (n < 1) return fail(GV_ERR_INVALID_ARG, "n must be >= 1");
     DeviceGuard dg(ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    launch_argmax(scores, n, ctx->dev_best, s);
+    // the argmax writes the index straight into pinned host memory: no copy
+    // operation after the kernel, only the wait for it
+    launch_argmax(scores, n, ctx->host_best_dev, s);
     GV_HIP(hipGetLastError());
-    int32_t h = -1;
-    GV_HIP(hipMemcpyAsync(&h, ctx->dev_best, sizeof(h), hipMemcpyDeviceToHost, s));
     GV_HIP(hipStreamSynchronize(s));
-    *best = h;
+    *best = *reinterpret_cast<volatile int32_t *>(ctx->host_best);
     return GV_OK;
 }
 
