@@ -1365,7 +1365,7 @@ size_t emit_post_words(uint64_t rcap) { return (size_t)((rcap + EMIT_RPB - 1) / 
 
 void launch_emit_scanned(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
                          uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit_scanned, dim3(4096), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
+    hipLaunchKernelGGL(k_emit_scanned, dim3(8192), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
 }
 
 void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, Status *st, uint64_t rcap,
