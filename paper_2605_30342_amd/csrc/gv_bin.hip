@@ -211,7 +211,16 @@ template <typename TG>
 // each step is the same for the whole wave (scalar loads).
 __global__ __launch_bounds__(WG) void k_count(GaussIn<TG> G, const ViewDev *__restrict__ views, int nv,
                                               float znear, float lowpass, float cut, uint32_t *__restrict__ cnt,
-                                              uint32_t *__restrict__ vmask, int mw) {
+                                              uint32_t *__restrict__ vmask, int mw, uint32_t *__restrict__ clr0,
+                                              uint32_t n0, uint32_t *__restrict__ clr1, uint64_t n1) {
+    // the call's zero fills (status words, tile ranges) ride along, so
+    // that they need no launches of their own
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n1; i += (uint64_t)gridDim.x * WG) {
+        if (i < n0) clr0[i] = 0u;
+        clr1[i] = 0u;
+    }
+    if (blockIdx.x == 0 && n0 > n1)
+        for (uint32_t i = n1 + threadIdx.x; i < n0; i += WG) clr0[i] = 0u;
     const int sub = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t g = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     if (g >= G.n) return;
@@ -338,6 +347,10 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
     __shared__ uint8_t mk[WAVES][64];      // 1 where an entry starts at that record of the chunk
     __shared__ float4 sgm[WAVES][64];      // each entry's Gaussian: mean, opacity
     __shared__ double sgS[WAVES][6][64];   // its 3D covariance (six terms, one row per term)
+    // the query's SH coefficients of each entry's Gaussian (K per entry, rows
+    // of K + 1 floats so that entries fall in different banks)
+    constexpr int GROW = MODE == 1 ? K + 1 : 1;
+    __shared__ float sgG[WAVES][MODE == 1 ? 64 : 1][GROW];
     if (st->overflow & 1u) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t ne = (uint64_t)G.n * PROJ_SPLIT;
@@ -370,6 +383,13 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
             sgm[w][lane] = make_float4(m[0], m[1], m[2], G.opacity(g));
 #pragma unroll
             for (int k = 0; k < 6; ++k) sgS[w][k][lane] = S[k];
+            if constexpr (MODE == 1) {
+                // read only where the records use them (real Gaussians, |P| > 0)
+                if (n_train > 0.0f && g < G.n - G.n_virtual) {
+#pragma unroll
+                    for (int kk = 0; kk < K; ++kk) sgG[w][lane][kk] = load_f(gamma, (int64_t)kk * G.n + g);
+                }
+            }
         }
         uint32_t total = 0;
         if (own) {
@@ -466,7 +486,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                 sh_eval<L>(dx, dy, dz, Y);
                                 float vt = 0.0f;
 #pragma unroll
-                                for (int kk = 0; kk < K; ++kk) vt = fmaf(load_f(gamma, (int64_t)kk * G.n + g), Y[kk], vt);
+                                for (int kk = 0; kk < K; ++kk) vt = fmaf(sgG[w][q][kk], Y[kk], vt);
                                 vt = fminf(fmaxf(vt, 0.0f), n_train);
                                 vis = (vt >= n_train) ? 1.0f : 1.0f - expf(n_train * log1pf(-vt / n_train));
                             }
@@ -1226,15 +1246,19 @@ int mask_words(int nv) {
 }
 
 void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt,
-                  uint32_t *vmask, hipStream_t s) {
+                  uint32_t *vmask, uint32_t *clr0, uint32_t n0, uint32_t *clr1, uint64_t n1, hipStream_t s) {
     static_assert(PROJ_SPLIT == WAVES, "one view subset per wave");
     const unsigned grid = (unsigned)((a.n + 63) / 64);
-    if (grid == 0) return;
+    if (grid == 0) {   // no Gaussian: the fills alone
+        launch_fill_u32(clr0, n0, 0u, s);
+        launch_fill_u32(clr1, n1, 0u, s);
+        return;
+    }
     const int mw = mask_words(nv);
     switch (a.dtype) {
-    case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
-    case 1: hipLaunchKernelGGL(k_count<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
-    default: hipLaunchKernelGGL(k_count<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw); break;
+    case 0: hipLaunchKernelGGL(k_count<float>, dim3(grid), dim3(WG), 0, s, gin<float>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw, clr0, n0, clr1, n1); break;
+    case 1: hipLaunchKernelGGL(k_count<_Float16>, dim3(grid), dim3(WG), 0, s, gin<_Float16>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw, clr0, n0, clr1, n1); break;
+    default: hipLaunchKernelGGL(k_count<uint16_t>, dim3(grid), dim3(WG), 0, s, gin<uint16_t>(a), views, nv, p.znear, p.lowpass, p.cut, cnt, vmask, mw, clr0, n0, clr1, n1); break;
     }
 }
 

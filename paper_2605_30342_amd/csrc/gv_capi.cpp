@@ -447,8 +447,9 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
 
     {
         StageScope sc(ctx, ST_CULL, s);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4, 0u, s);
-        launch_count(a, views, nv, geo, cnt, vmask, s);
+        // the count also clears the status and the tile ranges
+        launch_count(a, views, nv, geo, cnt, vmask, reinterpret_cast<uint32_t *>(st), sizeof(Status) / 4,
+                     reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, s);
         const uint64_t ne = (uint64_t)a.n * PROJ_SPLIT;
         launch_scan(cnt, offs, nullptr, ne, ne, blk, &st->R_total, &st->R_eff, R, &st->overflow, 1u, s);
     }
@@ -469,7 +470,6 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     {
         StageScope sc(ctx, ST_EMIT, s);
         const float qc = (float)(0.5 * geo.cut / std::log(2.0));
-        launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), (uint64_t)tiles * 2, 0u, s);
         if (lookback) {
             launch_emit(sval, bin, post, st, R, M, qc, (uint32_t)tiles, ik0, iv0, s);
         } else {

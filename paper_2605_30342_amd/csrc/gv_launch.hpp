@@ -58,8 +58,9 @@ void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint
 
 // Words of the per-(Gaussian, view subset) visibility mask for nv views.
 int mask_words(int nv);
+// Also zeroes n0 words at clr0 and n1 words at clr1 (one launch for all).
 void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, uint32_t *cnt, uint32_t *vmask,
-                  hipStream_t s);
+                  uint32_t *clr0, uint32_t n0, uint32_t *clr1, uint64_t n1, hipStream_t s);
 void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
