@@ -10,7 +10,9 @@ workgroup dispatcher drains in order).  Which
 schedule wins depends on the workload (list lengths per tile, image sizes,
 Gaussian footprints, the number of views), so the tuner times every
 candidate on the caller's actual workload, checks that the outputs agree, and
-caches the winner per workload class in a JSON file.
+caches the winner per workload class in a JSON file.  A candidate must beat
+the library's default schedule by more than TIE (run-to-run noise of the
+timings) to replace it, so that equal schedules do not flip between runs.
 """
 from __future__ import annotations
 
@@ -25,6 +27,17 @@ import torch
 BATCHES = (64, 128, 256)
 ORDERS = (0, 1, 2)
 CANDIDATES = tuple(itertools.product(BATCHES, ORDERS))
+# the library's defaults (gv_tuning) and the margin a candidate must beat them by
+DEFAULT = {"build": (64, 2), "query": (256, 0)}
+TIE = 0.005
+
+
+def pick(times: dict, default) -> tuple:
+    """The fastest candidate, or the default when it is within TIE of it."""
+    best = min(times, key=times.get)
+    if default in times and times[default] <= times[best] * (1.0 + TIE):
+        return default
+    return best
 
 
 def workload_class(mode: str, n_gaussians: int, cams) -> str:
@@ -92,7 +105,7 @@ class Autotuner:
                     ref = out
                 elif not torch.equal(out, ref):
                     raise RuntimeError(f"query results differ between schedules ({_label(c)})")
-        best = min(times, key=times.get)
+        best = pick(times, DEFAULT["query"])
         self._set("query", *best)
         self.table[key] = {"uq_batch": best[0], "uq_order": best[1],
                            "ms": {_label(k): round(v, 4) for k, v in times.items()}}
@@ -117,7 +130,7 @@ class Autotuner:
                     scale = ref.abs().amax(dim=0, keepdim=True) + 1e-30
                     if ((out - ref).abs() > 1e-5 * scale).any():
                         raise RuntimeError(f"build results differ between schedules ({_label(c)})")
-        best = min(times, key=times.get)
+        best = pick(times, DEFAULT["build"])
         self._set("build", *best)
         self.table[key] = {"vis_batch": best[0], "vis_order": best[1],
                            "ms": {_label(k): round(v, 4) for k, v in times.items()}}

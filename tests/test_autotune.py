@@ -1,7 +1,7 @@
 """The autotuner's cache: a cached choice is applied to the context on a
 cache hit exactly as a fresh tuning run applies it (CPU, stub context)."""
 from paper_2605_30342_amd import scenes
-from paper_2605_30342_amd.autotune import CANDIDATES, Autotuner, workload_class
+from paper_2605_30342_amd.autotune import CANDIDATES, DEFAULT, TIE, Autotuner, pick, workload_class
 
 
 class StubContext:
@@ -63,3 +63,15 @@ def test_apply_reports_a_miss():
     ctx = StubContext()
     assert not Autotuner(ctx).apply("query", 10, cams)
     assert ctx.set_calls == 0
+
+
+def test_default_schedule_wins_ties_within_the_noise_margin():
+    """A candidate replaces the default only when faster by more than TIE."""
+    d = DEFAULT["build"]
+    times = {c: 3.0 for c in CANDIDATES}
+    times[(64, 0)] = 2.8721
+    times[d] = 2.8722                      # equal within run-to-run noise
+    assert pick(times, d) == d
+    times[d] = 2.8721 * (1 + 2 * TIE)      # clearly slower
+    assert pick(times, d) == (64, 0)
+    assert pick({(128, 1): 1.0, (64, 0): 2.0}, d) == (128, 1)   # default not timed
