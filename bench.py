@@ -272,7 +272,7 @@ def serving_bench(ctx, w, dsc, gamma, L, log, n_requests=300, rates=(50.0, 80.0,
     16-512 views (log-uniform) of one class of 160x120 / 320x240 / 640x480:
     continuous batching (3 slots, same-scene merging, memory admission)
     against a plain queue (one slot, one request at a time), at Poisson rates
-    below and above the device's capacity (about 110 requests/s here)."""
+    below and above the device's capacity (about 150 requests/s here)."""
     import numpy as np
     import torch
     from paper_2605_30342_amd import scenes
