@@ -725,7 +725,7 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "avg_launch_ms": round(per_call[dom], 4)}
-    # the query blend's own fraction (the benchmark spec's target is stated on it)
+    # the query blend's own fraction (the query's roofline target is stated on it)
     # and the whole query's, with all its stages' time in the denominator
     uq_frac = query_valu(pairs_uq, stages_q, float(np.median(query_ms)))
     # HBM fractions of every stage and of projection + binning, per call
