@@ -203,6 +203,26 @@ def test_ragged_and_mixed_resolutions_in_one_call(ctx, tiny, tiny_ref):
     assert compare_gamma(bg, bo)[0] <= 1.0
 
 
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_scan_block_boundaries(ctx, tiny, n):
+    """Scenes whose (Gaussian, view subset) entries fill the scans' 4096-value
+    blocks exactly (1024 and 2048 Gaussians: 4096 and 8192 entries), so that
+    the total lands in the first slot of a block of its own: build and query
+    against the oracle."""
+    say(f"case: scan block boundary, {n} Gaussians")
+    sc = scenes.tiny_scene(n, seed=90 + n)
+    prm = oracle_params()
+    b = oracle.vf_build(sc, tiny.train, 2, prm)
+    g = gpu_build(ctx, _dsc(sc), tiny.train, 2)
+    assert compare_gamma(g, b)[0] <= 1.0
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, 2, tiny.train.n, tiny.cand, prm)
+    s, mp, _ = gpu_query(ctx, _dsc(sc), g32, 2, tiny.train.n, tiny.cand)
+    worst, flagged = compare_maps(mp, q)
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
+    _check_scores(s, q, mp)
+
+
 def _extreme_views():
     """Candidates at the largest image sizes the ABI accepts: 16384 x 16 and
     16 x 16384 pixels (1024 tiles along one axis), looking at the tiny scene."""
