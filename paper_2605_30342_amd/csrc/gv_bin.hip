@@ -340,7 +340,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 int ntv, float kappa_log2e, const float *__restrict__ cvar, int Lc,
                                                 float c3, float *__restrict__ rcc, float *__restrict__ rz,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
-                                                Bin *__restrict__ bin, uint32_t *__restrict__ ntr) {
+                                                Bin *__restrict__ bin, uint32_t *__restrict__ ntr, int pack) {
     constexpr int K = (L + 1) * (L + 1);
     __shared__ uint32_t srel[WAVES][64];   // first record of each entry (relative)
     __shared__ uint8_t cl[WAVES][64];      // lanes of the entries that own records, in order
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 Bin b = {};
                 if (!Pj.ok) {
                     bin[r] = b;
-                    if (ntr) ntr[r] = 0u;
+                    if (ntr) ntr[r] = pack ? r : 0u;
                     key[r] = DEAD_KEY;
                     rec[r] = Rec{0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
@@ -534,7 +534,10 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                     b.l21 = R.l21;
                     b.l22 = R.l22;
                     bin[r] = b;
-                    if (ntr) ntr[r] = bin_ntiles(b.dims);
+                    if (ntr) {
+                        const uint32_t nt = bin_ntiles(b.dims);
+                        ntr[r] = pack ? r | (min(nt, PACK_SAT) << PACK_SHIFT) : nt;
+                    }
                 }
             }
             started += (uint32_t)__popcll(P);
@@ -795,7 +798,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) 
 // sorted keys are not needed).
 // With drop (see k_radix_hist) the kept pairs are written compacted and their
 // total goes to *n_kept (by one thread of block 0), the count the following
-// passes take.  With gdst set, gdst[o] = gsrc[value] is also written for
+// passes take.  With gdst and gbin set, gdst[o] is the tile count a packed
+// value carries (see PACK_SHIFT; a saturated one from gbin[record]); with
+// gdst alone, gdst[o] = gsrc[value]; either is also written for
 // every output position o (a per-value word gathered into sorted order).
 __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -803,7 +808,8 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ hist,
                                                       const uint32_t *__restrict__ dtot,
                                                       uint32_t *__restrict__ n_kept,
-                                                      const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst) {
+                                                      const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst,
+                                                      const Bin *__restrict__ gbin) {
     __shared__ uint32_t run[RADIX];          // output position of this block's next pair of each digit
     __shared__ uint32_t wcnt[WAVES][RADIX];  // wave counts, then wave offsets inside the digit
     __shared__ uint32_t lbase[RADIX];        // first slot of each digit in the staged tile
@@ -893,7 +899,13 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
                 const uint32_t o = goff[(key >> shift) & mask] + j;
                 if (kout) kout[o] = key;
                 vout[o] = val;
-                gdst[o] = gsrc[val];
+                if (gbin) {   // packed values: the count they carry, or the binning line's
+                    uint32_t c = val >> PACK_SHIFT;
+                    if (c == PACK_SAT) c = bin_ntiles(gbin[val & PACK_RMASK].dims);
+                    gdst[o] = c;
+                } else {
+                    gdst[o] = gsrc[val];
+                }
             }
         } else if (!kout) {
             for (uint32_t j = t; j < cnt; j += WG) vout[goff[(sk[j] >> shift) & mask] + j] = sv[j];
@@ -1004,10 +1016,12 @@ __device__ __forceinline__ void emit_chunk(EmitLds &S, int w, int lane, uint32_t
 // Offsets from a scan done before (ioff[i]: first output of depth-ordered
 // record i; the scan has set the instance totals and the overflow flag, and
 // nothing is emitted on overflow).  Waves take chunks of 64 records in turn.
+// rmask: the record index bits of the values (PACK_RMASK for packed values).
 __global__ __launch_bounds__(WG) void k_emit_scanned(const uint32_t *__restrict__ sval, const Bin *__restrict__ bin,
                                                      const uint32_t *__restrict__ ioff,
                                                      const Status *__restrict__ st, float qcut, uint32_t dead_tile,
-                                                     uint32_t *__restrict__ ikey, uint32_t *__restrict__ ival) {
+                                                     uint32_t *__restrict__ ikey, uint32_t *__restrict__ ival,
+                                                     uint32_t rmask) {
     __shared__ EmitLds S;
     if (st->overflow) return;
     const uint64_t n = st->R_eff;
@@ -1019,7 +1033,7 @@ __global__ __launch_bounds__(WG) void k_emit_scanned(const uint32_t *__restrict_
         uint32_t r = 0, o = 0, nt = 0;
         Bin B = {};
         if (i < n) {
-            r = sval[i];
+            r = sval[i] & rmask;
             B = bin[r];
             o = ioff[i];
             nt = bin_ntiles(B.dims);
@@ -1276,14 +1290,15 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
 template <typename TG, typename TGam, int MODE>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
-                               const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
+                               const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, int pack,
+                               hipStream_t s) {
     const uint64_t chunks = ((uint64_t)a.n * PROJ_SPLIT + 63) / 64;
     const unsigned grid = (unsigned)std::min<uint64_t>((chunks + WAVES - 1) / WAVES, 4096);
     const int mw = mask_words(nv);
     const TGam *gm = (const TGam *)q.gamma;
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
-        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr
+        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr, pack
     const bool extra = q.color_var || q.rz;
 #define GV_PROJECT_LAUNCH(LL) \
     do { \
@@ -1309,32 +1324,33 @@ static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, 
 template <typename TG>
 static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                  const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
-                                 const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
+                                 const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, int pack,
+                                 hipStream_t s) {
     if (!q) {
         const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr, nullptr};
-        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, ntr, s);
+        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, ntr, pack, s);
         return;
     }
     if (q->mode == 2) {
-        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s);
+        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s);
         return;
     }
     switch (q->gamma_dtype) {
-    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
-    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
-    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, s); break;
+    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
+    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
+    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
     }
 }
 
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s) {
+                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, hipStream_t s) {
     if (a.n == 0) return;
     const int L = q ? q->sh_degree : 0;
     switch (a.dtype) {
-    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
-    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
-    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, s); break;
+    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
+    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
+    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
     }
 }
 
@@ -1354,7 +1370,8 @@ size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / S
 // the indices 0..n-1 and v0 is only used as a buffer.
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
-                      uint64_t n_cap, const uint32_t *gather_src, uint32_t *gather_dst, bool keys_out) {
+                      uint64_t n_cap, const uint32_t *gather_src, uint32_t *gather_dst, bool keys_out,
+                      const Bin *gather_bin) {
     int cur = 0;
     // about one tile of pairs per block at the capacity: fewer, fuller blocks
     // than a fixed grid when the sort is short
@@ -1375,7 +1392,8 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(WG), 0, s, ki, vin, last && !keys_out ? nullptr : ko, vo,
                            n_dev, shift, nb, dk,
-                           hist, dtot, kept, last ? gather_src : nullptr, last ? gather_dst : nullptr);
+                           hist, dtot, kept, last ? gather_src : nullptr, last ? gather_dst : nullptr,
+                           last ? gather_bin : nullptr);
         if (kept) n_dev = kept;
         cur ^= 1;
         vin = cur ? v1 : v0;
@@ -1388,8 +1406,9 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
 size_t emit_post_words(uint64_t rcap) { return (size_t)((rcap + EMIT_RPB - 1) / EMIT_RPB) + 1; }
 
 void launch_emit_scanned(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
-                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit_scanned, dim3(8192), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival);
+                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, uint32_t rmask, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit_scanned, dim3(8192), dim3(WG), 0, s, sval, bin, ioff, st, qcut, dead_tile, ikey, ival,
+                       rmask);
 }
 
 void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, Status *st, uint64_t rcap,

@@ -152,7 +152,7 @@ Layout make_layout(const gv_workspace &p) {
     if (lookback) {
         L.post = take(emit_post_words(R) * 8);
     } else {
-        L.ntr = take(R * 4);
+        L.ntr = take((R < ((uint64_t)1 << PACK_SHIFT) ? 0 : R) * 4);   // unpacked tile counts (large plans)
         L.icnt = take(R * 4);
         L.ioff = take((R + 1) * 4);
     }
@@ -437,7 +437,11 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     uint32_t *k1 = at<uint32_t>(ws, L.key1), *v1 = at<uint32_t>(ws, L.val1);
     const bool lookback = emit_lookback(p);
     unsigned long long *post = lookback ? at<unsigned long long>(ws, L.post) : nullptr;
-    uint32_t *ntr = lookback ? nullptr : at<uint32_t>(ws, L.ntr);
+    // scanned emission: the projection packs each record's tile count into its
+    // depth-sort value (or, for plans of 2^PACK_SHIFT records and more, writes
+    // the counts apart and the last depth pass gathers them)
+    const bool packed = !lookback && (uint64_t)p.max_records < ((uint64_t)1 << PACK_SHIFT);
+    uint32_t *ntr = lookback || packed ? nullptr : at<uint32_t>(ws, L.ntr);
     uint32_t *icnt = lookback ? nullptr : at<uint32_t>(ws, L.icnt), *ioff = lookback ? nullptr : at<uint32_t>(ws, L.ioff);
     uint32_t *ik0 = at<uint32_t>(ws, L.ikey0), *iv0 = at<uint32_t>(ws, L.ival0);
     uint32_t *ik1 = at<uint32_t>(ws, L.ikey1), *iv1 = at<uint32_t>(ws, L.ival1);
@@ -455,16 +459,17 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     }
     {
         StageScope sc(ctx, ST_PROJECT, s);
-        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, ntr, s);
+        launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, packed ? v0 : ntr, packed,
+                       s);
     }
     int dres;
     {
         StageScope sc(ctx, ST_SORT_DEPTH, s);
-        // scanned emission: the last pass also gathers each record's tile
-        // count into depth order
-        // (only the depth order of the records is used, not their sorted keys)
-        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, true, hist, dtot, s, DEAD_KEY, nullptr, R, ntr,
-                                 icnt, false);
+        // scanned emission: the last pass also writes each record's tile count
+        // in depth order (the count its packed value carries, or gathered);
+        // only the depth order of the records is used, not their sorted keys
+        dres = launch_radix_sort(k0, v0, k1, v1, &st->R_eff, 32, !packed, hist, dtot, s, DEAD_KEY, nullptr, R, ntr,
+                                 icnt, false, packed ? bin : nullptr);
     }
     const uint32_t *sval = dres ? v1 : v0;
     {
@@ -474,7 +479,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
             launch_emit(sval, bin, post, st, R, M, qc, (uint32_t)tiles, ik0, iv0, s);
         } else {
             launch_scan(icnt, ioff, &st->R_eff, 0, R, blk, &st->M_total, &st->M_eff, M, &st->overflow, 2u, s);
-            launch_emit_scanned(sval, bin, ioff, st, qc, (uint32_t)tiles, ik0, iv0, s);
+            launch_emit_scanned(sval, bin, ioff, st, qc, (uint32_t)tiles, ik0, iv0, packed ? PACK_RMASK : 0xFFFFFFFFu, s);
         }
     }
     int tres;

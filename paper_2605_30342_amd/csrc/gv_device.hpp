@@ -10,6 +10,13 @@ namespace gv {
 // Raster tile: 16x16 pixels, one 256-thread workgroup (4 waves of 64), one
 // pixel per lane.  Each wave covers an 8x8 quadrant of the tile.
 constexpr int TILE = 16;
+// Depth-sort values of the scanned emission: record index | min(tile count,
+// PACK_SAT) << PACK_SHIFT (records below 2^PACK_SHIFT), so that the sort
+// carries each record's tile count into depth order; a saturated count is
+// read from the record's binning line.
+constexpr int PACK_SHIFT = 24;
+constexpr uint32_t PACK_SAT = 255u;
+constexpr uint32_t PACK_RMASK = (1u << PACK_SHIFT) - 1u;
 constexpr int TILE_SHIFT = 4;
 constexpr int WG = 256;
 constexpr int WAVES = WG / 64;

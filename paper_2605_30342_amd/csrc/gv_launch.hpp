@@ -65,7 +65,7 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, uint32_t *ntr, hipStream_t s);
+                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, hipStream_t s);
 
 size_t scan_blk_count(uint64_t n_cap);
 void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
@@ -76,13 +76,15 @@ void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint6
 // equals it are removed by the first pass, which writes the kept count to
 // *n_kept for the rest of the sort.  n_cap: the most pairs *n_dev can hold
 // (sizes the grid).  gather_dst (optional): the last pass also writes
-// gather_dst[i] = gather_src[sorted value i] for every output position i.
+// gather_dst[i] = gather_src[sorted value i] for every output position i,
+// or, with gather_bin, the tile count the sorted value carries (PACK_SHIFT;
+// a saturated count from gather_bin[record]).
 // keys_out false: the sorted keys are not written (only the values are
 // sorted into the result buffer).
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev, int bits,
                       bool iota, uint32_t *hist, uint32_t *dtot, hipStream_t s, uint32_t drop, uint32_t *n_kept,
                       uint64_t n_cap, const uint32_t *gather_src = nullptr, uint32_t *gather_dst = nullptr,
-                      bool keys_out = true);
+                      bool keys_out = true, const Bin *gather_bin = nullptr);
 void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hipStream_t s);
 // Density control (Alg. 5): box corner and sides in FP64, particle scale.
 struct VirtArgs {
@@ -105,7 +107,7 @@ void launch_view_vis(const GaussArgs &a, const uint32_t *offs, const uint32_t *v
 // Instances of the first st->R_eff depth-ordered records (sval) at the output
 // offsets ioff of a scan done before (nothing on overflow).
 void launch_emit_scanned(const uint32_t *sval, const Bin *bin, const uint32_t *ioff, const Status *st, float qcut,
-                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, hipStream_t s);
+                         uint32_t dead_tile, uint32_t *ikey, uint32_t *ival, uint32_t rmask, hipStream_t s);
 // Post words the instance emission needs for rcap records (its look-back).
 size_t emit_post_words(uint64_t rcap);
 // Instances of the first st->R_eff depth-ordered records (sval) into
