@@ -136,7 +136,7 @@ typedef struct {
     int32_t kind;               /* 0 build, 1 query, 2 density control */
     int32_t sh_degree;
     int32_t emit_mode;          /* how instances find their output offsets: 1 a scan of
-                                   the records' tile counts, gathered into depth order by
+                                   the records' tile counts, carried into depth order by
                                    the depth sort; 2 a single-pass scan with decoupled
                                    look-back inside the emission (one read of each
                                    record's binning line); 0 chosen from the sizes (2 when

@@ -110,10 +110,12 @@ struct Layout {
     size_t total;
 };
 
-// Which emission a plan runs.  The scanned one gathers each depth-ordered
-// record's tile count in the last depth-sort pass and scans the counts before
-// it emits: two random 32-byte reads per record, cheap while the records'
-// binning lines stay in the 256 MB last-level cache, and its waves take
+// Which emission a plan runs.  The scanned one has the depth sort carry each
+// record's tile count into depth order (packed into the record's sort value;
+// gathered by the last pass for plans of 2^PACK_SHIFT records and more) and
+// scans the counts before it emits: one random 32-byte read per record,
+// cheap while the records' binning lines stay in the 256 MB last-level
+// cache, and its waves take
 // chunks of records in turn, which balances records with many tiles.  The
 // look-back one reads each binning line once and finds its offsets itself:
 // it pays off where the binning lines (32 bytes per record) far exceed that
