@@ -47,12 +47,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without comments and blank space runs (string and
+    character literals kept), so that comment edits leave the hash alone."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            i = src.find("\n", i)
+            i = n if i < 0 else i
+        elif src.startswith("/*", i):
+            i = src.find("*/", i + 2)
+            i = n if i < 0 else i + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the library's sources, comments and spacing aside."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_30342_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -579,7 +604,7 @@ def main():
                          "rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, separate passes) scaled so that "
                          "the run's device copy of --calib-copy-mib MiB reads and writes that many bytes; "
                          "trace_ms from the kernel trace of the same command.  Valid for the kernel sources "
-                         "whose hash is given; bench.py reports null otherwise.",
+                         "whose hash (comments and spacing aside) is given; bench.py reports null otherwise.",
                "command": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
                           "-d DIR/kt_<w> -o kt -- python3 bench.py --workload <w> --steps 3 --warmup 1 "
                           "--profile-only --no-autotune; then for C in FETCH_SIZE WRITE_SIZE: "

@@ -30,7 +30,8 @@ def test_source_hash_covers_every_kernel_source(tmp_path):
     h = b.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
     assert b.kernel_source_hash() == h   # deterministic
-    # a copy of the sources with one byte changed hashes differently
+    # a copy of the sources: a comment or spacing edit keeps the hash, a code
+    # edit changes it
     csrc = os.path.join(ROOT, "paper_2605_30342_amd", "csrc")
     dst = tmp_path / "paper_2605_30342_amd" / "csrc"
     dst.mkdir(parents=True)
@@ -40,8 +41,17 @@ def test_source_hash_covers_every_kernel_source(tmp_path):
     b.ROOT = str(tmp_path)
     assert b.kernel_source_hash() == h
     last = dst / names[-1]
-    last.write_bytes(last.read_bytes() + b" ")
+    orig = last.read_bytes()
+    last.write_bytes(orig + b"\n// a comment\n/* another */  \n")
+    assert b.kernel_source_hash() == h
+    last.write_bytes(orig + b"\nstatic int extra_symbol;\n")
     assert b.kernel_source_hash() != h
+
+
+def test_strip_comments_keeps_literals():
+    b = _bench_module()
+    src = 'int a = 1; // c\n/* x */ const char *s = "a//b /*c*/"; char q = \'"\'; int b; /* y\n z */ x'
+    assert b.strip_comments(src) == 'int a = 1; const char *s = "a//b /*c*/"; char q = \'"\'; int b; x'
 
 
 def test_traffic_is_reported_only_for_matching_sources(tmp_path):
