@@ -479,6 +479,69 @@ def test_lookback_emission_matches_the_scanned_one_and_the_oracle(ctx, case):
     assert torch.all(torch.isnan(s_))
 
 
+def test_scanned_emission_with_unpacked_tile_counts(ctx, tiny, tiny_ref):
+    """Plans of 2^24 records and more keep the tile counts apart from the
+    depth-sort values (the last depth pass gathers them): the same query and
+    build with the record capacity raised to 2^24 give the results of the
+    packed plan, bit-identical maps and gamma to FP32 rounding."""
+    say("case: scanned emission with the record capacity at 2^24 (tile counts gathered)")
+    import ctypes
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    gd = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    uprm = _lib.default_uq_params()
+    vprm = _lib.default_vf_params(sh_degree=2)
+    out = []
+    for big in (False, True):
+        wsq = ctx.query_workspace(dsc, tiny.cand, uprm, 2)
+        wsb = ctx.build_workspace(dsc, tiny.train, vprm)
+        if big:
+            for ws in (wsq, wsb):
+                ws.plan.max_records = 1 << 24
+                ws.plan.emit_mode = 1
+                ws.plan.bytes = ctx.L.gv_workspace_bytes(ctypes.byref(ws.plan))
+            wsq, wsb = ctx.alloc_workspace(wsq.plan), ctx.alloc_workspace(wsb.plan)
+        s_, m_ = ctx.vf_query_views(dsc, gd, 2, tiny.train.n, tiny.cand, uprm, wsq, want_maps=True)
+        gam = ctx.vf_build(dsc, tiny.train, 2, vprm, wsb)
+        torch.cuda.synchronize()
+        assert ctx.check_workspace(wsq)[0] == 0 and ctx.check_workspace(wsb)[0] == 0
+        out.append((s_.cpu().numpy(), m_.cpu().numpy(), gam.cpu().numpy().T.astype(np.float64)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    scale = np.abs(out[0][2]).max(1, keepdims=True) + 1e-30
+    assert np.all(np.abs(out[1][2] - out[0][2]) <= 1e-5 * scale)
+
+
+def test_records_with_hundreds_of_tiles(ctx):
+    """The stress scene seen at 640x480: its large Gaussians cover several
+    hundred of the 1200 tiles, past the 255 that a packed depth-sort value
+    can carry (their counts are read from the binning lines); build and
+    query against the oracle."""
+    say("case: records covering 255 tiles and more (stress scene at 640x480)")
+    tr = scenes.sphere_cameras(2, 7201, width=640, height=480)
+    cd = scenes.sphere_cameras(2, 7202, width=640, height=480)
+    sc = stress_scene(tr)
+    prm = oracle_params()
+    # the test is only meaningful if some record spans at least 255 tiles
+    p = oracle.project_view(sc, cd, 0, prm)
+    ok = p["ok"] > 0
+    rx, ry = np.sqrt(9.0 * p["sxx"][ok]), np.sqrt(9.0 * p["syy"][ok])
+    tx = np.minimum(np.floor((p["ux"][ok] + rx) / 16), 39) - np.maximum(np.floor((p["ux"][ok] - rx) / 16), 0) + 1
+    ty = np.minimum(np.floor((p["uy"][ok] + ry) / 16), 29) - np.maximum(np.floor((p["uy"][ok] - ry) / 16), 0) + 1
+    assert (np.clip(tx, 0, None) * np.clip(ty, 0, None)).max() >= 255
+    b = oracle.vf_build(sc, tr, 2, prm)
+    g = gpu_build(ctx, _dsc(sc), tr, 2)
+    worst_g, _ = compare_gamma(g, b)
+    g32 = b["gamma"].astype(np.float32).astype(np.float64)
+    q = oracle.vf_query(sc, g32, 2, tr.n, cd, prm)
+    s_, mp, _ = gpu_query(ctx, _dsc(sc), g32, 2, tr.n, cd)
+    worst, flagged = compare_maps(mp, q)
+    say(f"  gamma worst {worst_g:.3f}; map worst {worst:.3f}, flagged {flagged:.5f}")
+    assert worst_g <= 1.0 and worst <= 1.0 and flagged <= flag_bar(q["stats"])
+    _check_scores(s_, q, mp)
+
+
 def test_room_subset_build_and_query(ctx, room_small):
     say("case: room scene 20k Gaussians, L=3, 3 training views 800x800, 4 candidates 400x400")
     w = room_small
