@@ -25,13 +25,6 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t value)
         p[i] = value;
 }
 
-__global__ void k_fill_dev_u32(uint32_t *__restrict__ p, const uint32_t *__restrict__ n_dev, uint32_t mult,
-                               uint32_t value) {
-    const uint64_t n = (uint64_t)(*n_dev) * mult;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = value;
-}
-
 // ---------------------------------------------------------------- Gaussian loads
 
 template <typename TG>
@@ -340,7 +333,8 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                                                 int ntv, float kappa_log2e, const float *__restrict__ cvar, int Lc,
                                                 float c3, float *__restrict__ rcc, float *__restrict__ rz,
                                                 Rec *__restrict__ rec, uint32_t *__restrict__ key,
-                                                Bin *__restrict__ bin, uint32_t *__restrict__ ntr, int pack) {
+                                                Bin *__restrict__ bin, uint32_t *__restrict__ ntr, int pack,
+                                                uint32_t *__restrict__ zr0, uint32_t *__restrict__ zr1) {
     constexpr int K = (L + 1) * (L + 1);
     __shared__ uint32_t srel[WAVES][64];   // first record of each entry (relative)
     __shared__ uint8_t cl[WAVES][64];      // lanes of the entries that own records, in order
@@ -432,6 +426,11 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
                 for (int kk = 0; kk < 6; ++kk) S[kk] = sgS[w][kk][q];
                 Proj Pj;
                 project_exact(m, S, V, znear, lowpass, cut, Pj);
+                if constexpr (MODE == 0) {
+                    // the build's per-record accumulators start at zero
+                    if (zr0) zr0[r] = 0u;
+                    if (zr1) zr1[r] = 0u;
+                }
                 Bin b = {};
                 if (!Pj.ok) {
                     bin[r] = b;
@@ -555,7 +554,10 @@ __global__ __launch_bounds__(WG) void k_project(GaussIn<TG> G, const ViewDev *__
 // block sums, a single-block scan of the block sums (64-bit totals), and the
 // per-block scan.  out[n] receives the total (wrapped to 32 bits); the
 // 64-bit total goes to *total and min(total, tcap) to *eff; a total above
-// tcap sets `flag_bit` in *overflow.
+// tcap sets `flag_bit` in *overflow.  Scans of at most SCAN_OWN_BLOCKS blocks
+// (8M values) skip the middle phase: each block of the last one adds up the
+// sums of the blocks before it (at most 16 KiB of reads), one launch fewer.
+constexpr int SCAN_OWN_BLOCKS = 2048;
 
 __device__ __forceinline__ uint64_t scan_n(const uint32_t *n_dev, uint64_t n_host) {
     return n_dev ? (uint64_t)(*n_dev) : n_host;
@@ -623,15 +625,34 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(unsigned long long *__rest
 // consecutive ones both spread over the banks.
 __device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
 
+// OWN: the block adds up the sums of the blocks before it itself (a scan of
+// at most SCAN_OWN_BLOCKS blocks, so that k_scan_blocks is not launched), and
+// the block that holds out[n] writes the totals and the overflow flag as
+// k_scan_blocks does; otherwise blk[b] already holds the prefix of block b.
+template <bool OWN>
 __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                   const uint32_t *n_dev, uint64_t n_host,
-                                                  const unsigned long long *__restrict__ blk) {
+                                                  const unsigned long long *__restrict__ blk,
+                                                  unsigned long long *total, uint32_t *eff, uint64_t tcap,
+                                                  uint32_t *overflow, uint32_t flag_bit) {
     const uint64_t n = scan_n(n_dev, n_host);
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
     if (base > n) return;
     __shared__ uint32_t tile[SCAN_BLOCK + SCAN_BLOCK / 32];
     __shared__ unsigned long long wsum[WAVES];
+    __shared__ unsigned long long wpre[WAVES];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned long long pre = 0;
+    if constexpr (OWN) {
+#pragma unroll
+        for (int k = 0; k < SCAN_OWN_BLOCKS / WG; ++k) {
+            const uint32_t b = (uint32_t)(k * WG + t);
+            pre += b < blockIdx.x ? blk[b] : 0ull;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
+        if (lane == 0) wpre[w] = pre;
+    }
     // the block's elements, read with consecutive lanes on consecutive
     // elements (zero past n)
 #pragma unroll
@@ -658,13 +679,29 @@ __global__ __launch_bounds__(WG) void k_scan_down(const uint32_t *__restrict__ i
     }
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    unsigned long long run = blk[blockIdx.x] + inc - s;
+    if constexpr (OWN) {
+        pre = 0;
+#pragma unroll
+        for (int q = 0; q < WAVES; ++q) pre += wpre[q];
+    } else {
+        pre = blk[blockIdx.x];
+    }
+    unsigned long long run = pre + inc - s;
 #pragma unroll
     for (int q = 0; q < WAVES; ++q) run += q < w ? wsum[q] : 0ull;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         tile[scan_slot(t * SCAN_ITEMS + k)] = (uint32_t)run;
         run += v[k];
+    }
+    if constexpr (OWN) {
+        // the last thread of the block holding out[n] ends at the total
+        // (elements past n are zero)
+        if (t == WG - 1 && n < base + SCAN_BLOCK) {
+            if (total) *total = run;
+            if (eff) *eff = (uint32_t)(run < tcap ? run : tcap);
+            if (run > tcap && overflow) atomicOr(overflow, flag_bit);
+        }
     }
     __syncthreads();
     // out[e] for e <= n (out[n]: the total), consecutive lanes again
@@ -746,37 +783,6 @@ __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t *__restrict__ 
     hist[(size_t)t * gridDim.x + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
-// One block per digit: exclusive scan of that digit's nblk counts (one per
-// block of the histogram pass, nblk <= RADIX_BLOCKS).
-__global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t *__restrict__ dtot,
-                                                   int nblk) {
-    constexpr int PER = RADIX_BLOCKS / WG;
-    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
-    uint32_t v[PER];
-    uint32_t s = 0;
-    for (int k = 0; k < PER; ++k) {
-        const int i = (int)threadIdx.x * PER + k;
-        v[k] = i < nblk ? row[i] : 0u;
-        s += v[k];
-    }
-    __shared__ uint32_t buf[WG];
-    buf[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < WG; off <<= 1) {
-        const uint32_t y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
-        __syncthreads();
-        buf[threadIdx.x] += y;
-        __syncthreads();
-    }
-    uint32_t run = buf[threadIdx.x] - s;
-    for (int k = 0; k < PER; ++k) {
-        const int i = (int)threadIdx.x * PER + k;
-        if (i < nblk) row[i] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == WG - 1) dtot[blockIdx.x] = buf[WG - 1];
-}
-
 // Exclusive prefix sum over the block's 256 threads (one value each).
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -792,6 +798,47 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wtot) 
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) base += ww < w ? wtot[ww] : 0u;
     return base + inc - x;
+}
+
+// One block per digit: exclusive scan of that digit's nblk counts (one per
+// block of the histogram pass, nblk <= RADIX_BLOCKS), read and written with
+// consecutive lanes on consecutive counts; in LDS each thread scans
+// RADIX_BLOCKS / WG consecutive counts after one block-wide scan of the
+// threads' sums.  dtot[digit] receives the digit's total.
+__global__ __launch_bounds__(WG) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t *__restrict__ dtot,
+                                                   int nblk) {
+    constexpr int PER = RADIX_BLOCKS / WG;
+    __shared__ uint32_t tile[RADIX_BLOCKS + RADIX_BLOCKS / 32];
+    __shared__ uint32_t wtot[WAVES];
+    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * WG + t;
+        tile[scan_slot(i)] = i < nblk ? row[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[PER], s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = tile[scan_slot(t * PER + k)];
+        s += v[k];
+    }
+    // a thread rewrites only its own slots, which no other thread reads
+    // before the barrier below
+    uint32_t run = block_excl_scan(s, wtot);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        tile[scan_slot(t * PER + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * WG + t;
+        if (i < nblk) row[i] = tile[scan_slot(i)];
+    }
+    if (t == WG - 1) dtot[blockIdx.x] = run;
 }
 
 // kout NULL: only the values are written (the last pass of a sort whose
@@ -1236,10 +1283,6 @@ void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 4096)), dim3(WG), 0, s, p, n, value);
 }
 
-void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_dev_u32, dim3(2048), dim3(WG), 0, s, p, n_dev, mult, value);
-}
-
 template <typename TG>
 static GaussIn<TG> gin(const GaussArgs &a) {
     GaussIn<TG> G;
@@ -1291,14 +1334,14 @@ template <typename TG, typename TGam, int MODE>
 static void project_dispatch_L(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
                                const QueryArgs &q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, int pack,
-                               hipStream_t s) {
+                               uint32_t *zr0, uint32_t *zr1, hipStream_t s) {
     const uint64_t chunks = ((uint64_t)a.n * PROJ_SPLIT + 63) / 64;
     const unsigned grid = (unsigned)std::min<uint64_t>((chunks + WAVES - 1) / WAVES, 4096);
     const int mw = mask_words(nv);
     const TGam *gm = (const TGam *)q.gamma;
     const float kl = (float)(q.kappa * 1.4426950408889634);
 #define GV_PROJECT_ARGS gin<TG>(a), views, nv, p.znear, p.lowpass, p.cut, offs, vmask, mw, st, rcap, gm, q.n_train, \
-        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr, pack
+        q.view_vis, q.train_centres, q.n_train_views, kl, q.color_var, q.color_sh_degree, q.c3, q.rcc, q.rz, rec, key, bin, ntr, pack, zr0, zr1
     const bool extra = q.color_var || q.rz;
 #define GV_PROJECT_LAUNCH(LL) \
     do { \
@@ -1325,32 +1368,33 @@ template <typename TG>
 static void project_dispatch_gam(int L, const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p,
                                  const uint32_t *offs, const uint32_t *vmask, const Status *st, uint32_t rcap,
                                  const QueryArgs *q, Rec *rec, uint32_t *key, Bin *bin, uint32_t *ntr, int pack,
-                                 hipStream_t s) {
+                                 uint32_t *zr0, uint32_t *zr1, hipStream_t s) {
     if (!q) {
         const QueryArgs none = {0, 0, nullptr, 0, 0.f, nullptr, nullptr, 0, 0.f, nullptr, 0, 0.f, nullptr, nullptr};
-        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, ntr, pack, s);
+        project_dispatch_L<TG, float, 0>(0, a, views, nv, p, offs, vmask, st, rcap, none, rec, key, bin, ntr, pack, zr0, zr1, s);
         return;
     }
     if (q->mode == 2) {
-        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s);
+        project_dispatch_L<TG, float, 2>(0, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, zr0, zr1, s);
         return;
     }
     switch (q->gamma_dtype) {
-    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
-    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
-    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, s); break;
+    case 0: project_dispatch_L<TG, float, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
+    case 1: project_dispatch_L<TG, _Float16, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
+    default: project_dispatch_L<TG, uint16_t, 1>(L, a, views, nv, p, offs, vmask, st, rcap, *q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
     }
 }
 
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, hipStream_t s) {
+                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, uint32_t *zr0, uint32_t *zr1,
+                    hipStream_t s) {
     if (a.n == 0) return;
     const int L = q ? q->sh_degree : 0;
     switch (a.dtype) {
-    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
-    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
-    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, s); break;
+    case 0: project_dispatch_gam<float>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
+    case 1: project_dispatch_gam<_Float16>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
+    default: project_dispatch_gam<uint16_t>(L, a, views, nv, p, offs, vmask, st, rcap, q, rec, key, bin, ntr, pack, zr0, zr1, s); break;
     }
 }
 
@@ -1359,8 +1403,15 @@ void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint6
                  uint32_t *overflow, uint32_t flag_bit, hipStream_t s) {
     const unsigned nb = (unsigned)((n_cap + SCAN_BLOCK) / SCAN_BLOCK);   // covers out[n] too
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(WG), 0, s, in, n_dev, n_host, blk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, n_dev, n_host, total, eff, tcap, overflow, flag_bit);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(WG), 0, s, in, out, n_dev, n_host, blk);
+    if (nb <= SCAN_OWN_BLOCKS) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(nb), dim3(WG), 0, s, in, out, n_dev, n_host, blk, total, eff, tcap,
+                           overflow, flag_bit);
+    } else {
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, n_dev, n_host, total, eff, tcap, overflow,
+                           flag_bit);
+        hipLaunchKernelGGL(k_scan_down<false>, dim3(nb), dim3(WG), 0, s, in, out, n_dev, n_host, blk, nullptr,
+                           nullptr, 0, nullptr, 0u);
+    }
 }
 
 size_t scan_blk_count(uint64_t n_cap) { return (size_t)((n_cap + SCAN_BLOCK) / SCAN_BLOCK) + 1; }

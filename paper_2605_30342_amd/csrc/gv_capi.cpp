@@ -426,9 +426,11 @@ struct Binned {
     const uint32_t *torder; // tiles by decreasing list length (schedule 2), else NULL
 };
 
+// zero_a, zero_b (build): per-record words that the projection sets to zero
+// for every record slot it writes.
 static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layout &L, void *ws, const GaussArgs &a, int nv,
                              int64_t tiles, const GeomArgs &geo, const QueryArgs *query, hipStream_t s, Binned &out,
-                             int order) {
+                             int order, uint32_t *zero_a = nullptr, uint32_t *zero_b = nullptr) {
     Status *st = at<Status>(ws, L.status);
     ViewDev *views = at<ViewDev>(ws, L.views);
     uint32_t *cnt = at<uint32_t>(ws, L.cnt), *offs = at<uint32_t>(ws, L.offs), *vmask = at<uint32_t>(ws, L.vmask);
@@ -462,7 +464,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     {
         StageScope sc(ctx, ST_PROJECT, s);
         launch_project(a, views, nv, geo, offs, vmask, st, (uint32_t)R, query, rec, k0, bin, packed ? v0 : ntr, packed,
-                       s);
+                       zero_a, zero_b, s);
     }
     int dres;
     {
@@ -729,13 +731,12 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
         GV_TRY(plan_check(plan, workspace, 0, g->n, nv, tiles, pixels));
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
-        Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
-        launch_fill_dev_u32(reinterpret_cast<uint32_t *>(accT), &st->R_eff, 1, 0u, s);
-        launch_fill_dev_u32(accC, &st->R_eff, 1, 0u, s);
+        Binned bz;
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order,
+                           reinterpret_cast<uint32_t *>(accT), accC));
         {
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
@@ -800,13 +801,12 @@ static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const g
         GV_TRY(plan_check(plan, workspace, 0, g->n, nv, tiles, pixels));
         GV_HIP(hipMemcpyAsync(at<ViewDev>(workspace, Lay.views), views.data(), views.size() * sizeof(ViewDev),
                               hipMemcpyHostToDevice, s));
-        Binned bz;
-        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order));
         Status *st = at<Status>(workspace, Lay.status);
         float *accT = at<float>(workspace, Lay.accT);
         uint32_t *accC = at<uint32_t>(workspace, Lay.accC);
-        launch_fill_dev_u32(reinterpret_cast<uint32_t *>(accT), &st->R_eff, 1, 0u, s);
-        launch_fill_dev_u32(accC, &st->R_eff, 1, 0u, s);
+        Binned bz;
+        GV_TRY(run_binning(ctx, *plan, Lay, workspace, a, nv, tiles, geo, nullptr, s, bz, ctx->tuning.vis_order,
+                           reinterpret_cast<uint32_t *>(accT), accC));
         {
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),

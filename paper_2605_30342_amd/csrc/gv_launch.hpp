@@ -54,7 +54,6 @@ struct QueryArgs {
 };
 
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
-void launch_fill_dev_u32(uint32_t *p, const uint32_t *n_dev, uint32_t mult, uint32_t value, hipStream_t s);
 
 // Words of the per-(Gaussian, view subset) visibility mask for nv views.
 int mask_words(int nv);
@@ -65,7 +64,8 @@ void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const Geom
                     hipStream_t s);
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
-                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, hipStream_t s);
+                    uint32_t *key, Bin *bin, uint32_t *ntr, int pack, uint32_t *zr0, uint32_t *zr1,
+                    hipStream_t s);
 
 size_t scan_blk_count(uint64_t n_cap);
 void launch_scan(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_host, uint64_t n_cap,
