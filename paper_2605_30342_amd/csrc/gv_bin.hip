@@ -306,7 +306,8 @@ __device__ __forceinline__ float log_one_minus(float a) {
 // record is found from start marks and a ballot (as in the instance
 // emission), the view from the entry's visibility mask.  Lanes therefore stay
 // busy however few views of a Gaussian survive the cull.
-// MODE 0 (build) leaves the record's visibility at 0.  The query modes store
+// MODE 0 (build) leaves the record's visibility at 0 and zeroes zr0[r], zr1[r] (the
+// per-record accumulators of the blend, when given).  The query modes store
 // the Gaussian's visibility in direction d = camera -> Gaussian:
 // MODE 1, the visibility field (Alg. 4): V~ = sum_k gamma_k Y_k(d), clamped to
 //   [0, |P|], then V = 1 - (1 - V~/|P|)^|P| as 1 - exp(|P| log1p(-V~/|P|));

@@ -62,6 +62,7 @@ void launch_count(const GaussArgs &a, const ViewDev *views, int nv, const GeomAr
                   uint32_t *clr0, uint32_t n0, uint32_t *clr1, uint64_t n1, hipStream_t s);
 void launch_measure(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, unsigned long long *out,
                     hipStream_t s);
+// Build (q NULL): zr0[r] and zr1[r], if given, are set to zero for every record r written.
 void launch_project(const GaussArgs &a, const ViewDev *views, int nv, const GeomArgs &p, const uint32_t *offs,
                     const uint32_t *vmask, const Status *st, uint32_t rcap, const QueryArgs *q, Rec *rec,
                     uint32_t *key, Bin *bin, uint32_t *ntr, int pack, uint32_t *zr0, uint32_t *zr1,
