@@ -348,7 +348,10 @@ gv_status gv_workspace_check(gv_context *ctx, const gv_workspace *plan, const vo
  *            a contiguous run of tiles, so that neighbouring tiles, which
  *            share most of their records, share an L2 cache; 2: the tiles of
  *            all views by decreasing list length, sorted on the device before
- *            the blend, so that the longest tiles start first).
+ *            the blend, so that the longest tiles start first; 3 and 4:
+ *            persistent workgroups, about one per resident slot, take tiles
+ *            from a queue through an atomic counter until it is empty, in
+ *            tile order (3) or by decreasing list length (4)).
  * Results do not depend on the choice (VF CONST's float atomics may add in
  * another order).  Defaults: VF CONST 64 records, order 2; VF QUERY 256
  * records, order 0. */

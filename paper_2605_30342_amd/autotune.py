@@ -6,7 +6,9 @@ ones leave room for more resident workgroups per CU) and the tile order of
 the workgroups (0: workgroup b blends tile b; 1: each of the eight XCDs takes
 a contiguous run of tiles, so that neighbouring tiles share an L2; 2: the
 tiles of all views longest list first, a cost-ordered queue that the
-workgroup dispatcher drains in order).  Which
+workgroup dispatcher drains in order; 3 and 4: persistent workgroups, one
+round of resident ones, taking tiles from a queue through an atomic counter,
+in tile order or longest list first).  Which
 schedule wins depends on the workload (list lengths per tile, image sizes,
 Gaussian footprints, the number of views), so the tuner times every
 candidate on the caller's actual workload, checks that the outputs agree, and
@@ -25,7 +27,7 @@ from typing import Dict, Optional
 import torch
 
 BATCHES = (64, 128, 256)
-ORDERS = (0, 1, 2)
+ORDERS = (0, 1, 2, 3, 4)
 CANDIDATES = tuple(itertools.product(BATCHES, ORDERS))
 # the library's defaults (gv_tuning) and the margin a candidate must beat them by
 DEFAULT = {"build": (64, 2), "query": (256, 0)}

@@ -423,7 +423,7 @@ struct Binned {
     const uint32_t *sval;   // record ids in depth order
     const uint32_t *ival;   // record ids in (tile, depth) order
     const uint32_t *ikey;   // their instance keys (tile id, quadrant mask)
-    const uint32_t *torder; // tiles by decreasing list length (schedule 2), else NULL
+    const uint32_t *torder; // tiles by decreasing list length (schedules 2 and 4), else NULL
 };
 
 // zero_a, zero_b (build): per-record words that the projection sets to zero
@@ -499,7 +499,7 @@ static gv_status run_binning(gv_context *ctx, const gv_workspace &p, const Layou
     {
         StageScope sc(ctx, ST_RANGES, s);
         launch_ranges(skey, st, (uint32_t)tiles, ranges, s);
-        if (order == 2)
+        if (order == 2 || order == 4)
             out.torder = launch_tile_order(ranges, (uint32_t)tiles, at<uint32_t>(ws, L.torder),
                                            at<uint32_t>(ws, L.torder) + 4 * (uint64_t)tiles, hist, dtot, s);
     }
@@ -741,7 +741,7 @@ gv_status vf_build(gv_context *ctx, const gv_gaussians *g, const gv_camera *trai
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, st->tile_ticket, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -811,7 +811,7 @@ static gv_status view_visibility(gv_context *ctx, const gv_gaussians *g, const g
             StageScope sc(ctx, ST_RASTER_VIS, s);
             launch_raster_vis(at<ViewDev>(workspace, Lay.views), nv, (int)tiles, at<uint2>(workspace, Lay.ranges),
                               bz.ival, bz.ikey, at<Rec>(workspace, Lay.rec), prm->eps_T, qcut, accT, accC,
-                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, s);
+                              ctx->tuning.vis_batch, ctx->tuning.vis_order, bz.torder, st->tile_ticket, s);
         }
         {
             StageScope sc(ctx, ST_ACCUM, s);
@@ -1029,7 +1029,8 @@ static gv_status query_views(gv_context *ctx, const gv_gaussians *g, const Query
             Status *st = at<Status>(workspace, Lay.status);
             launch_raster_uq(at<ViewDev>(workspace, Lay.views), n_cand, (int)tiles, at<uint2>(workspace, Lay.ranges),
                              bz.ival, at<Rec>(workspace, Lay.rec), qa.rcc, qa.rz, u, tpart, mp, dmp,
-                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, ctx->tuning.uq_order, bz.torder, s);
+                             prm->count_pairs ? &st->measure[0] : nullptr, ctx->tuning.uq_batch, ctx->tuning.uq_order, bz.torder,
+                             st->tile_ticket, s);
         }
         launch_scores(at<ViewDev>(workspace, Lay.views), n_cand, tpart, at<Status>(workspace, Lay.status), scores, s);
         return GV_OK;
@@ -1278,8 +1279,8 @@ gv_status gv_set_tuning(gv_context *ctx, const gv_tuning *t) {
     if (!ctx || !t) return fail(GV_ERR_INVALID_ARG, "NULL argument");
     auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
     if (!ok(t->vis_batch) || !ok(t->uq_batch)) return fail(GV_ERR_INVALID_ARG, "batch sizes must be 64, 128 or 256");
-    if (t->vis_order < 0 || t->vis_order > 2 || t->uq_order < 0 || t->uq_order > 2)
-        return fail(GV_ERR_INVALID_ARG, "tile orders must be 0, 1 or 2");
+    if (t->vis_order < 0 || t->vis_order > 4 || t->uq_order < 0 || t->uq_order > 4)
+        return fail(GV_ERR_INVALID_ARG, "tile orders must be 0 to 4");
     ctx->tuning = *t;
     return GV_OK;
 }

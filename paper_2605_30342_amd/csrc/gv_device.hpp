@@ -101,6 +101,7 @@ struct Status {
     int32_t best;                 // argmax scratch
     uint32_t M_live;              // instances left after the tile sort drops dead ones
     uint32_t emit_ticket;         // next record block of the instance emission
+    uint32_t tile_ticket[8];      // per XCD: next queue position of a persistent blend
     unsigned long long measure[4];
 };
 

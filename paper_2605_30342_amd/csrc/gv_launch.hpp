@@ -119,11 +119,13 @@ void launch_emit(const uint32_t *sval, const Bin *bin, unsigned long long *lb, S
 void launch_ranges(const uint32_t *key, const Status *st, uint32_t dead_tile, uint2 *ranges, hipStream_t s);
 
 // order: tile schedule of the blend's workgroups (0 linear, 1 contiguous runs
-// of tiles per XCD, 2 the tiles listed by torder); batch: records staged per
-// LDS batch (64, 128, 256)
+// of tiles per XCD, 2 the tiles listed by torder; 3 and 4 persistent
+// workgroups taking tiles from a queue, in tile order or in torder's order,
+// through the eight ticket words, which must be zero at launch); batch:
+// records staged per LDS batch (64, 128, 256)
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                       int batch, int order, const uint32_t *torder, hipStream_t s);
+                       int batch, int order, const uint32_t *torder, uint32_t *ticket, hipStream_t s);
 // The tiles 0..T-1 by decreasing list length (ties by tile id), for the
 // blends' schedule 2: four T-word buffers and a count word of workspace;
 // returns the ordered ids (one of the buffers).
@@ -135,7 +137,7 @@ const uint32_t *launch_tile_order(const uint2 *ranges, uint32_t T, uint32_t *buf
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
-                      int order, const uint32_t *torder, hipStream_t s);
+                      int order, const uint32_t *torder, uint32_t *ticket, hipStream_t s);
 void launch_scores(const ViewDev *views, int nv, const float *tile_part, const Status *st, float *scores,
                    hipStream_t s);
 void launch_argmax(const float *scores, int n, int32_t *best, hipStream_t s);

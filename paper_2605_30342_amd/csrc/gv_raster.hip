@@ -151,12 +151,49 @@ __device__ __forceinline__ int pad_slot(int n) {
 // order 2: torder[b], the tiles of all views by decreasing list length (the
 // dispatcher hands workgroups to free slots in launch order, so the longest
 // tiles start first and the short ones fill the end: no straggler tail).
+// order 3 and 4 (persistent): a grid of about one round of resident
+// workgroups; each workgroup takes queue positions until the queue is empty:
+// position q is tile q (order 3) or torder[q] (order 4).  The queue is dealt
+// to the eight XCDs (workgroup b runs on XCD b mod 8): XCD x takes positions
+// x, x + 8, x + 16, ... through a counter of its own (cleared with the call's
+// status words), so that no single counter serialises every workgroup's
+// atomic and every XCD gets an equal share of long and short tiles.
 __device__ __forceinline__ int tile_of_block(int b, int T, int order, const uint32_t *torder) {
     if (order == 2) return (int)torder[b];
     if (order == 0) return b;
     const int x = b & 7, k = b >> 3;
     const int per = T >> 3, rem = T & 7;
     return x * per + min(x, rem) + k;
+}
+
+// Queue positions of a persistent workgroup (ticket: the eight XCD
+// counters).  Thread 0 asks for the next position when a tile starts, so the
+// atomic's round trip overlaps the tile's work: take_tile() issues the
+// request, next_tile() publishes its result to the workgroup.  The first
+// barrier keeps the previous tile's LDS in use until every thread has left
+// it; sq is read by all threads between the two barriers.
+struct TileQueue {
+    uint32_t *ctr;   // this XCD's counter
+    uint32_t x;      // this XCD
+    uint32_t pend;   // thread 0: the requested position's counter value
+    __device__ __forceinline__ void take_tile() {
+        if (threadIdx.x == 0) pend = atomicAdd(ctr, 1u);
+    }
+    __device__ __forceinline__ int next_tile(int &sq) {
+        __syncthreads();
+        if (threadIdx.x == 0) sq = (int)(pend * 8u + x);
+        __syncthreads();
+        return sq;
+    }
+};
+
+__device__ __forceinline__ TileQueue tile_queue(uint32_t *ticket) {
+    TileQueue tq;
+    tq.x = blockIdx.x & 7u;
+    tq.ctr = ticket + tq.x;
+    tq.pend = 0;
+    tq.take_tile();
+    return tq;
 }
 
 // ---------------------------------------------------------------- VF CONST raster (Alg. 2)
@@ -166,13 +203,10 @@ __device__ __forceinline__ int tile_of_block(int b, int T, int order, const uint
 // instead of a cross-lane reduction per Gaussian.
 // With RB = 64 the registers and LDS of a workgroup fit six per CU.
 template <int RB>
-__global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
-                                                   const uint2 *__restrict__ ranges,
-                                                   const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
-                                                   const Rec *__restrict__ rec,
-                                                   float eps_T, float qcut, float *__restrict__ acc_T,
-                                                   uint32_t *__restrict__ acc_c, int order,
-                                                   const uint32_t *__restrict__ torder) {
+__device__ __forceinline__ void vis_tile(const int gt, const ViewDev *__restrict__ views, int nv,
+                                         const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ival,
+                                         const uint32_t *__restrict__ ikey, const Rec *__restrict__ rec, float eps_T,
+                                         float qcut, float *__restrict__ acc_T, uint32_t *__restrict__ acc_c) {
     constexpr int LCAP = RB + LGROUP;
     __shared__ float4 wA[WAVES][LCAP];     // ux, uy, l11, l21 (tile-local centre)
     __shared__ float2 wB[WAVES][LCAP];     // l22, o
@@ -183,7 +217,6 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
     __shared__ uint32_t cpart[2 * RB];     // number of hit pixels
     __shared__ __align__(16) float scr[WAVES][LGROUP][SCR_STRIDE];
 
-    const int gt = tile_of_block(blockIdx.x, gridDim.x, order, torder);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -378,6 +411,33 @@ __global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewD
     if (blast != rg.y) flush(cur ^ 1, blast);
 }
 
+// PERSIST: the persistent schedules (orders 3 and 4), a kernel of its own so
+// that the one-tile form keeps its registers.
+template <int RB, bool PERSIST>
+__global__ __launch_bounds__(WG, RB == 64 ? 6 : 1) void k_raster_vis(const ViewDev *__restrict__ views, int nv,
+                                                   const uint2 *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ ival, const uint32_t *__restrict__ ikey,
+                                                   const Rec *__restrict__ rec,
+                                                   float eps_T, float qcut, float *__restrict__ acc_T,
+                                                   uint32_t *__restrict__ acc_c, int order,
+                                                   const uint32_t *__restrict__ torder, int ntiles,
+                                                   uint32_t *__restrict__ ticket) {
+    if constexpr (!PERSIST) {
+        vis_tile<RB>(tile_of_block(blockIdx.x, ntiles, order, torder), views, nv, ranges, ival, ikey, rec, eps_T,
+                     qcut, acc_T, acc_c);
+    } else {
+        __shared__ int sq;
+        TileQueue tq = tile_queue(ticket);
+        for (;;) {
+            const int q = tq.next_tile(sq);
+            if (q >= ntiles) break;
+            tq.take_tile();
+            vis_tile<RB>(order == 4 ? (int)torder[q] : q, views, nv, ranges, ival, ikey, rec, eps_T, qcut, acc_T,
+                         acc_c);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- VF QUERY raster (Alg. 6)
 
 // Lane -> pixel of the query blend: wave w covers quadrant w (8 x 8 pixels)
@@ -402,15 +462,14 @@ __device__ __forceinline__ void subblock_pixel(int t, int &qx, int &qy) {
 // DEPTH: also the expected depth of every pixel under the same weights,
 // sum w* z / sum w* (0 where nothing contributes), from the per-record depths
 // rz[], into dmaps (packed like maps); the same cost again.
+// Blends tile gt; returns the thread's composited pairs (COUNT).
 template <int RB, bool MAPS, bool COUNT, bool CC, bool DEPTH>
-__global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
-                                                  const uint2 *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ ival,
-                                                  const Rec *__restrict__ rec, const float *__restrict__ rcc,
-                                                  const float *__restrict__ rz,
-                                                  UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
-                                                  float *__restrict__ dmaps, unsigned long long *__restrict__ pairs,
-                                                  int order, const uint32_t *__restrict__ torder) {
+__device__ __forceinline__ uint32_t uq_tile(const int gt, const ViewDev *__restrict__ views, int nv,
+                                            const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ival,
+                                            const Rec *__restrict__ rec, const float *__restrict__ rcc,
+                                            const float *__restrict__ rz, const UqArgs &u,
+                                            float *__restrict__ tile_part, float *__restrict__ maps,
+                                            float *__restrict__ dmaps) {
     constexpr int NL = 4 * WAVES;          // sub-block lists per tile
     __shared__ float4 wA[RB + 1];          // ux, uy, l11, l21 per batch slot (slot RB: never hit)
     __shared__ float4 wB[RB + 1];          // l22, o (v + beta (1 - v)), o0 (1 - beta)(1 - v), v
@@ -420,7 +479,6 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
     __shared__ BatchCounts<NL> bc;         // per sub-block list: counts of the four waves
     __shared__ float red[WAVES];
 
-    const int gt = tile_of_block(blockIdx.x, gridDim.x, order, torder);
     const int vi = find_view(views, nv, gt);
     const ViewDev &V = views[vi];
     const int lt = gt - V.tile_base;
@@ -573,6 +631,34 @@ __global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ vi
 #pragma unroll
         for (int ww = 0; ww < WAVES; ++ww) tot += red[ww];
         tile_part[gt] = tot;
+    }
+    return npairs;
+}
+
+template <int RB, bool MAPS, bool COUNT, bool CC, bool DEPTH, bool PERSIST>
+__global__ __launch_bounds__(WG) void k_raster_uq(const ViewDev *__restrict__ views, int nv,
+                                                  const uint2 *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ ival,
+                                                  const Rec *__restrict__ rec, const float *__restrict__ rcc,
+                                                  const float *__restrict__ rz,
+                                                  UqArgs u, float *__restrict__ tile_part, float *__restrict__ maps,
+                                                  float *__restrict__ dmaps, unsigned long long *__restrict__ pairs,
+                                                  int order, const uint32_t *__restrict__ torder, int ntiles,
+                                                  uint32_t *__restrict__ ticket) {
+    uint32_t npairs = 0;
+    if constexpr (!PERSIST) {
+        npairs = uq_tile<RB, MAPS, COUNT, CC, DEPTH>(tile_of_block(blockIdx.x, ntiles, order, torder), views, nv,
+                                                     ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps);
+    } else {
+        __shared__ int sq;
+        TileQueue tq = tile_queue(ticket);
+        for (;;) {
+            const int q = tq.next_tile(sq);
+            if (q >= ntiles) break;
+            tq.take_tile();
+            npairs += uq_tile<RB, MAPS, COUNT, CC, DEPTH>(order == 4 ? (int)torder[q] : q, views, nv, ranges, ival,
+                                                          rec, rcc, rz, u, tile_part, maps, dmaps);
+        }
     }
     if (COUNT) block_count(npairs, pairs);
 }
@@ -930,19 +1016,37 @@ void launch_convert(const void *src, int sdt, void *dst, int ddt, uint64_t n, hi
 
 // ---------------------------------------------------------------- launchers
 
+// Grid of a blend: one workgroup per tile, or for the persistent orders (3,
+// 4) one round of resident workgroups at most (eight per CU; where fewer fit,
+// the rest start as the first ones finish, find the queue empty and exit).
+static unsigned blend_grid(int total_tiles, int order) {
+    if (order < 3) return (unsigned)total_tiles;
+    static const int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n = 256;
+        return n > 0 ? n : 256;
+    }();
+    return (unsigned)std::min<int64_t>(total_tiles, (int64_t)cus * 8);
+}
+
 template <int RB>
 static void raster_vis_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                           const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c,
-                          int order, const uint32_t *torder, hipStream_t s) {
-    hipLaunchKernelGGL(k_raster_vis<RB>, dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, ikey, rec, eps_T, qcut,
-                       acc_T, acc_c, order, torder);
+                          int order, const uint32_t *torder, uint32_t *ticket, hipStream_t s) {
+    if (order >= 3)
+        hipLaunchKernelGGL((k_raster_vis<RB, true>), dim3(blend_grid(total_tiles, order)), dim3(WG), 0, s, views, nv,
+                           ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, torder, total_tiles, ticket);
+    else
+        hipLaunchKernelGGL((k_raster_vis<RB, false>), dim3(total_tiles), dim3(WG), 0, s, views, nv, ranges, ival, ikey,
+                           rec, eps_T, qcut, acc_T, acc_c, order, torder, total_tiles, ticket);
 }
 
 void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                        const uint32_t *ikey, const Rec *rec, float eps_T, float qcut, float *acc_T, uint32_t *acc_c, int batch,
-                       int order, const uint32_t *torder, hipStream_t s) {
+                       int order, const uint32_t *torder, uint32_t *ticket, hipStream_t s) {
     if (total_tiles <= 0) return;
-#define GV_VIS_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, torder, s
+#define GV_VIS_ARGS views, nv, total_tiles, ranges, ival, ikey, rec, eps_T, qcut, acc_T, acc_c, order, torder, ticket, s
     switch (batch) {
     case 64: raster_vis_rb<64>(GV_VIS_ARGS); break;
     case 256: raster_vis_rb<256>(GV_VIS_ARGS); break;
@@ -951,27 +1055,27 @@ void launch_raster_vis(const ViewDev *views, int nv, int total_tiles, const uint
 #undef GV_VIS_ARGS
 }
 
-template <int RB, bool CC, bool DEPTH>
+template <int RB, bool CC, bool DEPTH, bool P>
 static void raster_uq_rb(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                          const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                          float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
-                         const uint32_t *torder, hipStream_t s) {
-    const dim3 g(total_tiles), b(WG);
-#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder
+                         const uint32_t *torder, uint32_t *ticket, hipStream_t s) {
+    const dim3 g(blend_grid(total_tiles, order)), b(WG);
+#define GV_UQ_ARGS views, nv, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, total_tiles, ticket
     if constexpr (DEPTH) {   // depth maps come with the entropy maps
         if (pairs)
-            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, true, P>), g, b, 0, s, GV_UQ_ARGS);
         else
-            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, true>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, true, P>), g, b, 0, s, GV_UQ_ARGS);
     } else {
         if (maps && pairs)
-            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, true, true, CC, false, P>), g, b, 0, s, GV_UQ_ARGS);
         else if (maps)
-            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, true, false, CC, false, P>), g, b, 0, s, GV_UQ_ARGS);
         else if (pairs)
-            hipLaunchKernelGGL((k_raster_uq<RB, false, true, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, false, true, CC, false, P>), g, b, 0, s, GV_UQ_ARGS);
         else
-            hipLaunchKernelGGL((k_raster_uq<RB, false, false, CC, false>), g, b, 0, s, GV_UQ_ARGS);
+            hipLaunchKernelGGL((k_raster_uq<RB, false, false, CC, false, P>), g, b, 0, s, GV_UQ_ARGS);
     }
 #undef GV_UQ_ARGS
 }
@@ -980,22 +1084,30 @@ template <int RB>
 static void raster_uq_var(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                           const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                           float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int order,
-                          const uint32_t *torder, hipStream_t s) {
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, s
+                          const uint32_t *torder, uint32_t *ticket, hipStream_t s) {
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, ticket, s
     const bool depth = dmaps && maps && rz;
-    if (rcc && depth) raster_uq_rb<RB, true, true>(GV_UQ_ARGS);
-    else if (rcc) raster_uq_rb<RB, true, false>(GV_UQ_ARGS);
-    else if (depth) raster_uq_rb<RB, false, true>(GV_UQ_ARGS);
-    else raster_uq_rb<RB, false, false>(GV_UQ_ARGS);
+    // the persistent schedules are built for the plain query; the colour and
+    // depth variants take the matching one-tile schedule (same tiles, same
+    // results)
+    if ((rcc || depth) && order >= 3) {
+        order = order == 4 ? 2 : 0;
+        ticket = nullptr;
+    }
+    if (rcc && depth) raster_uq_rb<RB, true, true, false>(GV_UQ_ARGS);
+    else if (rcc) raster_uq_rb<RB, true, false, false>(GV_UQ_ARGS);
+    else if (depth) raster_uq_rb<RB, false, true, false>(GV_UQ_ARGS);
+    else if (order >= 3) raster_uq_rb<RB, false, false, true>(GV_UQ_ARGS);
+    else raster_uq_rb<RB, false, false, false>(GV_UQ_ARGS);
 #undef GV_UQ_ARGS
 }
 
 void launch_raster_uq(const ViewDev *views, int nv, int total_tiles, const uint2 *ranges, const uint32_t *ival,
                       const Rec *rec, const float *rcc, const float *rz, const UqArgs &u,
                       float *tile_part, float *maps, float *dmaps, unsigned long long *pairs, int batch,
-                      int order, const uint32_t *torder, hipStream_t s) {
+                      int order, const uint32_t *torder, uint32_t *ticket, hipStream_t s) {
     if (total_tiles <= 0) return;
-#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, s
+#define GV_UQ_ARGS views, nv, total_tiles, ranges, ival, rec, rcc, rz, u, tile_part, maps, dmaps, pairs, order, torder, ticket, s
     switch (batch) {
     case 64: raster_uq_var<64>(GV_UQ_ARGS); break;
     case 256: raster_uq_var<256>(GV_UQ_ARGS); break;

@@ -24,8 +24,8 @@ class StubScene:
 
 
 def test_candidates_cover_both_axes():
-    assert {b for b, _ in CANDIDATES} == {64, 128, 256} and {o for _, o in CANDIDATES} == {0, 1, 2}
-    assert len(CANDIDATES) == 9
+    assert {b for b, _ in CANDIDATES} == {64, 128, 256} and {o for _, o in CANDIDATES} == {0, 1, 2, 3, 4}
+    assert len(CANDIDATES) == 15
 
 
 def test_cache_hit_applies_the_cached_choice(tmp_path):
