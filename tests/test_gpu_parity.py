@@ -730,6 +730,38 @@ def test_graph_replay_matches_eager(ctx, tiny, tiny_ref):
     assert torch.equal(s_g, s_e)
 
 
+def test_persistent_schedules_under_graph_replay(ctx, tiny, tiny_ref):
+    """The persistent blend schedules (orders 3 and 4: workgroups draining a
+    tile queue through counters that the call clears first) replayed from a
+    captured graph several times, with eager work between the replays: every
+    replay equals the eager call with the default one-tile schedule."""
+    say("case: persistent tile-queue schedules under graph replay")
+    import torch
+    from paper_2605_30342_amd import _lib
+    _, g32, _ = tiny_ref
+    dsc = _dsc(tiny.scene)
+    g = torch.from_numpy(np.ascontiguousarray(g32.T.astype(np.float32))).cuda()
+    prm_e = _lib.default_uq_params()
+    prm_g = _lib.default_uq_params(use_graph=1)
+    ws = ctx.query_workspace(dsc, tiny.cand, prm_e, 2)
+    t0 = ctx.get_tuning()
+    try:
+        s_ref, m_ref = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm_e, ws, want_maps=True)
+        s_ref, m_ref = s_ref.clone(), m_ref.clone()
+        for order in (3, 4):
+            ctx.set_tuning(t0["vis_batch"], t0["uq_batch"], t0["vis_order"], order)
+            for it in range(3):
+                s_g, m_g = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm_g, ws, want_maps=True)
+                s_g, m_g = s_g.clone(), m_g.clone()
+                junk = torch.randn(1 << 20, device="cuda").sum()          # unrelated eager work
+                torch.cuda.synchronize()
+                assert torch.equal(s_g, s_ref), (order, it)
+                assert torch.equal(m_g, m_ref), (order, it)
+                del junk
+    finally:
+        ctx.set_tuning(**t0)
+
+
 def test_graph_replay_follows_pixel_count_and_plan(ctx, tiny, tiny_ref):
     """Graph replays with expected-depth maps, alternating two camera sets of
     equal tile counts but different pixel counts (128x128 and 120x120, 8x8
