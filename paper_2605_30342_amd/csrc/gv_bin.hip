@@ -979,22 +979,35 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
 // reaches none of them is given the tile id past the last tile.
 //
 // A wave takes a chunk of 64 depth-ordered records and writes their instances
-// as one contiguous range in chunks of 64 outputs, lane j writing output
-// J + j.  The record owning an output is found without a search: records
-// starting inside the output chunk mark their first output in LDS, a ballot
-// over the marks gives every lane the number of records started up to its
-// output, and the compacted list of records that own tiles turns that count
-// into a lane.  Two kernels differ only in where a chunk's output offsets
-// come from: a scan of the records' tile counts done before (k_emit_scanned),
-// or the kernel's own single-pass scan (k_emit).
+// as one contiguous range, lane j writing output J + j, in two levels.  The
+// records' tile rows are taken 64 at a time: lane j computes row R0 + j's
+// band extents (the part of the quadrant test that depends on the row only,
+// done once per row instead of once per tile), its first output and its
+// first tile id, kept in LDS.  Then the outputs of those 64 rows are written
+// 64 at a time; each needs only its row's extents, its column and the
+// comparisons.  At both levels the owner of a row or an output is found
+// without a search: the owners starting inside the chunk mark their first
+// position in LDS, and a ballot over the marks gives every lane the number of
+// owners started up to its position (for rows, the compacted list of records
+// that own tiles turns that count into a lane).  Two kernels differ only in
+// where a chunk's output offsets come from: a scan of the records' tile
+// counts done before (k_emit_scanned), or the kernel's own single-pass scan
+// (k_emit).
 struct EmitLds {
-    uint2 sid[WAVES][64];       // record index, first output (relative to the chunk)
     float4 sgA[WAVES][64];      // band-test constants of each record: fx, fy, kx, 1 / a
     float4 sgB[WAVES][64];      // c, ey of the rightmost point, half height, anchor (bits)
     uint2 sgC[WAVES][64];       // first tile, rectangle dims
+    float4 rwE[WAVES][64];      // rows of the current 64: band extents (band_extents)
+    uint4 rwI[WAVES][64];       // rows: first output, first tile id, record index, anchor x (float bits)
     uint8_t cl[WAVES][64];      // lanes of the records that own at least one tile, in order
-    uint8_t mk[WAVES][64];      // 1 where a record starts at that output of the chunk
+    uint8_t mk[WAVES][64];      // 1 where a row / an output owner starts at that position
 };
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // This lane's record r (binning line B, nt tiles, first output rel after the
 // chunk's first output cbase); outputs at or past icap are not written.
@@ -1005,60 +1018,85 @@ __device__ __forceinline__ void emit_chunk(EmitLds &S, int w, int lane, uint32_t
     const bool owns = nt > 0;
     const unsigned long long own = __builtin_amdgcn_ballot_w64(owns);
     if (owns) S.cl[w][lanes_below(own)] = (uint8_t)lane;
-    S.sid[w][lane] = make_uint2(r, rel);
+    // the records' tile rows, numbered in record order
+    const uint32_t wy = owns ? bin_wy(B.dims) : 0u;
+    uint32_t rinc = wy;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(rinc, off);
+        if (lane >= off) rinc += y;
+    }
+    const uint32_t rrel = rinc - wy;
+    const uint32_t rtot = __shfl(rinc, 63);
     if (owns) {
         const EllipseBands E = ellipse_bands(B.l11, B.l21, B.l22, sq);
         S.sgA[w][lane] = make_float4(B.fx, B.fy, E.kx, E.ia);
         S.sgB[w][lane] = make_float4(B.l22, E.eyR, E.hy, __int_as_float(B.uvr));
         S.sgC[w][lane] = make_uint2(B.tile0, B.dims);
     }
-    // outputs of the chunk = end of the last record that owns tiles
-    uint32_t total = 0;
-    if (own) {
-        const int last = 63 - __builtin_clzll(own);
-        total = __shfl(rel + nt, last);
-    }
-    uint32_t started = 0;   // records (owning tiles) that start before the output chunk
-    for (uint32_t J = 0; J < total; J += 64) {
+    uint32_t rstarted = 0;   // records (owning tiles) whose rows start before the row chunk
+    for (uint32_t R0 = 0; R0 < rtot; R0 += 64) {
+        // row R0 + lane: its record, band extents, first output and first tile
         S.mk[w][lane] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (owns && rel >= J && rel < J + 64) S.mk[w][rel - J] = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const unsigned long long P = __builtin_amdgcn_ballot_w64(S.mk[w][lane] != 0);
-        const uint32_t upto = started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull);
-        const uint32_t jo = J + lane;
-        const unsigned long long o = cbase + jo;
-        if (jo < total && o < icap) {
-            const int q = S.cl[w][upto - 1];
-            const uint2 id = S.sid[w][q];
-            const uint2 C = S.sgC[w][q];
-            const uint32_t k = jo - id.y;
-            const uint32_t wx = bin_wx(C.y);
-            // k / wx in floating point (k < 2^24), corrected to the exact quotient
-            uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)wx));
-            int32_t rem = (int32_t)(k - ty * wx);
-            if (rem < 0) { --ty; rem += (int32_t)wx; }
-            else if (rem >= (int32_t)wx) { ++ty; rem -= (int32_t)wx; }
-            // quadrants of the tile the ellipse reaches; none: the instance is dead
+        wave_sync();
+        if (owns && rrel >= R0 && rrel < R0 + 64) S.mk[w][rrel - R0] = 1;
+        wave_sync();
+        const unsigned long long PR = __builtin_amdgcn_ballot_w64(S.mk[w][lane] != 0);
+        const uint32_t ri = R0 + lane;
+        const bool rv = ri < rtot;
+        // the row's record: its lane q; its index, first output and first row
+        // come from that lane's registers (every lane takes part in the shuffles)
+        const int q = rv ? (int)S.cl[w][rstarted + lanes_below(PR) + (uint32_t)((PR >> lane) & 1ull) - 1] : 0;
+        const uint32_t q_r = __shfl(r, q), q_rel = __shfl(rel, q), q_row = __shfl(rrel, q);
+        float4 ext = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint4 rinfo = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t rend = 0;   // first output past the row
+        if (rv) {
+            const uint32_t ty = ri - q_row;
             const float4 A = S.sgA[w][q], Bq = S.sgB[w][q];
+            const uint2 C = S.sgC[w][q];
+            const uint32_t wx = bin_wx(C.y);
             const int uvr = __float_as_int(Bq.w);
-            const float ux = (float)((int)(int16_t)(uvr & 0xFFFF) - rem * TILE) + A.x;
             const float uy = (float)((uvr >> 16) - (int)ty * TILE) + A.y;
-            const uint32_t qm = quadrant_mask_bands(ux, uy, A.z, A.w, Bq.x, Bq.y, Bq.z, qc);
-            const uint32_t tile = qm ? C.x + ty * bin_tiles_x(C.y) + (uint32_t)rem : dead_tile;
-            ikey[o] = tile | (qm << QMASK_SHIFT);
-            ival[o] = id.x;
+            ext = band_extents(uy, A.z, A.w, Bq.x, Bq.y, Bq.z, qc);
+            const uint32_t first = q_rel + ty * wx;
+            rinfo = make_uint4(first, C.x + ty * bin_tiles_x(C.y), q_r,
+                               __float_as_uint((float)(int)(int16_t)(uvr & 0xFFFF) + A.x));
+            rend = first + wx;
         }
-        started += (uint32_t)__popcll(P);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        rstarted += (uint32_t)__popcll(PR);
+        S.rwE[w][lane] = ext;
+        S.rwI[w][lane] = rinfo;
+        // the rows' outputs: [first output of row R0, end of the chunk's last row)
+        const uint32_t nr = min(rtot - R0, 64u);
+        const uint32_t o_first = __shfl(rinfo.x, 0);
+        const uint32_t o_end = __shfl(rend, (int)nr - 1);
+        uint32_t started = 0;   // rows of this chunk that start before the output chunk
+        for (uint32_t J = o_first; J < o_end; J += 64) {
+            wave_sync();
+            S.mk[w][lane] = 0;
+            wave_sync();
+            if (rv && rinfo.x >= J && rinfo.x < J + 64) S.mk[w][rinfo.x - J] = 1;
+            wave_sync();
+            const unsigned long long P = __builtin_amdgcn_ballot_w64(S.mk[w][lane] != 0);
+            const uint32_t jo = J + lane;
+            const unsigned long long o = cbase + jo;
+            if (jo < o_end && o < icap) {
+                const int row = (int)(started + lanes_below(P) + (uint32_t)((P >> lane) & 1ull)) - 1;
+                const uint4 I = S.rwI[w][row];
+                const float4 X = S.rwE[w][row];
+                const uint32_t rem = jo - I.x;
+                const float ux = __uint_as_float(I.w) - (float)(int)(rem * TILE);
+                const uint32_t qm = quadrant_mask_ext(ux, X);
+                const uint32_t tile = qm ? I.y + rem : dead_tile;
+                ikey[o] = tile | (qm << QMASK_SHIFT);
+                ival[o] = I.z;
+            }
+            started += (uint32_t)__popcll(P);
+        }
+        wave_sync();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
 }
 
 // Offsets from a scan done before (ioff[i]: first output of depth-ordered

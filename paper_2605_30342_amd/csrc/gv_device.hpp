@@ -224,10 +224,15 @@ __device__ __forceinline__ EllipseBands ellipse_bands(float a, float b, float c,
     return E;
 }
 
-__device__ __forceinline__ uint32_t quadrant_mask_bands(float ux, float uy, float kx, float ia, float c, float eyR,
-                                                     float hy, float qc) {
-    const float mg = fmaf(1e-5f, fabsf(ux), 0.01f);
-    uint32_t m = 0;
+// The quadrant test in two parts.  band_extents (once per tile row of a
+// record, from the centre's y offset uy in that row): per band j of eight
+// pixel rows, the ellipse's x-extent as offsets from the centre's x before
+// the margin, (a_j, b_j) = (xmax - ux, xmin - ux); a band no pixel row of
+// which meets the ellipse gets (-inf, +inf).  quadrant_mask_ext (per tile of
+// the row, from its ux): bit 2 j + i when the widened extent meets the pixel
+// centres of column block i (x from 8 i + 0.5 to 8 i + 7.5).
+__device__ __forceinline__ float4 band_extents(float uy, float kx, float ia, float c, float eyR, float hy, float qc) {
+    float e[4];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const float lo = fmaxf(uy - (8.0f * j + 7.5f), -hy), hi = fminf(uy - (8.0f * j + 0.5f), hy);
@@ -235,14 +240,22 @@ __device__ __forceinline__ uint32_t quadrant_mask_bands(float ux, float uy, floa
         const float tR = c * eR, tL = c * eL;
         const float sR = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tR, tR, qc), 0.0f));
         const float sL = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-tL, tL, qc), 0.0f));
-        const float xmax = fmaf(sR, ia, fmaf(kx, eR, ux)) + mg;
-        const float xmin = fmaf(-sL, ia, fmaf(kx, eL, ux)) - mg;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bool in = lo <= hi && xmax >= 8.0f * i + 0.5f && xmin <= 8.0f * i + 7.5f;
-            m |= in ? 1u << (2 * j + i) : 0u;
-        }
+        const bool valid = lo <= hi;
+        e[2 * j] = valid ? fmaf(sR, ia, kx * eR) : -__builtin_huge_valf();
+        e[2 * j + 1] = valid ? fmaf(-sL, ia, kx * eL) : __builtin_huge_valf();
     }
+    return make_float4(e[0], e[1], e[2], e[3]);
+}
+
+__device__ __forceinline__ uint32_t quadrant_mask_ext(float ux, const float4 &E) {
+    const float mg = fmaf(1e-5f, fabsf(ux), 0.01f);
+    const float xmax0 = (E.x + ux) + mg, xmin0 = (E.y + ux) - mg;
+    const float xmax1 = (E.z + ux) + mg, xmin1 = (E.w + ux) - mg;
+    uint32_t m = 0;
+    m |= (xmax0 >= 0.5f && xmin0 <= 7.5f) ? 1u : 0u;
+    m |= (xmax0 >= 8.5f && xmin0 <= 15.5f) ? 2u : 0u;
+    m |= (xmax1 >= 0.5f && xmin1 <= 7.5f) ? 4u : 0u;
+    m |= (xmax1 >= 8.5f && xmin1 <= 15.5f) ? 8u : 0u;
     return m;
 }
 
