@@ -622,8 +622,9 @@ def main():
         print(json.dumps({k: list(v) for k, v in doc["workloads"].items()}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the path shards by view across GPUs, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(across GPUs the query would be split by candidate view and the build's fields summed)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -24,8 +24,8 @@
  * EWA splatting used by 3D Gaussian Splatting (the paper builds on a modified
  * 3DGS rasteriser, Appendix on visibility-field construction).
  *
- * Readings where the paper is silent (kept identical on the GPU side, listed
- * in the design notes): alpha = o * exp(-m/2) with m the Mahalanobis distance
+ * Readings where the paper is silent (kept identical on the GPU side):
+ * alpha = o * exp(-m/2) with m the Mahalanobis distance
  * under the 2D covariance; "overlapping" means m <= cut (cut = 9, 3 sigma);
  * termination is T < eps_T tested after the update; depth is camera-space z,
  * and the depth order is decided on z rounded to FP32 (the kernels' sort-key
