@@ -872,8 +872,9 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
         run[t] = ex + hist[(size_t)t * gridDim.x + blockIdx.x];
         if (n_kept && blockIdx.x == 0 && t == RADIX - 1) *n_kept = ex + d;
     }
+    const uint64_t n = *n_dev;
     uint64_t start, end;
-    radix_chunk(*n_dev, start, end);
+    radix_chunk(n, start, end);
     const uint32_t mask = (1u << nbits) - 1u;
     for (uint64_t s = start; s < end; s += RTILE) {
         const uint64_t base = s + (uint64_t)w * RWAVE + lane;
@@ -947,12 +948,18 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t *__restrict
                 const uint32_t o = goff[(key >> shift) & mask] + j;
                 if (kout) kout[o] = key;
                 vout[o] = val;
+                // the gathered index is a value's record index, below n in a
+                // call that projected its records; a call whose records
+                // overflowed skips the projection and sorts the workspace's
+                // stale contents, so the index is checked before every read
+                // (the call then reports the overflow and emits nothing)
                 if (gbin) {   // packed values: the count they carry, or the binning line's
                     uint32_t c = val >> PACK_SHIFT;
-                    if (c == PACK_SAT) c = bin_ntiles(gbin[val & PACK_RMASK].dims);
+                    const uint32_t rr = val & PACK_RMASK;
+                    if (c == PACK_SAT) c = rr < n ? bin_ntiles(gbin[rr].dims) : 0u;
                     gdst[o] = c;
                 } else {
-                    gdst[o] = gsrc[val];
+                    gdst[o] = val < n ? gsrc[val] : 0u;
                 }
             }
         } else if (!kout) {

@@ -325,6 +325,51 @@ def test_capacity_overflow_is_reported(ctx, tiny, tiny_ref):
     assert torch.all(torch.isnan(s))
 
 
+@pytest.mark.parametrize("fill", [0x00, 0xFF])
+def test_record_overflow_over_stale_workspace_is_reported(ctx, tiny, tiny_ref, fill):
+    """Record capacity a third of what the call needs, in a workspace whose
+    bytes are all `fill` beforehand: the call skips the projection and sorts
+    the workspace's stale contents (with 0xFF every packed sort value claims a
+    saturated tile count and record 2^24 - 1).  Query and build both report
+    GV_ERR_CAPACITY (the query also NaN scores), neither reading outside its
+    workspace (every gathered record index is checked against the sorted
+    count); calls with large enough workspaces afterwards still match the
+    oracle."""
+    say(f"case: record overflow over a workspace filled with {fill:#04x}")
+    import ctypes
+    import torch
+    from paper_2605_30342_amd import _lib
+    b, g32, q = tiny_ref
+    dsc = _dsc(tiny.scene)
+    prm = _lib.default_uq_params()
+    full = ctx.query_workspace(dsc, tiny.cand, prm, 2)
+    plan = ctx.query_plan(dsc, tiny.cand, 2, max(1, full.plan.max_records // 3), full.plan.max_instances)
+    ws = ctx.alloc_workspace(plan)
+    ws.buf.fill_(fill)
+    g = torch.from_numpy(g32.T.astype(np.float32).copy()).cuda()
+    s, _ = ctx.vf_query_views(dsc, g, 2, tiny.train.n, tiny.cand, prm, ws)
+    st, counts = ctx.check_workspace(ws)
+    torch.cuda.synchronize()
+    assert st == _lib.GV_ERR_CAPACITY and (counts[2] & 1), (st, counts)
+    assert torch.all(torch.isnan(s))
+    vprm = _lib.default_vf_params(sh_degree=2)
+    bws = ctx.build_workspace(dsc, tiny.train, vprm)
+    bplan = bws.plan
+    bplan.max_records = max(1, bplan.max_records // 3)
+    bplan.bytes = ctx.L.gv_workspace_bytes(ctypes.byref(bplan))
+    small = ctx.alloc_workspace(bplan)
+    small.buf.fill_(fill)
+    ctx.vf_build(dsc, tiny.train, 2, params=vprm, ws=small)
+    st, counts = ctx.check_workspace(small)
+    torch.cuda.synchronize()
+    assert st == _lib.GV_ERR_CAPACITY and (counts[2] & 1), (st, counts)
+    worst, _ = compare_gamma(gpu_build(ctx, dsc, tiny.train, 2), b)
+    assert worst <= 1.0
+    s2, mp, _ = gpu_query(ctx, dsc, g32, 2, tiny.train.n, tiny.cand)
+    worst, flagged = compare_maps(mp, q)
+    assert worst <= 1.0 and flagged <= flag_bar(q["stats"])
+
+
 # ---------------------------------------------------------------- room scenes
 
 @pytest.fixture(scope="module")
